@@ -1,0 +1,238 @@
+"""CPU oracle for the speculative coloring rounds -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps ``oracle.c`` (plain C, built
+with gcc) through ctypes and shares no code with the device library.
+
+Graph arguments are duck-typed: a bipartite graph exposes
+``n_a, n_b, a_off, a_idx, b_off, b_idx``; a symmetric graph for distance-2
+coloring exposes ``n, off, idx``.  A caller ``order`` (order[k] = the vertex
+of rank k) is applied by relabelling vertices to their ranks, re-sorting every
+member list, running the natural-order oracle and mapping the colors back.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+OK, E_INVALID, E_NOT_CONVERGED, E_INTERNAL = 0, -1, -6, -8
+FIRST_FIT, B1, B2 = 0, 1, 2
+
+
+def build(verbose: bool = False) -> str:
+    """Compile oracle.c into liboracle.so next to it (gcc, OpenMP)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+           "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        lib.oracle_color.argtypes = [i32, i32, P, P, P, P, i32, u64, i32, i32, i32, i32,
+                                     P, P, i32, P, P, P, P, P]
+        lib.oracle_color.restype = ctypes.c_int
+        lib.oracle_seq_greedy.argtypes = [i32, i32, P, P, P, P, i32, P]
+        lib.oracle_seq_greedy.restype = ctypes.c_int
+        lib.oracle_count_violations.argtypes = [i32, i32, P, P, i32, P]
+        lib.oracle_count_violations.restype = ctypes.c_int64
+        lib.oracle_color_stats.argtypes = [P, i64, P, P]
+        lib.oracle_color_stats.restype = ctypes.c_int
+        lib.oracle_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _c32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+# ---------------------------------------------------------------------------
+# relabelling by rank (plain data movement)
+
+
+def _relabel_lists(n_rows, off, idx, inv_cols, row_order=None):
+    """Rows reordered by row_order (if given), entries mapped through inv_cols
+    and re-sorted within each row."""
+    off = np.asarray(off, dtype=np.int64)
+    idx = np.asarray(idx)
+    counts = np.diff(off)
+    if row_order is None:
+        row_order = np.arange(n_rows)
+    new_counts = counts[row_order]
+    new_off = np.zeros(n_rows + 1, dtype=np.int64)
+    np.cumsum(new_counts, out=new_off[1:])
+    new_rows = np.repeat(np.arange(n_rows, dtype=np.int64), new_counts)
+    src_pos = np.concatenate([np.arange(off[r], off[r + 1]) for r in row_order]) if n_rows else np.zeros(0, np.int64)
+    vals = inv_cols[idx[src_pos]] if idx.size else np.zeros(0, np.int64)
+    key = np.lexsort((vals, new_rows))
+    return new_off, _c32(vals[key])
+
+
+def _inverse(order, n):
+    order = np.asarray(order, dtype=np.int64)
+    if order.shape != (n,) or not np.array_equal(np.sort(order), np.arange(n)):
+        raise ValueError("order must be a permutation of the colored vertices")
+    inv = np.empty(n, dtype=np.int64)
+    inv[order] = np.arange(n)
+    return order, inv
+
+
+# ---------------------------------------------------------------------------
+# the rounds
+
+
+class Result:
+    def __init__(self, status, colors, rounds, log):
+        self.status = status
+        self.colors = colors
+        self.rounds = rounds
+        self.log = log
+
+    def __repr__(self):
+        return f"Result(status={self.status}, rounds={self.rounds})"
+
+
+def _run(n_a, n_b, a_off, a_idx, b_off, b_idx, d2, net_color_mask, policy, chunk,
+         max_rounds, start_round, init_colors, log_cap):
+    lib = _load()
+    a_off, b_off = _c64(a_off), _c64(b_off)
+    a_idx, b_idx = _c32(a_idx), _c32(b_idx)
+    colors = np.full(n_a, -1, dtype=np.int32) if init_colors is None else _c32(init_colors).copy()
+    rounds = np.zeros(1, dtype=np.int32)
+    lm = np.zeros(log_cap, dtype=np.int32)
+    lw = np.zeros(log_cap, dtype=np.int64)
+    ll = np.zeros(log_cap, dtype=np.int64)
+    le = np.zeros(log_cap, dtype=np.int64)
+    lc = np.zeros(log_cap, dtype=np.int32)
+    st = lib.oracle_color(n_a, n_b, _ptr(a_off), _ptr(a_idx), _ptr(b_off), _ptr(b_idx),
+                          int(d2), ctypes.c_uint64(net_color_mask & (2 ** 64 - 1)), int(policy), int(chunk),
+                          int(max_rounds), int(start_round), _ptr(colors), _ptr(rounds),
+                          log_cap, _ptr(lm), _ptr(lw), _ptr(ll), _ptr(le), _ptr(lc))
+    r = int(rounds[0])
+    k = min(r, log_cap)
+    log = {"mode": lm[:k].copy(), "w": lw[:k].copy(), "losers": ll[:k].copy(),
+           "evicted": le[:k].copy(), "max_color": lc[:k].copy()}
+    return int(st), colors, r, log
+
+
+def bgpc(g, net_color_mask: int = 0, policy: int = FIRST_FIT, chunk: int = 64,
+         max_rounds: int = 0, order=None, init_colors=None, start_round: int = 0,
+         log_cap: int = 4096) -> Result:
+    """Bipartite-graph partial coloring of V_A (Sections II-III, V)."""
+    n_a, n_b = int(g.n_a), int(g.n_b)
+    a_off, a_idx, b_off, b_idx = g.a_off, g.a_idx, g.b_off, g.b_idx
+    inv = None
+    if order is not None:
+        order, inv = _inverse(order, n_a)
+        b_off, b_idx = _relabel_lists(n_b, b_off, b_idx, inv)
+        a_off, a_idx = _relabel_lists(n_a, a_off, a_idx, np.arange(n_b, dtype=np.int64), row_order=order)
+        if init_colors is not None:
+            init_colors = np.asarray(init_colors)[order]
+    st, colors, r, log = _run(n_a, n_b, a_off, a_idx, b_off, b_idx, 0, net_color_mask, policy, chunk,
+                              max_rounds, start_round, init_colors, log_cap)
+    if inv is not None:
+        colors = colors[inv]
+    return Result(st, colors, r, log)
+
+
+def d2gc(adj, net_color_mask: int = 0, policy: int = FIRST_FIT, chunk: int = 64,
+         max_rounds: int = 0, order=None, init_colors=None, start_round: int = 0,
+         log_cap: int = 4096) -> Result:
+    """Distance-2 coloring of a symmetric graph without self loops (Section IV)."""
+    n = int(adj.n)
+    off, idx = adj.off, adj.idx
+    inv = None
+    if order is not None:
+        order, inv = _inverse(order, n)
+        off, idx = _relabel_lists(n, off, idx, inv, row_order=order)
+        if init_colors is not None:
+            init_colors = np.asarray(init_colors)[order]
+    st, colors, r, log = _run(n, n, off, idx, off, idx, 1, net_color_mask, policy, chunk,
+                              max_rounds, start_round, init_colors, log_cap)
+    if inv is not None:
+        colors = colors[inv]
+    return Result(st, colors, r, log)
+
+
+def seq_greedy(g, order=None) -> np.ndarray:
+    """Sequential first-fit in rank order (bipartite graph)."""
+    lib = _load()
+    n_a, n_b = int(g.n_a), int(g.n_b)
+    a_off, a_idx, b_off, b_idx = g.a_off, g.a_idx, g.b_off, g.b_idx
+    inv = None
+    if order is not None:
+        order, inv = _inverse(order, n_a)
+        b_off, b_idx = _relabel_lists(n_b, b_off, b_idx, inv)
+        a_off, a_idx = _relabel_lists(n_a, a_off, a_idx, np.arange(n_b, dtype=np.int64), row_order=order)
+    a_off, b_off, a_idx, b_idx = _c64(a_off), _c64(b_off), _c32(a_idx), _c32(b_idx)
+    out = np.empty(n_a, dtype=np.int32)
+    st = lib.oracle_seq_greedy(n_a, n_b, _ptr(a_off), _ptr(a_idx), _ptr(b_off), _ptr(b_idx), 0, _ptr(out))
+    if st:
+        raise RuntimeError(f"oracle_seq_greedy failed: {st}")
+    return out[inv] if inv is not None else out
+
+
+def seq_greedy_d2(adj) -> np.ndarray:
+    lib = _load()
+    n = int(adj.n)
+    off, idx = _c64(adj.off), _c32(adj.idx)
+    out = np.empty(n, dtype=np.int32)
+    st = lib.oracle_seq_greedy(n, n, _ptr(off), _ptr(idx), _ptr(off), _ptr(idx), 1, _ptr(out))
+    if st:
+        raise RuntimeError(f"oracle_seq_greedy failed: {st}")
+    return out
+
+
+def violations(g, colors) -> int:
+    """Shared-net color repeats plus uncolored vertices (0 = valid coloring)."""
+    lib = _load()
+    colors = _c32(colors)
+    if hasattr(g, "n_b"):
+        b_off, b_idx = _c64(g.b_off), _c32(g.b_idx)
+        return int(lib.oracle_count_violations(int(g.n_a), int(g.n_b), _ptr(b_off), _ptr(b_idx), 0, _ptr(colors)))
+    off, idx = _c64(g.off), _c32(g.idx)
+    return int(lib.oracle_count_violations(int(g.n), int(g.n), _ptr(off), _ptr(idx), 1, _ptr(colors)))
+
+
+def color_stats(colors) -> dict:
+    """Non-empty color sets and their cardinalities (the balancing metrics)."""
+    lib = _load()
+    colors = _c32(colors)
+    oi = np.zeros(5, dtype=np.int64)
+    od = np.zeros(2, dtype=np.float64)
+    st = lib.oracle_color_stats(_ptr(colors), colors.shape[0], _ptr(oi), _ptr(od))
+    if st:
+        raise RuntimeError("oracle_color_stats failed")
+    return {"n_distinct": int(oi[0]), "max_color": int(oi[1]), "card_min": int(oi[2]),
+            "card_max": int(oi[3]), "n_empty_below_max": int(oi[4]),
+            "card_mean": float(od[0]), "card_std": float(od[1])}

@@ -1,0 +1,528 @@
+/*
+ * oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow CPU statement of the speculative greedy coloring of
+ * Tas, Kaya and Saule, "Greed is Good: Optimistic Algorithms for
+ * Bipartite-Graph Partial Coloring on Multicore Architectures" (2017),
+ * run with fixed round semantics so that every round has one exact result.
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load this file; the coloring library never links, calls or includes it,
+ * and it shares no code, header or table with the device implementation.
+ *
+ * Problem (Section II): color the V_A side of a bipartite graph so that any
+ * two vertices sharing a V_B net differ; colors are non-negative, -1 marks an
+ * uncolored vertex.  nets(u) lists the nets of vertex u, vtxs(v) the vertices
+ * of net v.  For distance-2 coloring (Section IV) the nets are the closed
+ * neighbourhoods N[v] = {v} u nbor(v) of a symmetric graph.
+ *
+ * Round semantics fixed here where the paper's threads race:
+ *   - every round reads a snapshot s of the previous round's colors and
+ *     writes a tentative array t (Algorithm 1's loop run Jacobi-style);
+ *   - removal is global: u loses iff some x sharing a net with u has
+ *     t[x] == t[u] and a lower rank (the rule of Algorithm 3); a loser is
+ *     reset to -1 (as Algorithms 7 and 10 do);
+ *   - a net-based round (Algorithm 8 / 9) writes vertex x only from its
+ *     owner net: the largest net containing x, ties to the lowest net id;
+ *   - the balancing state of Algorithms 11 and 12 lives per chunk of `chunk`
+ *     consecutive worklist entries and restarts every round.
+ * Ranks are vertex ids; a caller-supplied order is applied by relabelling the
+ * graph before the call (oracle/__init__.py).
+ *
+ * Every parallel loop below runs items that do not read each other's output
+ * within the round, so the OpenMP schedule cannot change any result.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+#include <omp.h>
+
+enum { OR_OK = 0, OR_E_INVALID = -1, OR_E_NOT_CONVERGED = -6, OR_E_INTERNAL = -8 };
+enum { POL_FF = 0, POL_B1 = 1, POL_B2 = 2 };
+
+typedef struct {
+    int32_t n_a, n_b, d2;
+    const int64_t *a_off; const int32_t *a_idx;   /* nets(u)  (d2: nbor(u)) */
+    const int64_t *b_off; const int32_t *b_idx;   /* vtxs(v)  (d2: nbor(v)) */
+} graph_t;
+
+/* nets(u); in distance-2 mode N[u] = {u} followed by nbor(u) */
+static int64_t nets_count(const graph_t *g, int32_t u)
+{
+    int64_t k = g->a_off[u + 1] - g->a_off[u];
+    return g->d2 ? k + 1 : k;
+}
+static int32_t net_at(const graph_t *g, int32_t u, int64_t k)
+{
+    if (g->d2) {
+        if (k == 0) return u;
+        k -= 1;
+    }
+    return g->a_idx[g->a_off[u] + k];
+}
+/* vtxs(v); in distance-2 mode the center v comes first (Algorithm 9), then nbor(v) */
+static int64_t vtxs_count(const graph_t *g, int32_t v)
+{
+    int64_t k = g->b_off[v + 1] - g->b_off[v];
+    return g->d2 ? k + 1 : k;
+}
+static int32_t vtx_at(const graph_t *g, int32_t v, int64_t k)
+{
+    if (g->d2) {
+        if (k == 0) return v;
+        k -= 1;
+    }
+    return g->b_idx[g->b_off[v] + k];
+}
+
+/* A forbidden-color set F kept as a marker array that is never cleared:
+ * color col is in F iff mark[col] == cur (the marker trick of the paper's
+ * implementation notes at the end of Section III). */
+typedef struct {
+    int64_t *mark;
+    int32_t *holder;
+    int64_t cap;
+    int64_t cur;
+} fset_t;
+
+static int fset_init(fset_t *f, int64_t cap)
+{
+    f->cap = cap;
+    f->cur = 0;
+    f->mark = (int64_t *)calloc((size_t)cap, sizeof(int64_t));
+    f->holder = (int32_t *)calloc((size_t)cap, sizeof(int32_t));
+    return (f->mark && f->holder) ? 0 : -1;
+}
+static void fset_free(fset_t *f)
+{
+    free(f->mark);
+    free(f->holder);
+}
+static void fset_clear(fset_t *f) { f->cur++; }
+static int fset_has(const fset_t *f, int64_t col)
+{
+    return col >= 0 && col < f->cap && f->mark[col] == f->cur;
+}
+static void fset_add(fset_t *f, int64_t col) { f->mark[col] = f->cur; }
+
+typedef struct { int64_t col_max, col_next; } chunk_state_t;
+
+/* The color policies.  First-fit: Algorithm 2's closing search.
+ * B1: Algorithm 11.  B2: Algorithm 12 (col_max / 3 is an integer floor). */
+static int64_t policy_pick(int policy, const fset_t *F, chunk_state_t *st, int32_t rank)
+{
+    int64_t col;
+    if (policy == POL_B1) {
+        if (rank % 2 == 0) {
+            col = st->col_max;
+            while (col >= 0 && fset_has(F, col)) col--;
+            if (col == -1) {
+                col = st->col_max + 1;
+                while (fset_has(F, col)) col++;
+            }
+        } else {
+            col = 0;
+            while (fset_has(F, col)) col++;
+        }
+        if (col > st->col_max) st->col_max = col;
+    } else if (policy == POL_B2) {
+        col = st->col_next;
+        while (fset_has(F, col)) col++;
+        if (col > st->col_max) {
+            col = 0;
+            while (fset_has(F, col)) col++;
+        }
+        if (col > st->col_max) st->col_max = col;
+        int64_t cap = st->col_max / 3 + 1;
+        st->col_next = (col + 1 < cap) ? col + 1 : cap;
+    } else {
+        col = 0;
+        while (fset_has(F, col)) col++;
+    }
+    return col;
+}
+
+/* owner(u): the net of u with the most vertices, ties to the lowest net id. */
+static void compute_owner(const graph_t *g, int32_t *owner)
+{
+    #pragma omp parallel for schedule(dynamic, 1024)
+    for (int32_t u = 0; u < g->n_a; u++) {
+        int32_t best = -1;
+        int64_t best_size = -1;
+        int64_t k = nets_count(g, u);
+        for (int64_t j = 0; j < k; j++) {
+            int32_t v = net_at(g, u, j);
+            int64_t sz = vtxs_count(g, v);
+            if (sz > best_size || (sz == best_size && v < best)) {
+                best = v;
+                best_size = sz;
+            }
+        }
+        owner[u] = best;
+    }
+}
+
+static int64_t max_net_size(const graph_t *g)
+{
+    int64_t m = 0;
+    for (int32_t v = 0; v < g->n_b; v++) {
+        int64_t k = vtxs_count(g, v);
+        if (k > m) m = k;
+    }
+    return m;
+}
+
+/*
+ * Vertex-based coloring of the worklist (Algorithm 4 gathering F, Algorithm 2
+ * first-fit or Algorithms 11 / 12 choosing the color).  F(w) is every color
+ * found in the snapshot among the vertices sharing a net with w.
+ */
+static int color_vertex_round(const graph_t *g, const int32_t *s, int32_t *t,
+                              const int32_t *W, int64_t nw, int policy, int32_t chunk,
+                              int64_t color_cap)
+{
+    int err = 0;
+    int64_t nchunks = (nw + chunk - 1) / chunk;
+    #pragma omp parallel reduction(| : err)
+    {
+        fset_t F;
+        if (fset_init(&F, color_cap)) {
+            err |= 1;
+        } else {
+            #pragma omp for schedule(dynamic, 1)
+            for (int64_t ch = 0; ch < nchunks; ch++) {
+                chunk_state_t st = {0, 0};
+                int64_t lo = ch * chunk, hi = lo + chunk < nw ? lo + chunk : nw;
+                for (int64_t i = lo; i < hi; i++) {
+                    int32_t w = W[i];
+                    fset_clear(&F);
+                    int64_t kn = nets_count(g, w);
+                    for (int64_t a = 0; a < kn; a++) {
+                        int32_t v = net_at(g, w, a);
+                        int64_t kv = vtxs_count(g, v);
+                        for (int64_t b = 0; b < kv; b++) {
+                            int32_t x = vtx_at(g, v, b);
+                            if (x != w && s[x] != -1) fset_add(&F, s[x]);
+                        }
+                    }
+                    int64_t col = policy_pick(policy, &F, &st, w);
+                    if (col + 1 >= color_cap) err |= 2;
+                    t[w] = (int32_t)col;
+                }
+            }
+            fset_free(&F);
+        }
+    }
+    return err ? OR_E_INTERNAL : OR_OK;
+}
+
+/*
+ * Net-based coloring (Algorithm 8; Algorithm 9 in distance-2 mode): every net
+ * with an uncolored member gathers the colors of its colored members into F,
+ * queues the rest, and hands out colors from the top of [0, |vtxs(v)|)
+ * downwards, skipping F (reverse first-fit).  Only the owner net's proposal is
+ * written.  Worklist vertices without any net take the policy's color for an
+ * empty F.
+ */
+static int color_net_round(const graph_t *g, const int32_t *s, int32_t *t,
+                           const int32_t *owner, const int32_t *W, int64_t nw,
+                           int policy, int64_t color_cap, int64_t max_size)
+{
+    int err = 0;
+    #pragma omp parallel reduction(| : err)
+    {
+        fset_t F;
+        int32_t *L = (int32_t *)malloc((size_t)(max_size + 1) * sizeof(int32_t));
+        if (fset_init(&F, color_cap) || !L) {
+            err |= 1;
+        } else {
+            #pragma omp for schedule(dynamic, 256)
+            for (int32_t v = 0; v < g->n_b; v++) {
+                int64_t kv = vtxs_count(g, v);
+                int any_uncolored = 0;
+                for (int64_t b = 0; b < kv; b++)
+                    if (s[vtx_at(g, v, b)] == -1) any_uncolored = 1;
+                if (!any_uncolored) continue;
+                fset_clear(&F);
+                int64_t nl = 0;
+                for (int64_t b = 0; b < kv; b++) {
+                    int32_t x = vtx_at(g, v, b);
+                    if (s[x] != -1 && !fset_has(&F, s[x])) {
+                        fset_add(&F, s[x]);
+                    } else {
+                        /* a colored x whose color is already in F would mean two
+                         * colored members of one net share a color, which the
+                         * removal step never leaves behind */
+                        if (s[x] != -1) err |= 4;
+                        L[nl++] = x;
+                    }
+                }
+                int64_t col = kv - 1;   /* |vtxs(v)| - 1; distance-2: |nbor(v)| */
+                for (int64_t i = 0; i < nl; i++) {
+                    while (col >= 0 && fset_has(&F, col)) col--;
+                    if (col < 0) err |= 8;
+                    if (owner[L[i]] == v) t[L[i]] = (int32_t)col;
+                    col--;
+                }
+            }
+            #pragma omp for schedule(static)
+            for (int64_t i = 0; i < nw; i++) {
+                int32_t w = W[i];
+                if (owner[w] == -1) {
+                    const fset_t empty = {NULL, NULL, 0, 0};
+                    chunk_state_t st = {0, 0};
+                    t[w] = (int32_t)policy_pick(policy, &empty, &st, w);
+                }
+            }
+            fset_free(&F);
+        }
+        free(L);
+    }
+    return err ? OR_E_INTERNAL : OR_OK;
+}
+
+/*
+ * Removal: u loses iff t[u] != -1 and a vertex x sharing a net with u has
+ * t[x] == t[u] and x < u (the lower rank keeps its color, Algorithm 3's
+ * rule, applied to every colored vertex).  Per net, the lowest-ranked holder
+ * of each color is found first; every other holder of that color loses.
+ */
+static int remove_conflicts(const graph_t *g, const int32_t *t, uint8_t *lose, int64_t color_cap)
+{
+    int err = 0;
+    memset(lose, 0, (size_t)g->n_a);
+    #pragma omp parallel reduction(| : err)
+    {
+        fset_t F;
+        if (fset_init(&F, color_cap)) {
+            err |= 1;
+        } else {
+            #pragma omp for schedule(dynamic, 256)
+            for (int32_t v = 0; v < g->n_b; v++) {
+                int64_t kv = vtxs_count(g, v);
+                fset_clear(&F);
+                for (int64_t b = 0; b < kv; b++) {
+                    int32_t x = vtx_at(g, v, b);
+                    int32_t col = t[x];
+                    if (col == -1) continue;
+                    if (!fset_has(&F, col) || x < F.holder[col]) {
+                        fset_add(&F, col);
+                        F.holder[col] = x;
+                    }
+                }
+                for (int64_t b = 0; b < kv; b++) {
+                    int32_t x = vtx_at(g, v, b);
+                    int32_t col = t[x];
+                    if (col != -1 && F.holder[col] != x) {
+                        #pragma omp atomic write
+                        lose[x] = 1;
+                    }
+                }
+            }
+            fset_free(&F);
+        }
+    }
+    return err ? OR_E_INTERNAL : OR_OK;
+}
+
+/*
+ * The speculative loop of Algorithm 1 on V_color = V_A.
+ *   colors     in: starting coloring (all -1, or a conflict-free partial one
+ *              to resume from); out: the coloring reached.
+ *   start_round  index of the first round (selects the net_color_mask bit).
+ *   max_rounds   rounds to run at most (0: n_a + 65); status -6 when the
+ *              worklist is still non-empty after them.
+ *   log_*      optional per-round records (mode, |W_r|, losers, evicted
+ *              colored vertices, max color after the round), log_cap entries.
+ */
+int oracle_color(int32_t n_a, int32_t n_b,
+                 const int64_t *a_off, const int32_t *a_idx,
+                 const int64_t *b_off, const int32_t *b_idx,
+                 int32_t d2, uint64_t net_color_mask, int32_t policy, int32_t chunk,
+                 int32_t max_rounds, int32_t start_round,
+                 int32_t *colors, int32_t *rounds_out,
+                 int32_t log_cap, int32_t *log_mode, int64_t *log_w, int64_t *log_losers,
+                 int64_t *log_evicted, int32_t *log_maxc)
+{
+    if (n_a < 0 || n_b < 0 || chunk <= 0 || policy < 0 || policy > 2) return OR_E_INVALID;
+    if (d2 && n_a != n_b) return OR_E_INVALID;
+    graph_t g = {n_a, n_b, d2, a_off, a_idx, b_off, b_idx};
+    if (max_rounds <= 0) max_rounds = n_a + 65;
+
+    int32_t *s = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_a + 1));
+    int32_t *t = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_a + 1));
+    int32_t *W = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_a + 1));
+    int32_t *owner = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_a + 1));
+    uint8_t *lose = (uint8_t *)malloc((size_t)(n_a + 1));
+    int status = OR_OK;
+    if (!s || !t || !W || !owner || !lose) { status = OR_E_INTERNAL; goto done; }
+
+    compute_owner(&g, owner);
+    int64_t max_size = max_net_size(&g);
+    int32_t r = 0;
+    for (;;) {
+        /* snapshot and worklist of the uncolored vertices, ascending rank */
+        memcpy(s, colors, sizeof(int32_t) * (size_t)n_a);
+        int64_t nw = 0, maxc = -1;
+        for (int32_t u = 0; u < n_a; u++) {
+            if (s[u] == -1) W[nw++] = u;
+            else if (s[u] > maxc) maxc = s[u];
+        }
+        if (nw == 0) break;
+        if (r >= max_rounds) { status = OR_E_NOT_CONVERGED; break; }
+        int32_t round_id = start_round + r;
+        int net_mode = round_id < 64 && ((net_color_mask >> round_id) & 1u);
+        /* every color a round can produce stays below this bound */
+        int64_t cap = maxc + 2 + (int64_t)chunk + 2;
+        if (max_size + 2 > cap) cap = max_size + 2;
+
+        memcpy(t, s, sizeof(int32_t) * (size_t)n_a);
+        int e = net_mode ? color_net_round(&g, s, t, owner, W, nw, policy, cap, max_size)
+                         : color_vertex_round(&g, s, t, W, nw, policy, chunk, cap);
+        if (e) { status = e; break; }
+        int64_t tmax = -1;
+        for (int32_t u = 0; u < n_a; u++)
+            if (t[u] > tmax) tmax = t[u];
+        if (tmax + 2 > cap) cap = tmax + 2;
+        e = remove_conflicts(&g, t, lose, cap);
+        if (e) { status = e; break; }
+        int64_t losers = 0, evicted = 0, nmax = -1;
+        for (int32_t u = 0; u < n_a; u++) {
+            if (lose[u]) {
+                losers++;
+                if (s[u] != -1) evicted++;
+                colors[u] = -1;
+            } else {
+                colors[u] = t[u];
+                if (t[u] > nmax) nmax = t[u];
+            }
+        }
+        if (r < log_cap) {
+            if (log_mode) log_mode[r] = net_mode;
+            if (log_w) log_w[r] = nw;
+            if (log_losers) log_losers[r] = losers;
+            if (log_evicted) log_evicted[r] = evicted;
+            if (log_maxc) log_maxc[r] = (int32_t)nmax;
+        }
+        r++;
+    }
+    if (rounds_out) *rounds_out = r;
+done:
+    free(s); free(t); free(W); free(owner); free(lose);
+    return status;
+}
+
+/*
+ * Sequential greedy coloring: vertices in rank order, each taking the
+ * smallest color not used by an already colored vertex sharing a net with it
+ * (the sequential V-V of the experiments, which needs no conflict phase).
+ */
+int oracle_seq_greedy(int32_t n_a, int32_t n_b,
+                      const int64_t *a_off, const int32_t *a_idx,
+                      const int64_t *b_off, const int32_t *b_idx,
+                      int32_t d2, int32_t *colors)
+{
+    graph_t g = {n_a, n_b, d2, a_off, a_idx, b_off, b_idx};
+    fset_t F;
+    if (fset_init(&F, (int64_t)n_a + 2)) return OR_E_INTERNAL;
+    for (int32_t u = 0; u < n_a; u++) colors[u] = -1;
+    for (int32_t u = 0; u < n_a; u++) {
+        fset_clear(&F);
+        int64_t kn = nets_count(&g, u);
+        for (int64_t a = 0; a < kn; a++) {
+            int32_t v = net_at(&g, u, a);
+            int64_t kv = vtxs_count(&g, v);
+            for (int64_t b = 0; b < kv; b++) {
+                int32_t x = vtx_at(&g, v, b);
+                if (x != u && colors[x] != -1) fset_add(&F, colors[x]);
+            }
+        }
+        int64_t col = 0;
+        while (fset_has(&F, col)) col++;
+        colors[u] = (int32_t)col;
+    }
+    fset_free(&F);
+    return OR_OK;
+}
+
+/* Number of (net, pair) violations: two members of one net with one color, or
+ * a member left uncolored (counted once per member). */
+int64_t oracle_count_violations(int32_t n_a, int32_t n_b,
+                                const int64_t *b_off, const int32_t *b_idx,
+                                int32_t d2, const int32_t *colors)
+{
+    graph_t g = {n_a, n_b, d2, NULL, NULL, b_off, b_idx};
+    int64_t bad = 0;
+    int64_t cap = 2;
+    for (int32_t u = 0; u < n_a; u++) {
+        if (colors[u] < 0) bad++;
+        else if (colors[u] + 2 > cap) cap = colors[u] + 2;
+    }
+    #pragma omp parallel reduction(+ : bad)
+    {
+        fset_t F;
+        if (fset_init(&F, cap) == 0) {
+            #pragma omp for schedule(dynamic, 256)
+            for (int32_t v = 0; v < n_b; v++) {
+                fset_clear(&F);
+                int64_t kv = vtxs_count(&g, v);
+                for (int64_t b = 0; b < kv; b++) {
+                    int32_t col = colors[vtx_at(&g, v, b)];
+                    if (col < 0) continue;
+                    if (fset_has(&F, col)) bad++;
+                    else fset_add(&F, col);
+                }
+            }
+            fset_free(&F);
+        } else {
+            bad += 1;
+        }
+    }
+    return bad;
+}
+
+/*
+ * Color-set statistics (the quantities of the balancing experiments): the
+ * number of non-empty color sets, the largest color, the min / max / mean /
+ * population standard deviation of the non-empty set cardinalities, and the
+ * number of empty sets below the largest color.  Uncolored entries are
+ * ignored.
+ */
+int oracle_color_stats(const int32_t *colors, int64_t n, int64_t *out_i, double *out_d)
+{
+    int64_t maxc = -1;
+    for (int64_t i = 0; i < n; i++)
+        if (colors[i] > maxc) maxc = colors[i];
+    int64_t *card = (int64_t *)calloc((size_t)(maxc + 2), sizeof(int64_t));
+    if (!card) return OR_E_INTERNAL;
+    for (int64_t i = 0; i < n; i++)
+        if (colors[i] >= 0) card[colors[i]]++;
+    int64_t ndist = 0, cmin = 0, cmax = 0, total = 0;
+    for (int64_t c = 0; c <= maxc; c++) {
+        if (card[c] == 0) continue;
+        if (ndist == 0 || card[c] < cmin) cmin = card[c];
+        if (card[c] > cmax) cmax = card[c];
+        ndist++;
+        total += card[c];
+    }
+    double mean = ndist ? (double)total / (double)ndist : 0.0;
+    double var = 0.0;
+    for (int64_t c = 0; c <= maxc; c++) {
+        if (card[c] == 0) continue;
+        double d = (double)card[c] - mean;
+        var += d * d;
+    }
+    var = ndist ? var / (double)ndist : 0.0;
+    double sd = sqrt(var);
+    out_i[0] = ndist;
+    out_i[1] = maxc;
+    out_i[2] = cmin;
+    out_i[3] = cmax;
+    out_i[4] = (maxc + 1) - ndist;
+    out_d[0] = mean;
+    out_d[1] = sd;
+    free(card);
+    return OR_OK;
+}
+
+int oracle_num_threads(void) { return omp_get_max_threads(); }

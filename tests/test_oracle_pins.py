@@ -1,0 +1,326 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Hand-derived round-by-round states (tests/golden/worked_examples.json),
+closed forms, independent checks written with numpy / scipy (validity,
+bounds, the first round's survivors), brute force on tiny graphs, and
+reductions to sequential greedy coloring.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from paper_1701_02628_amd import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _cases():
+    with open(os.path.join(HERE, "golden", "worked_examples.json")) as f:
+        return json.load(f)["cases"]
+
+
+def _graph(case):
+    if case["kind"] == "bgpc":
+        return synth.from_nets(case["n"], case["nets"])
+    return synth.adjacency_from_edges(case["n"], case["edges"])
+
+
+def _run(g, **kw):
+    return oracle.bgpc(g, **kw) if hasattr(g, "n_b") else oracle.d2gc(g, **kw)
+
+
+# ---------------------------------------------------------------------------
+# independent helpers (numpy / scipy, no oracle code)
+
+
+def incidence(g):
+    """nets x vertices 0/1 matrix (bipartite) or (A + I) (distance-2)."""
+    if hasattr(g, "n_b"):
+        rows = np.repeat(np.arange(g.n_b), np.diff(g.b_off))
+        return sp.csr_matrix((np.ones(g.nnz), (rows, g.b_idx)), shape=(g.n_b, g.n_a))
+    rows = np.repeat(np.arange(g.n), np.diff(g.off))
+    a = sp.csr_matrix((np.ones(g.nnz), (rows, g.idx)), shape=(g.n, g.n))
+    return (a + sp.identity(g.n, format="csr")).tocsr()
+
+
+def conflict_graph(g):
+    """u ~ x iff they share a net (u != x)."""
+    m = incidence(g)
+    c = (m.T @ m).tocsr()
+    c.setdiag(0)
+    c.eliminate_zeros()
+    c.data[:] = 1
+    return c
+
+
+def independent_violations(g, colors):
+    m = incidence(g).tocoo()
+    col = colors[m.col]
+    if (colors < 0).any():
+        return int((colors < 0).sum())
+    key = np.lexsort((col, m.row))
+    r, c = m.row[key], col[key]
+    same = (r[1:] == r[:-1]) & (c[1:] == c[:-1])
+    return int(same.sum())
+
+
+def max_net_size(g):
+    return int(np.diff(incidence(g).indptr).max())
+
+
+def chromatic_number(adj_matrix):
+    n = adj_matrix.shape[0]
+    nbrs = [set(adj_matrix[i].indices.tolist()) for i in range(n)]
+    for k in range(1, n + 1):
+        col = [-1] * n
+
+        def place(i):
+            if i == n:
+                return True
+            for c in range(k):
+                if all(col[j] != c for j in nbrs[i]):
+                    col[i] = c
+                    if place(i + 1):
+                        return True
+            col[i] = -1
+            return False
+
+        if place(0):
+            return k
+    return 0
+
+
+# ---------------------------------------------------------------------------
+# hand-derived worked examples
+
+
+@pytest.mark.parametrize("case", _cases(), ids=lambda c: c["name"])
+def test_worked_examples(case):
+    g = _graph(case)
+    kw = dict(net_color_mask=case["net_color_mask"], policy=case["policy"], chunk=case["chunk"])
+    states = case["states"]
+    for k, expect in enumerate(states, start=1):
+        r = _run(g, max_rounds=k, **kw)
+        assert r.colors.tolist() == expect, (k, r.colors.tolist(), expect)
+        assert r.status == (oracle.OK if k == len(states) else oracle.E_NOT_CONVERGED)
+    final = _run(g, **kw)
+    assert final.rounds == len(states)
+
+
+# ---------------------------------------------------------------------------
+# closed forms
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 31, 64, 65, 130])
+def test_single_net(k):
+    """One net of k vertices: vertex-based rounds settle one vertex per round
+    (c[u] = u after k rounds); one net-based round colors it at once from the
+    top (c = k - 1 - position)."""
+    g = synth.from_nets(k, [list(range(k))])
+    r = oracle.bgpc(g)
+    assert r.colors.tolist() == list(range(k)) and r.rounds == k
+    assert r.log["w"].tolist() == list(range(k, 0, -1))
+    r = oracle.bgpc(g, net_color_mask=1)
+    assert r.colors.tolist() == list(range(k - 1, -1, -1)) and r.rounds == 1
+
+
+def test_disjoint_nets():
+    sizes = [3, 1, 7, 2, 7, 4]
+    nets, base = [], 0
+    for s in sizes:
+        nets.append(list(range(base, base + s)))
+        base += s
+    g = synth.from_nets(base, nets)
+    r = oracle.bgpc(g)
+    expect = np.concatenate([np.arange(s) for s in sizes])
+    assert np.array_equal(r.colors, expect) and r.rounds == max(sizes)
+    r = oracle.bgpc(g, net_color_mask=1)
+    assert np.array_equal(r.colors, np.concatenate([np.arange(s)[::-1] for s in sizes])) and r.rounds == 1
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_first_round_survivors(seed):
+    """Round 1 of first-fit: every vertex proposes 0, so exactly the vertices
+    without a lower-ranked neighbour keep it."""
+    g = synth.random_uniform(3000, 2500, 2, 9, seed)
+    r = oracle.bgpc(g, max_rounds=1)
+    c = conflict_graph(g).tocoo()
+    has_lower = np.zeros(g.n_a, bool)
+    has_lower[c.row[c.col < c.row]] = True
+    assert np.array_equal(r.colors == 0, ~has_lower)
+    assert np.array_equal(r.colors == -1, has_lower)
+
+
+def test_path_alternates():
+    """Nets {i, i+1}: a path; greedy colorings alternate 0, 1."""
+    n = 101
+    g = synth.from_nets(n, [[i, i + 1] for i in range(n - 1)])
+    expect = [i % 2 for i in range(n)]
+    assert oracle.seq_greedy(g).tolist() == expect
+    assert oracle.bgpc(g).colors.tolist() == expect
+
+
+def test_chunk_one_is_first_fit():
+    """With one entry per chunk the balancing state never carries over: B1 and
+    B2 start every pick at col_max = col_next = 0, which is first-fit."""
+    g = synth.random_uniform(4000, 3000, 2, 12, 8)
+    ff = oracle.bgpc(g)
+    for pol in (1, 2):
+        r = oracle.bgpc(g, policy=pol, chunk=1)
+        assert np.array_equal(r.colors, ff.colors) and r.rounds == ff.rounds
+
+
+# ---------------------------------------------------------------------------
+# validity and bounds on random graphs
+
+
+SCHEDULES = [dict(), dict(net_color_mask=1), dict(net_color_mask=0b10), dict(net_color_mask=0b11),
+             dict(policy=1), dict(policy=2), dict(net_color_mask=1, policy=1), dict(net_color_mask=1, policy=2)]
+
+
+@pytest.mark.parametrize("kw", SCHEDULES, ids=str)
+def test_valid_and_bounded(kw):
+    g = synth.random_uniform(6000, 5000, 2, 20, 17)
+    r = oracle.bgpc(g, **kw)
+    assert r.status == oracle.OK
+    assert independent_violations(g, r.colors) == 0
+    ncol = len(np.unique(r.colors))
+    assert ncol >= max_net_size(g)                       # max net size is a lower bound
+    d2 = np.diff(conflict_graph(g).indptr)
+    if not kw.get("net_color_mask") and not kw.get("policy"):
+        assert r.colors.max() <= d2.max()                  # first-fit: color <= |N(w)|
+    # termination: rounds <= popcount(mask) + n_A, and every vertex-based
+    # round colors at least the lowest-ranked worklist vertex
+    assert r.rounds <= bin(kw.get("net_color_mask", 0)).count("1") + g.n_a
+    for i in range(r.rounds - 1):
+        if r.log["mode"][i] == 0:
+            assert r.log["w"][i + 1] < r.log["w"][i]
+
+
+def test_net_round_colors_below_net_size():
+    g = synth.random_uniform(5000, 5000, 2, 30, 19)
+    r = oracle.bgpc(g, net_color_mask=1, max_rounds=1)
+    sizes = np.diff(g.b_off)
+    # every color handed out in a net round lies below the owner's size
+    owner_size = np.zeros(g.n_a, int)
+    for v in range(g.n_b):
+        for x in g.b_idx[g.b_off[v]:g.b_off[v + 1]]:
+            owner_size[x] = max(owner_size[x], sizes[v])
+    colored = r.colors >= 0
+    assert (r.colors[colored] < owner_size[colored]).all()
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_brute_force_chromatic(seed):
+    rng = np.random.Generator(np.random.PCG64(100 + seed))
+    n = int(rng.integers(3, 10))
+    nets = [rng.choice(n, size=int(rng.integers(2, min(n, 4) + 1)), replace=False).tolist()
+            for _ in range(int(rng.integers(1, 8)))]
+    g = synth.from_nets(n, nets)
+    chi = chromatic_number(conflict_graph(g))
+    for kw in SCHEDULES:
+        r = oracle.bgpc(g, **kw)
+        assert independent_violations(g, r.colors) == 0
+        assert len(np.unique(r.colors)) >= chi
+
+
+# ---------------------------------------------------------------------------
+# sequential greedy
+
+
+def test_seq_greedy_independent():
+    """Sequential first-fit written out with scipy neighbourhoods."""
+    g = synth.random_uniform(800, 700, 2, 6, 23)
+    c = conflict_graph(g)
+    colors = np.full(g.n_a, -1)
+    for u in range(g.n_a):
+        used = {int(colors[x]) for x in c[u].indices if x < u}
+        k = 0
+        while k in used:
+            k += 1
+        colors[u] = k
+    assert np.array_equal(oracle.seq_greedy(g), colors)
+
+
+def test_stencil_vertex_rounds_equal_seq_greedy():
+    """On the 27-point stencil the vertex-based rounds reach the sequential
+    greedy coloring with 27 colors (the max net size, hence optimal)."""
+    g = synth.stencil27(12)
+    r = oracle.bgpc(g)
+    sg = oracle.seq_greedy(g)
+    assert np.array_equal(r.colors, sg)
+    assert len(np.unique(sg)) == 27 == max_net_size(g)
+
+
+# ---------------------------------------------------------------------------
+# distance-2
+
+
+def test_d2gc_equals_bipartite_closed_neighbourhoods():
+    """Vertex-based distance-2 rounds are the bipartite rounds on the nets
+    N[v] (ranks and removal do not depend on the order inside a net)."""
+    adj = synth.rmat(9, 6, 0.57, 0.19, 0.19, seed=2)
+    nets = [sorted([v] + adj.idx[adj.off[v]:adj.off[v + 1]].tolist()) for v in range(adj.n)]
+    g = synth.from_nets(adj.n, nets)
+    for kw in (dict(), dict(policy=1), dict(policy=2)):
+        a = oracle.d2gc(adj, **kw)
+        b = oracle.bgpc(g, **kw)
+        assert np.array_equal(a.colors, b.colors) and a.rounds == b.rounds
+
+
+@pytest.mark.parametrize("mask", [0, 1, 3])
+def test_d2gc_valid_and_bounded(mask):
+    adj = synth.rmat(10, 8, 0.57, 0.19, 0.19, seed=6)
+    r = oracle.d2gc(adj, net_color_mask=mask)
+    assert r.status == oracle.OK
+    assert independent_violations(adj, r.colors) == 0
+    deg = np.diff(adj.off)
+    assert len(np.unique(r.colors)) >= deg.max() + 1    # Delta + 1 lower bound
+
+
+# ---------------------------------------------------------------------------
+# resume, order, statistics
+
+
+@pytest.mark.parametrize("mask", [0, 1, 0b110])
+def test_resume(mask):
+    g = synth.random_uniform(3000, 2600, 2, 10, 29)
+    full = oracle.bgpc(g, net_color_mask=mask)
+    for k in (1, 2, 3):
+        part = oracle.bgpc(g, net_color_mask=mask, max_rounds=k)
+        rest = oracle.bgpc(g, net_color_mask=mask, init_colors=part.colors, start_round=k)
+        assert np.array_equal(rest.colors, full.colors) and rest.rounds + k == full.rounds
+
+
+def test_order_is_relabelling():
+    g = synth.random_uniform(2000, 1500, 2, 8, 37)
+    rng = np.random.Generator(np.random.PCG64(3))
+    perm = rng.permutation(g.n_a)          # new id of old vertex u is perm[u]
+    nets = [sorted(perm[g.b_idx[g.b_off[v]:g.b_off[v + 1]]].tolist()) for v in range(g.n_b)]
+    h = synth.from_nets(g.n_a, nets)
+    order = np.argsort(perm)               # rank k -> old vertex with new id k
+    for kw in (dict(), dict(net_color_mask=1), dict(policy=1)):
+        via_order = oracle.bgpc(g, order=order, **kw)
+        relabelled = oracle.bgpc(h, **kw)
+        assert np.array_equal(via_order.colors, relabelled.colors[perm])
+    assert np.array_equal(oracle.bgpc(g, order=np.arange(g.n_a)).colors, oracle.bgpc(g).colors)
+
+
+def test_color_stats_against_numpy():
+    rng = np.random.Generator(np.random.PCG64(4))
+    for colors in (rng.integers(-1, 50, size=5000), np.array([0, 0, 3, 3, 3, -1]), np.array([7])):
+        colors = colors.astype(np.int32)
+        s = oracle.color_stats(colors)
+        valid = colors[colors >= 0]
+        vals, counts = np.unique(valid, return_counts=True)
+        assert s["n_distinct"] == len(vals)
+        assert s["max_color"] == valid.max()
+        assert s["card_min"] == counts.min() and s["card_max"] == counts.max()
+        assert s["n_empty_below_max"] == valid.max() + 1 - len(vals)
+        assert s["card_mean"] == pytest.approx(counts.mean(), rel=1e-12)
+        assert s["card_std"] == pytest.approx(counts.std(), rel=1e-12)
