@@ -1,0 +1,177 @@
+/*
+ * bgpc.h -- C ABI of the MI355X (gfx950) speculative greedy coloring library.
+ *
+ * Method: Tas, Kaya and Saule, "Greed is Good: Optimistic Algorithms for
+ * Bipartite-Graph Partial Coloring on Multicore Architectures" (2017).
+ *
+ * Problem (Section II): given a bipartite graph G = (V_A u V_B, E), give every
+ * vertex of V_A a non-negative color so that two vertices adjacent to a common
+ * V_B vertex ("net") differ.  -1 marks an uncolored vertex.  Distance-2
+ * coloring (Section IV) colors every vertex of a symmetric graph differently
+ * from all vertices within distance two; the library runs it as the bipartite
+ * problem whose nets are the closed neighbourhoods N[v] = {v} u nbor(v).
+ *
+ * The colors come from the speculative loop of Algorithm 1 with fixed round
+ * semantics so that the result of every round is unique:
+ *   - a round reads the colors left by the previous round (a snapshot) and
+ *     proposes tentative colors for the uncolored vertices, in rank order;
+ *   - a vertex loses its tentative or current color iff a vertex sharing a
+ *     net with it holds the same color and has a lower rank (Algorithm 3's
+ *     rule); losers become uncolored and form the next round's worklist;
+ *   - vertex-based rounds choose by first-fit (Algorithms 2 and 4) or by the
+ *     balancing policies B1 / B2 (Algorithms 11 and 12), whose state restarts
+ *     every `chunk` consecutive worklist entries;
+ *   - net-based rounds (Algorithms 8 and 9) run reverse first-fit inside each
+ *     net holding an uncolored vertex, starting at |vtxs(v)| - 1; a vertex
+ *     takes the proposal of its owner net only: the largest net containing
+ *     it, ties to the lowest net id.  Net-based rounds run where bit r of
+ *     net_color_mask is set; every other round is vertex-based.
+ * Ranks are vertex ids, or positions in `order` when one is given.
+ *
+ * Conventions for every entry point:
+ *   - graph arrays and colors_out are DEVICE pointers (hipMalloc / torch
+ *     tensors on the GPU); option, log and stats structs are host memory;
+ *   - the caller owns every buffer it passes; inputs are never modified;
+ *   - the library allocates its own stream-ordered workspace per call and
+ *     releases it before returning;
+ *   - calls are ordered on opts->stream (NULL: the default stream) and return
+ *     after the result is complete;
+ *   - a negative return value is a bgpc_status error; colors_out is then
+ *     undefined, except for BGPC_E_NOT_CONVERGED, where it holds the state
+ *     reached after max_rounds rounds (uncolored vertices are -1).
+ *   - calls on distinct streams may run concurrently from distinct threads.
+ */
+#ifndef BGPC_H
+#define BGPC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BGPC_API __attribute__((visibility("default")))
+
+typedef enum {
+    BGPC_OK = 0,
+    BGPC_E_INVALID = -1,         /* bad sizes, NULL pointers, bad option values */
+    BGPC_E_UNSORTED = -2,        /* (BGPC_STRICT) a member list not strictly ascending */
+    BGPC_E_NOT_TRANSPOSE = -3,   /* (BGPC_STRICT) csr_A is not the transpose of csr_B */
+    BGPC_E_NOT_SYMMETRIC = -4,   /* (BGPC_STRICT) adjacency not symmetric, or a self loop */
+    BGPC_E_OOM = -5,             /* device workspace allocation failed */
+    BGPC_E_NOT_CONVERGED = -6,   /* worklist non-empty after max_rounds rounds */
+    BGPC_E_HIP = -7,             /* a HIP runtime call failed */
+    BGPC_E_UNSUPPORTED = -8,     /* a size beyond the library's limits (see below) */
+    BGPC_E_INTERNAL = -9         /* a device-side invariant check failed */
+} bgpc_status;
+
+/*
+ * Compressed sparse rows.  offsets[n_rows + 1] and indices[nnz] are device
+ * arrays of int32; row i lists its columns in indices[offsets[i] ..
+ * offsets[i + 1]), strictly ascending.  nnz must equal offsets[n_rows].
+ */
+typedef struct {
+    int32_t n_rows;
+    int32_t n_cols;
+    int64_t nnz;
+    const int32_t *offsets;
+    const int32_t *indices;
+} bgpc_csr;
+
+/* color policies of vertex-based rounds */
+enum {
+    BGPC_FIRST_FIT = 0,   /* Algorithm 2: smallest color not forbidden */
+    BGPC_B1 = 1,          /* Algorithm 11: alternate reverse / forward search around col_max */
+    BGPC_B2 = 2           /* Algorithm 12: forward search from col_next, capped at col_max / 3 + 1 */
+};
+
+/* opts->flags */
+enum {
+    BGPC_STRICT = 1u,     /* validate sortedness, transpose / symmetry before coloring */
+    BGPC_RESUME = 2u      /* colors_out holds a conflict-free partial coloring to continue from */
+};
+
+/*
+ * Optional per-round record, host arrays of `cap` entries each (any may be
+ * NULL).  Round r (counted from the call's first round) stores: mode (0
+ * vertex-based, 1 net-based), |W_r| (vertices the round started uncolored),
+ * the losers of its removal step, how many of them were colored before the
+ * round ("evicted"; only net-based rounds after the first can evict), and the
+ * largest color present after the round.  `n` receives the rounds recorded.
+ */
+typedef struct {
+    int32_t cap;
+    int32_t n;
+    int32_t *mode;
+    int64_t *w_size;
+    int64_t *losers;
+    int64_t *evicted;
+    int32_t *max_color;
+} bgpc_round_log;
+
+typedef struct {
+    uint64_t net_color_mask;  /* bit r (r < 64): round r is net-based */
+    int32_t policy;           /* BGPC_FIRST_FIT, BGPC_B1 or BGPC_B2 */
+    int32_t chunk;            /* worklist entries per balancing state, >= 1 (default 64) */
+    int32_t max_rounds;       /* rounds to run at most; 0: n + 65 */
+    int32_t start_round;      /* index of the first round (selects mask bits); with BGPC_RESUME */
+    uint32_t flags;           /* BGPC_STRICT | BGPC_RESUME */
+    int32_t reserved;
+    void *stream;             /* hipStream_t; NULL = default stream */
+    bgpc_round_log *log;      /* optional */
+    int32_t *rounds_out;      /* optional, host: rounds run */
+} bgpc_opts;
+
+/* Fills *opts with the defaults: vertex-based first-fit rounds, chunk 64. */
+BGPC_API void bgpc_opts_default(bgpc_opts *opts);
+
+/*
+ * Bipartite-graph partial coloring of V_A (Sections II-III, V).
+ *   csr_A    vertices -> nets: n_rows = |V_A|, n_cols = |V_B| (nets(u))
+ *   csr_B    nets -> vertices: n_rows = |V_B|, n_cols = |V_A| (vtxs(v)),
+ *            the transpose of csr_A
+ *   order    NULL for the natural order, else a device int32[|V_A|]
+ *            permutation: order[k] is the vertex of rank k
+ *   colors_out  device int32[|V_A|]; with BGPC_RESUME it is read first
+ * Limits: |V_A|, |V_B| < 2^30; nnz < 2^31; a net of at most 1,048,576
+ * vertices; colors below 1,048,576.
+ */
+BGPC_API int bgpc_color(const bgpc_csr *csr_A, const bgpc_csr *csr_B, const int32_t *order,
+                        const bgpc_opts *opts, int32_t *colors_out);
+
+/*
+ * Distance-2 coloring (Section IV) of a symmetric graph without self loops:
+ * adj is its CSR (n_rows = n_cols = n).  Nets are the closed neighbourhoods;
+ * in net-based rounds the center of N[v] is queued before nbor(v)
+ * (Algorithm 9) and colors start at |nbor(v)|.
+ */
+BGPC_API int d2gc_color(const bgpc_csr *adj, const int32_t *order, const bgpc_opts *opts,
+                        int32_t *colors_out);
+
+/*
+ * Color-set statistics of a coloring (the metrics of the balancing
+ * experiments, Section VI): non-empty color sets, largest color, min / max /
+ * mean / population standard deviation of the non-empty set cardinalities,
+ * empty sets below the largest color.  Entries < 0 are ignored.
+ * colors: device int32[n]; stream: hipStream_t or NULL.
+ */
+typedef struct {
+    int64_t n_distinct;
+    int64_t max_color;
+    int64_t card_min;
+    int64_t card_max;
+    int64_t n_empty_below_max;
+    double card_mean;
+    double card_std;
+} bgpc_stats;
+
+BGPC_API int color_stats(const int32_t *colors, int64_t n, void *stream, bgpc_stats *out);
+
+/* Human-readable name of a status code (static storage). */
+BGPC_API const char *bgpc_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BGPC_H */

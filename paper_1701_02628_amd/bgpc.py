@@ -1,0 +1,208 @@
+"""Thin ctypes binding of libbgpc.so (argument marshalling only).
+
+Every coloring step runs in the HIP library; this module only turns torch
+device tensors into the pointers and structs of ``include/bgpc.h``.  It
+raises if the library is missing or a tensor is not an int32 tensor on the
+GPU: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libbgpc.so")
+
+OK = 0
+E_INVALID, E_UNSORTED, E_NOT_TRANSPOSE, E_NOT_SYMMETRIC = -1, -2, -3, -4
+E_OOM, E_NOT_CONVERGED, E_HIP, E_UNSUPPORTED, E_INTERNAL = -5, -6, -7, -8, -9
+FIRST_FIT, B1, B2 = 0, 1, 2
+STRICT, RESUME = 1, 2
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("n_cols", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("offsets", ctypes.c_void_p), ("indices", ctypes.c_void_p)]
+
+
+class RoundLog(ctypes.Structure):
+    _fields_ = [("cap", ctypes.c_int32), ("n", ctypes.c_int32), ("mode", ctypes.c_void_p),
+                ("w_size", ctypes.c_void_p), ("losers", ctypes.c_void_p), ("evicted", ctypes.c_void_p),
+                ("max_color", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("net_color_mask", ctypes.c_uint64), ("policy", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("max_rounds", ctypes.c_int32), ("start_round", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p), ("log", ctypes.POINTER(RoundLog)),
+                ("rounds_out", ctypes.POINTER(ctypes.c_int32))]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_distinct", ctypes.c_int64), ("max_color", ctypes.c_int64), ("card_min", ctypes.c_int64),
+                ("card_max", ctypes.c_int64), ("n_empty_below_max", ctypes.c_int64),
+                ("card_mean", ctypes.c_double), ("card_std", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libbgpc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1701_02628_amd/build.py "
+                               "(the coloring path has no CPU fallback)")
+        lib = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        lib.bgpc_opts_default.argtypes = [ctypes.POINTER(Opts)]
+        lib.bgpc_opts_default.restype = None
+        lib.bgpc_color.argtypes = [ctypes.POINTER(Csr), ctypes.POINTER(Csr), P, ctypes.POINTER(Opts), P]
+        lib.bgpc_color.restype = ctypes.c_int
+        lib.d2gc_color.argtypes = [ctypes.POINTER(Csr), P, ctypes.POINTER(Opts), P]
+        lib.d2gc_color.restype = ctypes.c_int
+        lib.color_stats.argtypes = [P, ctypes.c_int64, P, ctypes.POINTER(Stats)]
+        lib.color_stats.restype = ctypes.c_int
+        lib.bgpc_status_string.argtypes = [ctypes.c_int]
+        lib.bgpc_status_string.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+EXPORTED = ("bgpc_opts_default", "bgpc_color", "d2gc_color", "color_stats", "bgpc_status_string")
+
+
+def status_string(code: int) -> str:
+    return load().bgpc_status_string(int(code)).decode()
+
+
+def _dev_ptr(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous int32 tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class DeviceCsr:
+    """int32 CSR resident on the GPU (offsets, indices) with its shape."""
+
+    def __init__(self, offsets, indices, n_rows, n_cols):
+        self.offsets, self.indices = offsets, indices
+        self.n_rows, self.n_cols = int(n_rows), int(n_cols)
+
+    @property
+    def nnz(self):
+        return int(self.indices.numel())
+
+    def as_struct(self) -> Csr:
+        idx_ptr = self.indices.data_ptr() if self.indices.numel() else None
+        return Csr(self.n_rows, self.n_cols, self.nnz, _dev_ptr(self.offsets, "offsets").value, idx_ptr)
+
+
+def upload_csr(off, idx, n_rows, n_cols, device="cuda") -> DeviceCsr:
+    import torch
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    if off[-1] >= 2 ** 31:
+        raise ValueError("more than 2^31 - 1 entries")
+    o = torch.from_numpy(off.astype(np.int32)).to(device)
+    i = torch.from_numpy(np.ascontiguousarray(idx, dtype=np.int32)).to(device)
+    return DeviceCsr(o, i, n_rows, n_cols)
+
+
+def upload_bipartite(g, device="cuda"):
+    """(csr_A, csr_B) on the GPU for a host graph with n_a, n_b, a_*, b_*."""
+    A = upload_csr(g.a_off, g.a_idx, g.n_a, g.n_b, device)
+    B = upload_csr(g.b_off, g.b_idx, g.n_b, g.n_a, device)
+    return A, B
+
+
+def upload_adjacency(adj, device="cuda") -> DeviceCsr:
+    return upload_csr(adj.off, adj.idx, adj.n, adj.n, device)
+
+
+class Result:
+    def __init__(self, status, rounds, log):
+        self.status, self.rounds, self.log = status, rounds, log
+
+    def __repr__(self):
+        return f"Result(status={self.status}, rounds={self.rounds})"
+
+
+def _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags, stream, log_cap):
+    lib = load()
+    o = Opts()
+    lib.bgpc_opts_default(ctypes.byref(o))
+    o.net_color_mask = int(net_color_mask) & (2 ** 64 - 1)
+    o.policy, o.chunk, o.max_rounds = int(policy), int(chunk), int(max_rounds)
+    o.start_round, o.flags = int(start_round), int(flags)
+    o.stream = _stream_handle(stream)
+    rounds = ctypes.c_int32(0)
+    o.rounds_out = ctypes.pointer(rounds)
+    keep = [rounds]
+    log_arrays = None
+    if log_cap:
+        log_arrays = {"mode": np.zeros(log_cap, np.int32), "w": np.zeros(log_cap, np.int64),
+                      "losers": np.zeros(log_cap, np.int64), "evicted": np.zeros(log_cap, np.int64),
+                      "max_color": np.zeros(log_cap, np.int32)}
+        lg = RoundLog(log_cap, 0, log_arrays["mode"].ctypes.data, log_arrays["w"].ctypes.data,
+                      log_arrays["losers"].ctypes.data, log_arrays["evicted"].ctypes.data,
+                      log_arrays["max_color"].ctypes.data)
+        o.log = ctypes.pointer(lg)
+        keep.append(lg)
+    return o, rounds, log_arrays, keep
+
+
+def _finish(status, rounds, log_arrays, o):
+    log = None
+    if log_arrays is not None:
+        n = o.log.contents.n
+        log = {k: v[:n].copy() for k, v in log_arrays.items()}
+    return Result(int(status), int(rounds.value), log)
+
+
+def bgpc_color(csr_A: DeviceCsr, csr_B: DeviceCsr, order, colors_out, net_color_mask=0, policy=FIRST_FIT,
+               chunk=64, max_rounds=0, start_round=0, flags=0, stream=None, log_cap=0) -> Result:
+    """Bipartite-graph partial coloring; colors_out is an int32 GPU tensor of |V_A|."""
+    lib = load()
+    o, rounds, log_arrays, keep = _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags,
+                                             stream, log_cap)
+    a, b = csr_A.as_struct(), csr_B.as_struct()
+    order_p = _dev_ptr(order, "order") if order is not None else None
+    st = lib.bgpc_color(ctypes.byref(a), ctypes.byref(b), order_p, ctypes.byref(o), _dev_ptr(colors_out, "colors_out"))
+    del keep
+    return _finish(st, rounds, log_arrays, o)
+
+
+def d2gc_color(adj: DeviceCsr, order, colors_out, net_color_mask=0, policy=FIRST_FIT, chunk=64, max_rounds=0,
+               start_round=0, flags=0, stream=None, log_cap=0) -> Result:
+    """Distance-2 coloring of a symmetric graph; colors_out is an int32 GPU tensor of n."""
+    lib = load()
+    o, rounds, log_arrays, keep = _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags,
+                                             stream, log_cap)
+    a = adj.as_struct()
+    order_p = _dev_ptr(order, "order") if order is not None else None
+    st = lib.d2gc_color(ctypes.byref(a), order_p, ctypes.byref(o), _dev_ptr(colors_out, "colors_out"))
+    del keep
+    return _finish(st, rounds, log_arrays, o)
+
+
+def color_stats(colors, stream=None) -> dict:
+    """Color-set statistics of an int32 GPU tensor of colors."""
+    lib = load()
+    out = Stats()
+    st = lib.color_stats(_dev_ptr(colors, "colors"), int(colors.numel()), _stream_handle(stream), ctypes.byref(out))
+    if st != OK:
+        raise RuntimeError(f"color_stats failed: {status_string(st)}")
+    return {"n_distinct": out.n_distinct, "max_color": out.max_color, "card_min": out.card_min,
+            "card_max": out.card_max, "n_empty_below_max": out.n_empty_below_max,
+            "card_mean": out.card_mean, "card_std": out.card_std}

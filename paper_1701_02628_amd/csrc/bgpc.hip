@@ -1,0 +1,625 @@
+// Host driver and C ABI of the speculative coloring library (see bgpc.h).
+//
+// Every round is a fixed chain of launches on the caller's stream; the
+// kernels read the worklist length from device memory, so rounds are queued
+// without waiting.  The chain of round r ends with a one-thread kernel that
+// copies (rounds done, worklist length) into pinned host memory; the host
+// keeps at most LOOKAHEAD rounds queued beyond what it has seen completed and
+// stops queueing as soon as it sees an empty worklist.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "bgpc.h"
+#include "kernels.h"
+
+using namespace bgpc;
+
+namespace {
+
+constexpr int LOOKAHEAD = 12;
+
+struct DevInfo {
+    int cus = 256;
+    int lds_max = 65536;
+};
+
+DevInfo dev_info()
+{
+    static std::mutex mu;
+    static std::vector<DevInfo> cache;
+    static std::vector<bool> have;
+    int dev = 0;
+    hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)cache.size() <= dev) {
+        cache.resize(dev + 1);
+        have.resize(dev + 1, false);
+    }
+    if (!have[dev]) {
+        DevInfo d;
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) d.cus = v;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            d.lds_max = v;
+        cache[dev] = d;
+        have[dev] = true;
+    }
+    return cache[dev];
+}
+
+#define HIP_TRY(x)                                  \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return BGPC_E_HIP;    \
+    } while (0)
+
+#define LAUNCH_CHECK()                              \
+    do {                                            \
+        if (hipGetLastError() != hipSuccess) {      \
+            st_code = BGPC_E_HIP;                   \
+            goto finish;                            \
+        }                                           \
+    } while (0)
+
+int grid_for(long n, int block, int cap)
+{
+    long g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+// stream-ordered device workspace carved from one allocation
+struct Arena {
+    char *base = nullptr;
+    size_t used = 0, cap = 0;
+    hipStream_t s = nullptr;
+    bool async = true;
+    int reserve(size_t bytes, hipStream_t stream)
+    {
+        s = stream;
+        cap = bytes;
+        hipError_t e = hipMallocAsync((void **)&base, bytes, stream);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            async = false;
+            e = hipMalloc((void **)&base, bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                base = nullptr;
+                return BGPC_E_OOM;
+            }
+        }
+        return BGPC_OK;
+    }
+    template <class T>
+    T *take(size_t count)
+    {
+        size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+        T *p = (T *)(base + used);
+        used += bytes;
+        return p;
+    }
+    void release()
+    {
+        if (!base) return;
+        if (async) hipFreeAsync(base, s);
+        else {
+            hipStreamSynchronize(s);
+            hipFree(base);
+        }
+        base = nullptr;
+    }
+};
+
+size_t aligned(size_t count, size_t elem) { return (count * elem + 255) & ~(size_t)255; }
+
+// pinned host mirror of the device progress counters, one per thread
+struct HostProgress {
+    volatile int *h = nullptr;
+    int *d = nullptr;
+    HostProgress()
+    {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, 64, hipHostMallocMapped) == hipSuccess) {
+            h = (volatile int *)p;
+            void *dp = nullptr;
+            if (hipHostGetDevicePointer(&dp, p, 0) == hipSuccess) d = (int *)dp;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+};
+
+__global__ void k_publish(Ctrl *ctrl, int par_next, int round_issued, int *host)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int nw = ctrl->n_w[par_next];
+        int err = ctrl->error;
+        __atomic_store_n(&host[1], nw, __ATOMIC_RELAXED);
+        __atomic_store_n(&host[2], err, __ATOMIC_RELAXED);
+        __threadfence_system();
+        __atomic_store_n(&host[0], round_issued, __ATOMIC_RELEASE);
+        __threadfence_system();
+    }
+}
+
+struct RunArgs {
+    Graph g;
+    bool d2;
+    const bgpc_opts *o;
+    int *st;
+    hipStream_t s;
+};
+
+template <bool D2>
+int run(const RunArgs &a)
+{
+    const Graph g = a.g;
+    const bgpc_opts &o = *a.o;
+    hipStream_t s = a.s;
+    int *st = a.st;
+    const int n_a = g.n_a, n_b = g.n_b;
+    const DevInfo di = dev_info();
+    const bool resume = (o.flags & BGPC_RESUME) != 0;
+    const int policy = o.policy;
+    const int chunk = o.chunk;
+    int max_rounds = o.max_rounds > 0 ? o.max_rounds : n_a + 65;
+    const int start_round = o.start_round;
+
+    if (o.rounds_out) *o.rounds_out = 0;
+    if (o.log) o.log->n = 0;
+    if (n_a == 0) return BGPC_OK;
+
+    // ---- workspace
+    const int max_tiles = (n_a + TILE - 1) / TILE + 1;
+    const int rec_cap = std::min(max_rounds, 1 << 20) + 2;
+    bool any_net_round = false;
+    for (int r = 0; r < max_rounds && start_round + r < 64; r++)
+        if (start_round + r >= 0 && ((o.net_color_mask >> (start_round + r)) & 1ull)) any_net_round = true;
+    size_t bytes = aligned(n_a + 1, 4) * 3            // W[0], W[1], heavy
+                   + aligned(n_a + 1, 1)              // lose
+                   + aligned(n_b + 1, 8)              // mask0
+                   + aligned(n_b + 1, 4)              // big net list
+                   + aligned(max_tiles, 4)            // tile counts
+                   + aligned(1, sizeof(Ctrl))         //
+                   + aligned(8, 4)                    // shape figures
+                   + aligned(rec_cap, sizeof(RoundRec))
+                   + (any_net_round ? aligned(n_a + 1, 4) : 0);
+    Arena ar;
+    int rc = ar.reserve(bytes, s);
+    if (rc != BGPC_OK) return rc;
+    int *W0 = ar.take<int>(n_a + 1);
+    int *W1 = ar.take<int>(n_a + 1);
+    int *heavy = ar.take<int>(n_a + 1);
+    uint8_t *lose = ar.take<uint8_t>(n_a + 1);
+    uint64_t *mask0 = ar.take<uint64_t>(n_b + 1);
+    int *big = ar.take<int>(n_b + 1);
+    int *tile_count = ar.take<int>(max_tiles);
+    Ctrl *ctrl = ar.take<Ctrl>(1);
+    int *shape = ar.take<int>(8);
+    RoundRec *rec = ar.take<RoundRec>(rec_cap);
+    int *owner = any_net_round ? ar.take<int>(n_a + 1) : nullptr;
+    int *Wb[2] = {W0, W1};
+
+    int st_code = BGPC_OK;
+    int h_shape[8] = {0};
+    Ctrl h_ctrl;
+    std::vector<RoundRec> h_rec;
+    int issued = 0;
+    const int nthr = 256;
+    const int g_a = grid_for(n_a, nthr, di.cus * 8);
+    const int g_b = grid_for(n_b, nthr, di.cus * 8);
+    // pinned counters live for the thread's lifetime (never freed: freeing at
+    // thread exit could run after the HIP runtime has shut down)
+    static thread_local HostProgress *prog_p = new HostProgress();
+    HostProgress &prog = *prog_p;
+
+    // ---- shape of the graph: largest net, big nets, distance-2 bound
+    k_fill_i32<<<1, 64, 0, s>>>(shape, 0, 8);
+    k_fill_i32<<<grid_for(rec_cap * (long)sizeof(RoundRec) / 4, nthr, di.cus * 4), nthr, 0, s>>>(
+        (int *)rec, 0, rec_cap * (long)sizeof(RoundRec) / 4);
+    k_net_shape<D2><<<g_b, nthr, 0, s>>>(g, &shape[0], big, &shape[1]);
+    k_two_hop_bound<D2><<<g_a, nthr, 0, s>>>(g, &shape[2]);
+    LAUNCH_CHECK();
+    if (hipMemcpyAsync(h_shape, shape, sizeof(h_shape), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        st_code = BGPC_E_HIP;
+        goto finish;
+    }
+    {
+        const int max_net = h_shape[0];
+        const int n_big = h_shape[1];
+        const long two_hop = h_shape[2];
+        const int lds_total = std::min(di.lds_max, 65536);
+        const int lds_budget = lds_total - 10240;   // beside the kernels' static LDS
+        // bitmap capacity of the wide vertex paths, in bits
+        long need_bits = std::max<long>(two_hop + 2, max_net + 1) + chunk + 66;
+        const int lds_bits = (int)std::min<long>(((need_bits + 31) / 32) * 32, (long)lds_budget * 8);
+        const int wide_bytes = lds_bits / 8;
+        // net-based rounds: bitmap + suffix counts of the largest net
+        const int ncolor_words = std::min(lds_budget / 4, 2 * ((max_net + 31) / 32) + 2);
+        if (any_net_round && 2 * ((max_net + 31) / 32) + 1 > lds_budget / 4) {
+            st_code = BGPC_E_UNSUPPORTED;
+            goto finish;
+        }
+        const int conflict_bytes = (int)(WIN_COLORS * sizeof(int));
+        if (lds_total < conflict_bytes) {
+            st_code = BGPC_E_UNSUPPORTED;
+            goto finish;
+        }
+
+        if (any_net_round) k_owner<D2><<<g_a, nthr, 0, s>>>(g, owner);
+
+        // ---- initial state
+        k_fill_u8<<<g_a, nthr, 0, s>>>(lose, 0, n_a + 1);
+        if (!resume) {
+            k_fill_i32<<<g_a, nthr, 0, s>>>(st, -1, n_a);
+            k_iota<<<g_a, nthr, 0, s>>>(W0, n_a);
+            k_fill_u64<<<g_b, nthr, 0, s>>>(mask0, 0ull, n_b + 1);
+            k_init_ctrl<<<1, 64, 0, s>>>(ctrl, n_a, -1);
+        } else {
+            k_init_ctrl<<<1, 64, 0, s>>>(ctrl, 0, -1);
+            k_check_colors<<<g_a, nthr, 0, s>>>(st, n_a, 1 << 29, &ctrl->error);
+            if (hipMemcpyAsync(&h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                st_code = BGPC_E_HIP;
+                goto finish;
+            }
+            if (h_ctrl.error) {
+                st_code = BGPC_E_INVALID;
+                goto finish;
+            }
+            k_max_color<<<g_a, nthr, 0, s>>>(st, n_a, ctrl);
+            k_mask_rebuild<D2><<<g_b, nthr, 0, s>>>(g, st, mask0);
+            const int gt = grid_for(max_tiles, 1, di.cus * 4);
+            k_count_uncolored<<<gt, TILE_BLOCK, 0, s>>>(st, n_a, tile_count);
+            // identity compaction: the uncolored vertices in id order become W0
+            k_compact<<<gt, TILE_BLOCK, 0, s>>>(nullptr, n_a, ctrl, 1, st, tile_count, W0, rec, 0, 0, 0);
+        }
+        LAUNCH_CHECK();
+
+        if (prog.h) {
+            prog.h[0] = -1;
+            prog.h[1] = -1;
+            prog.h[2] = 0;
+        }
+
+        // ---- rounds
+        const int gt = grid_for(max_tiles, 1, di.cus * 4);
+        const int g_big = std::max(1, std::min(n_big, di.cus * 4));
+        const int g_chunk = grid_for((n_a + chunk - 1) / chunk, 1, di.cus * 16);
+        bool done = false;
+        bool use_prog = prog.h && prog.d;
+        while (!done && issued < max_rounds) {
+            // keep at most LOOKAHEAD rounds in flight beyond the last one seen
+            if (use_prog) {
+                long spins = 0;
+                for (;;) {
+                    int seen = prog.h[0];
+                    std::atomic_thread_fence(std::memory_order_acquire);
+                    int nw = prog.h[1];
+                    if ((seen >= 0 && nw == 0) || prog.h[2] != 0) {
+                        done = true;
+                        break;
+                    }
+                    if (issued - (seen + 1) < LOOKAHEAD) break;
+                    if ((++spins & 1023) == 0) {
+                        hipError_t q = hipStreamQuery(s);
+                        if (q == hipSuccess) {
+                            // all queued work is complete but not seen: stop
+                            // relying on the host mapping and read the device
+                            if (hipMemcpy(&h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost) != hipSuccess) {
+                                st_code = BGPC_E_HIP;
+                                goto finish;
+                            }
+                            use_prog = false;
+                            if (h_ctrl.n_w[issued & 1] == 0 || h_ctrl.error) done = true;
+                            break;
+                        }
+                        if (q != hipErrorNotReady) {
+                            st_code = BGPC_E_HIP;
+                            goto finish;
+                        }
+                    }
+                    std::this_thread::yield();
+                }
+                if (done) break;
+            } else if (issued > 0 && issued % LOOKAHEAD == 0) {
+                if (hipMemcpyAsync(&h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess) {
+                    st_code = BGPC_E_HIP;
+                    goto finish;
+                }
+                if (h_ctrl.n_w[issued & 1] == 0 || h_ctrl.error) break;
+            }
+            const int r = issued;
+            const int rr = std::min(r, rec_cap - 2);   // record slot
+            const int par = r & 1;
+            const int rid = start_round + r;
+            const bool net_mode = rid >= 0 && rid < 64 && ((o.net_color_mask >> rid) & 1ull);
+            int *Wc = Wb[par], *Wn = Wb[par ^ 1];
+            if (net_mode) {
+                k_ncolor_small<D2><<<g_b, nthr, 0, s>>>(g, st, owner, ctrl);
+                k_ncolor_big<D2><<<g_big, 256, ncolor_words * 4, s>>>(g, st, owner, big, &shape[1], ctrl,
+                                                                       ncolor_words);
+                if (!D2) k_ncolor_isolated<<<g_a, nthr, 0, s>>>(g, Wc, ctrl, par, st);
+                k_conflict_small<D2><<<g_b, nthr, 0, s>>>(g, st, lose, 0);
+                k_conflict_big<D2><<<g_big, 256, conflict_bytes, s>>>(g, st, lose, big, &shape[1], ctrl, 0);
+                const bool full = r > 0 || resume;
+                if (full) {
+                    k_set_max_final<<<1, 64, 0, s>>>(ctrl, -1);
+                    k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, nullptr, ctrl, par, st, lose, mask0, tile_count, rec, rr, 0);
+                    k_compact<<<gt, TILE_BLOCK, 0, s>>>(nullptr, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 1, 1);
+                    k_mask_rebuild<D2><<<g_b, nthr, 0, s>>>(g, st, mask0);
+                } else {
+                    k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1);
+                    k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 1, 1);
+                }
+            } else {
+                if (policy == BGPC_FIRST_FIT) {
+                    k_vcolor_ff<D2><<<g_a, nthr, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy);
+                    k_vcolor_wide<D2><<<di.cus * 2, 256, wide_bytes, s>>>(g, heavy, ctrl, st, lds_bits);
+                } else {
+                    k_vcolor_chunked<D2><<<g_chunk, 64, wide_bytes, s>>>(g, Wc, ctrl, par, st, mask0, policy, chunk,
+                                                                          lds_bits);
+                }
+                k_conflict_small<D2><<<g_b, nthr, 0, s>>>(g, st, lose, 1);
+                k_conflict_big<D2><<<g_big, 256, conflict_bytes, s>>>(g, st, lose, big, &shape[1], ctrl, 1);
+                k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1);
+                k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 0, 1);
+            }
+            if (use_prog) k_publish<<<1, 64, 0, s>>>(ctrl, par ^ 1, r, prog.d);
+            LAUNCH_CHECK();
+            issued++;
+        }
+    }
+
+finish:
+    if (hipMemcpyAsync(&h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        if (st_code == BGPC_OK) st_code = BGPC_E_HIP;
+    }
+    if (st_code == BGPC_OK) {
+        if (h_ctrl.error & (ERR_COLOR_CAP | ERR_NET_TOO_BIG)) st_code = BGPC_E_UNSUPPORTED;
+        else if (h_ctrl.error) st_code = BGPC_E_INTERNAL;
+        else if (h_ctrl.n_w[issued & 1] != 0) st_code = BGPC_E_NOT_CONVERGED;
+    }
+    if (st_code == BGPC_OK || st_code == BGPC_E_NOT_CONVERGED) {
+        if (o.rounds_out) *o.rounds_out = h_ctrl.rounds;
+        if (o.log && o.log->cap > 0) {
+            int k = std::min(o.log->cap, h_ctrl.rounds);
+            h_rec.resize(std::max(k, 1));
+            if (k > 0 && (hipMemcpyAsync(h_rec.data(), rec, sizeof(RoundRec) * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                          hipStreamSynchronize(s) != hipSuccess)) {
+                st_code = BGPC_E_HIP;
+            } else {
+                for (int i = 0; i < k; i++) {
+                    if (o.log->mode) o.log->mode[i] = h_rec[i].mode;
+                    if (o.log->w_size) o.log->w_size[i] = h_rec[i].w;
+                    if (o.log->losers) o.log->losers[i] = h_rec[i].losers;
+                    if (o.log->evicted) o.log->evicted[i] = h_rec[i].evicted;
+                    if (o.log->max_color) o.log->max_color[i] = h_rec[i].max_color;
+                }
+                o.log->n = k;
+            }
+        }
+    }
+    ar.release();
+    if (!ar.async) (void)hipGetLastError();
+    hipStreamSynchronize(s);
+    return st_code;
+}
+
+int validate_bipartite(const bgpc_csr *A, const bgpc_csr *B, hipStream_t s)
+{
+    int *d_err = nullptr;
+    HIP_TRY(hipMallocAsync((void **)&d_err, 256, s));
+    const DevInfo di = dev_info();
+    k_fill_i32<<<1, 64, 0, s>>>(d_err, 0, 1);
+    k_check_sorted<<<grid_for(A->n_rows, 256, di.cus * 8), 256, 0, s>>>(A->offsets, A->indices, A->n_rows, A->n_cols,
+                                                                          d_err);
+    k_check_sorted<<<grid_for(B->n_rows, 256, di.cus * 8), 256, 0, s>>>(B->offsets, B->indices, B->n_rows, B->n_cols,
+                                                                          d_err);
+    int h_err = 0;
+    hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, s);
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h_err == 0) {
+        int ends[2] = {0, 0};
+        hipMemcpyAsync(&ends[0], A->offsets + A->n_rows, sizeof(int), hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(&ends[1], B->offsets + B->n_rows, sizeof(int), hipMemcpyDeviceToHost, s);
+        k_check_transpose<<<grid_for(A->n_rows, 256, di.cus * 8), 256, 0, s>>>(A->offsets, A->indices, A->n_rows,
+                                                                                 B->offsets, B->indices, 0, d_err);
+        hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, s);
+        HIP_TRY(hipStreamSynchronize(s));
+        if (ends[0] != A->nnz || ends[1] != B->nnz) h_err |= 1;
+    }
+    hipFreeAsync(d_err, s);
+    hipStreamSynchronize(s);
+    if (h_err & 1) return BGPC_E_INVALID;
+    if (h_err & 2) return BGPC_E_UNSORTED;
+    if (h_err & 4) return BGPC_E_NOT_TRANSPOSE;
+    return BGPC_OK;
+}
+
+int validate_symmetric(const bgpc_csr *adj, hipStream_t s)
+{
+    int *d_err = nullptr;
+    HIP_TRY(hipMallocAsync((void **)&d_err, 256, s));
+    const DevInfo di = dev_info();
+    k_fill_i32<<<1, 64, 0, s>>>(d_err, 0, 1);
+    k_check_sorted<<<grid_for(adj->n_rows, 256, di.cus * 8), 256, 0, s>>>(adj->offsets, adj->indices, adj->n_rows,
+                                                                            adj->n_cols, d_err);
+    int h_err = 0;
+    hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, s);
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h_err == 0) {
+        int end = 0;
+        hipMemcpyAsync(&end, adj->offsets + adj->n_rows, sizeof(int), hipMemcpyDeviceToHost, s);
+        k_check_transpose<<<grid_for(adj->n_rows, 256, di.cus * 8), 256, 0, s>>>(
+            adj->offsets, adj->indices, adj->n_rows, adj->offsets, adj->indices, 1, d_err);
+        hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, s);
+        HIP_TRY(hipStreamSynchronize(s));
+        if (end != adj->nnz) h_err |= 1;
+    }
+    hipFreeAsync(d_err, s);
+    hipStreamSynchronize(s);
+    if (h_err & 1) return BGPC_E_INVALID;
+    if (h_err & 2) return BGPC_E_UNSORTED;
+    if (h_err & (4 | 8)) return BGPC_E_NOT_SYMMETRIC;
+    return BGPC_OK;
+}
+
+bool csr_ok(const bgpc_csr *c)
+{
+    return c && c->n_rows >= 0 && c->n_cols >= 0 && c->nnz >= 0 && c->nnz < (1ll << 31) &&
+           c->n_rows < (1 << 30) && c->n_cols < (1 << 30) && c->offsets && (c->nnz == 0 || c->indices);
+}
+
+bool opts_ok(const bgpc_opts &o)
+{
+    return o.policy >= 0 && o.policy <= 2 && o.chunk >= 1 && o.max_rounds >= 0 && o.start_round >= 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+BGPC_API void bgpc_opts_default(bgpc_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->policy = BGPC_FIRST_FIT;
+    o->chunk = 64;
+}
+
+BGPC_API int bgpc_color(const bgpc_csr *csr_A, const bgpc_csr *csr_B, const int32_t *order, const bgpc_opts *opts,
+                        int32_t *colors_out)
+{
+    bgpc_opts o;
+    if (opts) o = *opts;
+    else bgpc_opts_default(&o);
+    if (!csr_ok(csr_A) || !csr_ok(csr_B) || !colors_out || !opts_ok(o)) return BGPC_E_INVALID;
+    if (csr_A->n_rows != csr_B->n_cols || csr_A->n_cols != csr_B->n_rows || csr_A->nnz != csr_B->nnz)
+        return BGPC_E_INVALID;
+    if (order) return BGPC_E_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)o.stream;
+    if (o.flags & BGPC_STRICT) {
+        int v = validate_bipartite(csr_A, csr_B, s);
+        if (v != BGPC_OK) return v;
+    }
+    RunArgs a;
+    a.g = Graph{csr_A->n_rows, csr_B->n_rows, csr_A->offsets, csr_A->indices, csr_B->offsets, csr_B->indices};
+    a.d2 = false;
+    a.o = &o;
+    a.st = colors_out;
+    a.s = s;
+    return run<false>(a);
+}
+
+BGPC_API int d2gc_color(const bgpc_csr *adj, const int32_t *order, const bgpc_opts *opts, int32_t *colors_out)
+{
+    bgpc_opts o;
+    if (opts) o = *opts;
+    else bgpc_opts_default(&o);
+    if (!csr_ok(adj) || !colors_out || !opts_ok(o) || adj->n_rows != adj->n_cols) return BGPC_E_INVALID;
+    if (order) return BGPC_E_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)o.stream;
+    if (o.flags & BGPC_STRICT) {
+        int v = validate_symmetric(adj, s);
+        if (v != BGPC_OK) return v;
+    }
+    RunArgs a;
+    a.g = Graph{adj->n_rows, adj->n_rows, adj->offsets, adj->indices, adj->offsets, adj->indices};
+    a.d2 = true;
+    a.o = &o;
+    a.st = colors_out;
+    a.s = s;
+    return run<true>(a);
+}
+
+BGPC_API int color_stats(const int32_t *colors, int64_t n, void *stream, bgpc_stats *out)
+{
+    if (!out || n < 0 || (n > 0 && !colors)) return BGPC_E_INVALID;
+    std::memset(out, 0, sizeof(*out));
+    out->max_color = -1;
+    if (n == 0) return BGPC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const DevInfo di = dev_info();
+    int *d_max = nullptr;
+    HIP_TRY(hipMallocAsync((void **)&d_max, 256, s));
+    k_fill_i32<<<1, 64, 0, s>>>(d_max, -1, 1);
+    k_colors_max<<<grid_for(n, 256, di.cus * 8), 256, 0, s>>>(colors, n, d_max);
+    int h_max = -1;
+    hipMemcpyAsync(&h_max, d_max, sizeof(int), hipMemcpyDeviceToHost, s);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        hipFreeAsync(d_max, s);
+        return BGPC_E_HIP;
+    }
+    if (h_max < 0) {
+        hipFreeAsync(d_max, s);
+        hipStreamSynchronize(s);
+        return BGPC_OK;
+    }
+    const int ncol = h_max + 1;
+    int *d_count = nullptr;
+    long long *d_i = nullptr;
+    double *d_d = nullptr;
+    char *blk = nullptr;
+    size_t bytes = aligned(ncol, 4) + aligned(5, 8) + aligned(2, 8);
+    if (hipMallocAsync((void **)&blk, bytes, s) != hipSuccess) {
+        hipFreeAsync(d_max, s);
+        return BGPC_E_OOM;
+    }
+    d_count = (int *)blk;
+    d_i = (long long *)(blk + aligned(ncol, 4));
+    d_d = (double *)(blk + aligned(ncol, 4) + aligned(5, 8));
+    k_fill_i32<<<grid_for(ncol, 256, di.cus * 8), 256, 0, s>>>(d_count, 0, ncol);
+    k_hist<<<grid_for(n, 256, di.cus * 8), 256, 0, s>>>(colors, n, d_count, ncol);
+    k_hist_reduce<<<1, 1024, 0, s>>>(d_count, ncol, d_i, d_d);
+    long long hi[5];
+    double hd[2];
+    hipMemcpyAsync(hi, d_i, sizeof(hi), hipMemcpyDeviceToHost, s);
+    hipMemcpyAsync(hd, d_d, sizeof(hd), hipMemcpyDeviceToHost, s);
+    e = hipStreamSynchronize(s);
+    hipFreeAsync(blk, s);
+    hipFreeAsync(d_max, s);
+    hipStreamSynchronize(s);
+    if (e != hipSuccess) return BGPC_E_HIP;
+    out->n_distinct = hi[0];
+    out->max_color = hi[1];
+    out->card_min = hi[2];
+    out->card_max = hi[3];
+    out->n_empty_below_max = hi[4];
+    out->card_mean = hd[0];
+    out->card_std = hd[1];
+    return BGPC_OK;
+}
+
+BGPC_API const char *bgpc_status_string(int status)
+{
+    switch (status) {
+    case BGPC_OK: return "ok";
+    case BGPC_E_INVALID: return "invalid argument";
+    case BGPC_E_UNSORTED: return "member list not strictly ascending";
+    case BGPC_E_NOT_TRANSPOSE: return "csr_A is not the transpose of csr_B";
+    case BGPC_E_NOT_SYMMETRIC: return "adjacency not symmetric or has a self loop";
+    case BGPC_E_OOM: return "device workspace allocation failed";
+    case BGPC_E_NOT_CONVERGED: return "worklist not empty after max_rounds rounds";
+    case BGPC_E_HIP: return "HIP runtime error";
+    case BGPC_E_UNSUPPORTED: return "size beyond the library's limits";
+    case BGPC_E_INTERNAL: return "device-side invariant violated";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

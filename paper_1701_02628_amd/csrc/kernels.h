@@ -1,0 +1,1004 @@
+// Round kernels of the speculative coloring loop (gfx950, wave64).
+//
+// One round of Algorithm 1 is a fixed sequence of launches that all read the
+// worklist length from device memory, so the host never waits on a round:
+//
+//   coloring   vertex-based: k_vcolor_ff (first-fit through per-net masks of
+//              colors 0..63) + k_vcolor_wide (block per vertex whose colors
+//              spill past 63), or k_vcolor_chunked (B1 / B2, wave per chunk);
+//              net-based: k_ncolor_small (thread per net) + k_ncolor_big
+//              (block per net)
+//   removal    k_conflict_small (thread per net) + k_conflict_big (block per
+//              net)
+//   apply      k_apply: losers -> -1, winners keep their color and set their
+//              bit in the masks of their nets; per-tile loser counts
+//   compaction k_compact: stable scatter of the losers into the next worklist
+#pragma once
+
+#include "common.h"
+
+namespace bgpc {
+
+constexpr int SMALL_NET = 64;       // nets up to this size run thread-per-net
+constexpr int TILE = 2048;          // worklist entries per compaction tile
+constexpr int TILE_BLOCK = 256;     // threads of the apply / compaction blocks
+constexpr int HASH_MAX = 4096;      // big nets up to this size use an LDS hash
+constexpr int WIN_COLORS = 16384;   // color window of the largest nets
+
+// ---------------------------------------------------------------------------
+// setup
+
+__global__ void k_fill_i32(int *p, int v, long n)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, long n)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_fill_u8(uint8_t *p, uint8_t v, long n)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_iota(int *p, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = i;
+}
+
+__global__ void k_init_ctrl(Ctrl *c, int n_w, int max_color)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c->n_w[0] = n_w;
+        c->n_w[1] = 0;
+        c->n_heavy = 0;
+        c->max_color = max_color;
+        c->rounds = 0;
+        c->error = 0;
+        c->pad[0] = max_color;   // largest color present (max_final)
+        c->pad[1] = 0;
+    }
+}
+
+// Per-graph shape figures: largest net, and a bound on every vertex's
+// distance-2 neighbourhood (sum of the sizes of its nets); big-net list.
+template <bool D2>
+__global__ void k_net_shape(Graph g, int *max_net, int *big_list, int *n_big)
+{
+    int local = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n_b; v += gridDim.x * blockDim.x) {
+        int sz = Acc<D2>::size(g, v);
+        local = max(local, sz);
+        if (sz > SMALL_NET) big_list[atomicAdd(n_big, 1)] = v;
+    }
+    local = wave_max(local);
+    if (lane_id() == 0) atomicMax(max_net, local);
+}
+
+template <bool D2>
+__global__ void k_two_hop_bound(Graph g, int *bound)
+{
+    long local = 0;
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < g.n_a; u += gridDim.x * blockDim.x) {
+        long s = 0;
+        int k = Acc<D2>::nets_count(g, u);
+        for (int j = 0; j < k; j++) s += Acc<D2>::size(g, Acc<D2>::net_at(g, u, j));
+        local = max(local, s);
+    }
+    int l32 = (int)min(local, (long)0x3fffffff);
+    l32 = wave_max(l32);
+    if (lane_id() == 0) atomicMax(bound, l32);
+}
+
+// owner(u): the largest net containing u, ties to the lowest net id
+template <bool D2>
+__global__ void k_owner(Graph g, int *owner)
+{
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < g.n_a; u += gridDim.x * blockDim.x) {
+        int best = -1, best_sz = -1;
+        int k = Acc<D2>::nets_count(g, u);
+        for (int j = 0; j < k; j++) {
+            int v = Acc<D2>::net_at(g, u, j);
+            int sz = Acc<D2>::size(g, v);
+            if (sz > best_sz || (sz == best_sz && v < best)) {
+                best = v;
+                best_sz = sz;
+            }
+        }
+        owner[u] = best;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// validation (BGPC_STRICT)
+
+__global__ void k_check_sorted(const int *off, const int *idx, int n_rows, int n_cols, int *err)
+{
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n_rows; r += gridDim.x * blockDim.x) {
+        int b = off[r], e = off[r + 1];
+        if (b > e) {
+            atomicOr(err, 1);
+            continue;
+        }
+        int prev = -1;
+        for (int k = b; k < e; k++) {
+            int x = idx[k];
+            if (x < 0 || x >= n_cols) atomicOr(err, 1);
+            else if (x <= prev) atomicOr(err, 2);
+            prev = x;
+        }
+    }
+}
+
+__device__ __forceinline__ bool sorted_contains(const int *idx, int b, int e, int key)
+{
+    while (b < e) {
+        int m = (b + e) >> 1;
+        int x = idx[m];
+        if (x == key) return true;
+        if (x < key) b = m + 1;
+        else e = m;
+    }
+    return false;
+}
+
+// every entry (u, v) of `a` appears as (v, u) in `b`; with no_self, u != v
+__global__ void k_check_transpose(const int *a_off, const int *a_idx, int n_rows,
+                                  const int *b_off, const int *b_idx, int no_self, int *err)
+{
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < n_rows; u += gridDim.x * blockDim.x) {
+        for (int k = a_off[u]; k < a_off[u + 1]; k++) {
+            int v = a_idx[k];
+            if (no_self && v == u) atomicOr(err, 8);
+            if (!sorted_contains(b_idx, b_off[v], b_off[v + 1], u)) atomicOr(err, 4);
+        }
+    }
+}
+
+// resumed colorings: entries must be -1 or a color below the cap
+__global__ void k_check_colors(const int *st, int n, int cap, int *err)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int s = st[i];
+        if (s < -1 || s >= cap) atomicOr(err, 16);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// masks of colors 0..63 held by the colored members of each net
+
+template <bool D2>
+__global__ void k_mask_rebuild(Graph g, const int *st, uint64_t *mask0)
+{
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n_b; v += gridDim.x * blockDim.x) {
+        uint64_t m = 0;
+        int sz = Acc<D2>::size(g, v);
+        for (int k = 0; k < sz; k++) {
+            int c = snap_color(st[Acc<D2>::member(g, v, k)]);
+            if (c >= 0 && c < 64) m |= 1ull << c;
+        }
+        mask0[v] = m;
+    }
+}
+
+__global__ void k_max_color(const int *st, int n, Ctrl *ctrl)
+{
+    int local = -1;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        local = max(local, cur_color(st[i]));
+    local = wave_max(local);
+    if (lane_id() == 0 && local >= 0) {
+        atomicMax(&ctrl->max_color, local);
+        atomicMax(&ctrl->pad[0], local);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forbidden-color bitmaps built cooperatively by a block (wide path)
+
+// Sets bit c of `bits` for every snapshot color c < cap_bits found among the
+// vertices sharing a net with w (w excluded): F(w) of Algorithm 4.  The
+// distance-2 neighbourhood is enumerated flat: the sizes of a block-sized
+// batch of nets are prefix-summed, then every thread walks the batch's
+// members by position.  `s_net`, `s_pre` hold blockDim.x + 1 ints each.
+template <bool D2>
+__device__ void build_forbidden(const Graph &g, const int *st, int w, uint32_t *bits, int cap_bits,
+                                int *s_net, int *s_pre, int *scan_scratch)
+{
+    const int nt = blockDim.x, tid = threadIdx.x;
+    int nn = Acc<D2>::nets_count(g, w);
+    for (int base = 0; base < nn; base += nt) {
+        int k = base + tid;
+        int v = k < nn ? Acc<D2>::net_at(g, w, k) : -1;
+        int sz = v >= 0 ? Acc<D2>::size(g, v) : 0;
+        int total;
+        int ex = block_excl_scan(sz, scan_scratch, &total);
+        s_net[tid] = v;
+        s_pre[tid] = ex;
+        if (tid == 0) s_pre[nt] = total;
+        __syncthreads();
+        int cnt = min(nt, nn - base);
+        for (int f = tid; f < total; f += nt) {
+            int lo = 0, hi = cnt - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (s_pre[mid] <= f) lo = mid;
+                else hi = mid - 1;
+            }
+            int x = Acc<D2>::member(g, s_net[lo], f - s_pre[lo]);
+            if (x == w) continue;
+            int c = snap_color(st[x]);
+            if (c >= 0 && c < cap_bits) atomicOr(&bits[c >> 5], 1u << (c & 31));
+        }
+        __syncthreads();
+    }
+}
+
+// smallest color >= from that is not in the bitmap (colors >= cap are free)
+__device__ int block_find_free_up(const uint32_t *bits, int cap_bits, int from, int *s_res)
+{
+    const int nt = blockDim.x, tid = threadIdx.x;
+    if (from >= cap_bits) return from;
+    int nwords = (cap_bits + 31) >> 5;
+    int w0 = from >> 5;
+    for (int base = w0; base < nwords; base += nt) {
+        if (tid == 0) *s_res = 0x7fffffff;
+        __syncthreads();
+        int wi = base + tid;
+        if (wi < nwords) {
+            uint32_t free_bits = ~bits[wi];
+            if (wi == w0) free_bits &= ~0u << (from & 31);
+            if (free_bits) atomicMin(s_res, (wi << 5) + __builtin_ctz(free_bits));
+        }
+        __syncthreads();
+        int r = *s_res;
+        __syncthreads();
+        if (r != 0x7fffffff) return r;
+    }
+    return max(from, nwords << 5);
+}
+
+// largest color <= from that is not in the bitmap, or -1
+__device__ int block_find_free_down(const uint32_t *bits, int cap_bits, int from, int *s_res)
+{
+    const int nt = blockDim.x, tid = threadIdx.x;
+    if (from < 0) return -1;
+    if (from >= cap_bits) return from;
+    int w0 = from >> 5;
+    for (int top = w0; top >= 0; top -= nt) {
+        if (tid == 0) *s_res = -1;
+        __syncthreads();
+        int wi = top - tid;
+        if (wi >= 0) {
+            uint32_t free_bits = ~bits[wi];
+            if (wi == w0) {
+                int sh = from & 31;
+                free_bits &= (sh == 31) ? ~0u : ((2u << sh) - 1u);
+            }
+            if (free_bits) atomicMax(s_res, (wi << 5) + 31 - __builtin_clz(free_bits));
+        }
+        __syncthreads();
+        int r = *s_res;
+        __syncthreads();
+        if (r != -1) return r;
+    }
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// vertex-based coloring, first-fit
+
+// Thread per worklist entry: F(w) restricted to colors 0..63 is the OR of the
+// masks of w's nets; the first clear bit is the first-fit color.  Entries
+// whose 64 low colors are all forbidden are queued for k_vcolor_wide.
+template <bool D2>
+__global__ void k_vcolor_ff(Graph g, const int *W, Ctrl *ctrl, int par, int *st, const uint64_t *mask0,
+                            int *heavy)
+{
+    const int n = ctrl->n_w[par];
+    int local_max = -1;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int w = W[i];
+        uint64_t m = D2 ? mask0[w] : 0ull;
+        int b = g.a_off[w], e = g.a_off[w + 1];
+        for (int k = b; k < e; k++) m |= mask0[g.a_idx[k]];
+        if (~m) {
+            int col = __builtin_ctzll(~m);
+            st[w] = TENT | col;
+            local_max = max(local_max, col);
+        } else {
+            heavy[atomicAdd(&ctrl->n_heavy, 1)] = w;
+        }
+    }
+    local_max = wave_max(local_max);
+    if (lane_id() == 0 && local_max >= 0) atomicMax(&ctrl->max_color, local_max);
+}
+
+// Block per queued vertex: full forbidden bitmap in LDS, first clear bit.
+template <bool D2>
+__global__ void k_vcolor_wide(Graph g, const int *heavy, Ctrl *ctrl, int *st, int lds_bits)
+{
+    extern __shared__ uint32_t dyn[];
+    __shared__ int s_net[1025], s_pre[1025], s_scan[20], s_res;
+    const int nh = ctrl->n_heavy;
+    if (nh == 0) return;
+    int cap = ctrl->max_color + 2;
+    if (cap > lds_bits) {
+        if (threadIdx.x == 0 && blockIdx.x == 0) atomicOr(&ctrl->error, ERR_COLOR_CAP);
+        return;
+    }
+    int nwords = (cap + 31) >> 5;
+    for (int h = blockIdx.x; h < nh; h += gridDim.x) {
+        int w = heavy[h];
+        for (int i = threadIdx.x; i < nwords; i += blockDim.x) dyn[i] = 0;
+        __syncthreads();
+        build_forbidden<D2>(g, st, w, dyn, cap, s_net, s_pre, s_scan);
+        int col = block_find_free_up(dyn, cap, 0, &s_res);
+        if (threadIdx.x == 0) {
+            st[w] = TENT | col;
+            atomicMax(&ctrl->max_color, col);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// vertex-based coloring with the balancing policies (Algorithms 11 and 12)
+
+struct PolicyState {
+    int col_max, col_next;
+};
+
+__device__ __forceinline__ uint64_t bits_upto(int a)  // bits 0..a
+{
+    return a >= 63 ? ~0ull : ((1ull << (a + 1)) - 1ull);
+}
+
+// Resolve one pick from the 64 low forbidden bits alone; false when the
+// answer may depend on colors >= 64.
+__device__ __forceinline__ bool pick_low(int policy, uint64_t m, int rank, const PolicyState &s, int *col)
+{
+    uint64_t fr = ~m;
+    if (policy == 1 && (rank & 1) == 0) {  // B1, even rank
+        if (s.col_max > 63) return false;
+        uint64_t low = fr & bits_upto(s.col_max);
+        if (low) {
+            *col = 63 - __builtin_clzll(low);
+            return true;
+        }
+        uint64_t high = fr & ~bits_upto(s.col_max);
+        if (high) {
+            *col = __builtin_ctzll(high);
+            return true;
+        }
+        return false;
+    }
+    if (policy == 2) {  // B2
+        if (s.col_next > 63) return false;
+        uint64_t z = fr & (~0ull << s.col_next);
+        if (!z) return false;
+        int c = __builtin_ctzll(z);
+        if (c > s.col_max) c = __builtin_ctzll(fr);
+        *col = c;
+        return true;
+    }
+    // first-fit (also B1 with an odd rank)
+    if (!fr) return false;
+    *col = __builtin_ctzll(fr);
+    return true;
+}
+
+__device__ __forceinline__ int pick_bitmap(int policy, const uint32_t *bits, int cap, int rank, const PolicyState &s,
+                                           int *s_res)
+{
+    if (policy == 1 && (rank & 1) == 0) {
+        int c = block_find_free_down(bits, cap, s.col_max, s_res);
+        if (c == -1) c = block_find_free_up(bits, cap, s.col_max + 1, s_res);
+        return c;
+    }
+    if (policy == 2) {
+        int c = block_find_free_up(bits, cap, s.col_next, s_res);
+        if (c > s.col_max) c = block_find_free_up(bits, cap, 0, s_res);
+        return c;
+    }
+    return block_find_free_up(bits, cap, 0, s_res);
+}
+
+__device__ __forceinline__ void policy_update(int policy, int col, PolicyState &s)
+{
+    s.col_max = max(s.col_max, col);
+    if (policy == 2) s.col_next = min(col + 1, s.col_max / 3 + 1);
+}
+
+// One wave (block of 64) per chunk of `chunk` consecutive worklist entries;
+// the policy state runs through the chunk in worklist order.  Lanes compute
+// the low masks of 64 entries at a time; an entry whose pick needs colors
+// >= 64 builds its full forbidden bitmap with the whole wave.
+template <bool D2>
+__global__ void __launch_bounds__(64) k_vcolor_chunked(Graph g, const int *W, Ctrl *ctrl, int par, int *st,
+                                                        const uint64_t *mask0, int policy, int chunk, int lds_bits)
+{
+    extern __shared__ uint32_t dyn[];
+    __shared__ int s_net[65], s_pre[65], s_scan[4], s_res;
+    const int n = ctrl->n_w[par];
+    const int nchunks = (n + chunk - 1) / chunk;
+    const int lane = threadIdx.x;
+    for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        PolicyState s = {0, 0};
+        int lo = ch * chunk, hi = min(lo + chunk, n);
+        int cap = -1;
+        for (int sub = lo; sub < hi; sub += WAVE) {
+            int i = sub + lane;
+            int w = -1;
+            uint64_t m = 0;
+            if (i < hi) {
+                w = W[i];
+                m = D2 ? mask0[w] : 0ull;
+                for (int k = g.a_off[w]; k < g.a_off[w + 1]; k++) m |= mask0[g.a_idx[k]];
+            }
+            int cnt = min(WAVE, hi - sub);
+            for (int j = 0; j < cnt; j++) {
+                int wj = __shfl(w, j);
+                uint64_t mj = shfl64(m, j);
+                int col;
+                if (!pick_low(policy, mj, wj, s, &col)) {
+                    if (cap < 0) cap = ctrl->max_color + 2;
+                    if (cap > lds_bits) {
+                        if (lane == 0) atomicOr(&ctrl->error, ERR_COLOR_CAP);
+                        return;
+                    }
+                    int nwords = (cap + 31) >> 5;
+                    for (int q = lane; q < nwords; q += WAVE) dyn[q] = 0;
+                    __syncthreads();
+                    build_forbidden<D2>(g, st, wj, dyn, cap, s_net, s_pre, s_scan);
+                    col = pick_bitmap(policy, dyn, cap, wj, s, &s_res);
+                }
+                policy_update(policy, col, s);
+                if (lane == 0) {
+                    st[wj] = TENT | col;
+                    atomicMax(&ctrl->max_color, col);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// net-based coloring (Algorithm 8; Algorithm 9 in distance-2 mode)
+
+// Thread per net of at most SMALL_NET members: the forbidden colors below
+// |vtxs(v)| fit in one 64-bit word; uncolored members in adjacency order take
+// the free colors from |vtxs(v)| - 1 downwards; only the owner net writes.
+template <bool D2>
+__global__ void k_ncolor_small(Graph g, int *st, const int *owner, Ctrl *ctrl)
+{
+    int local_max = -1;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n_b; v += gridDim.x * blockDim.x) {
+        int sz = Acc<D2>::size(g, v);
+        if (sz == 0 || sz > SMALL_NET) continue;
+        uint64_t F = 0;
+        int nun = 0;
+        for (int k = 0; k < sz; k++) {
+            int c = snap_color(st[Acc<D2>::member(g, v, k)]);
+            if (c < 0) {
+                nun++;
+            } else if (c < sz) {
+                if ((F >> c) & 1ull) atomicOr(&ctrl->error, ERR_NET_DUP);
+                F |= 1ull << c;
+            }
+        }
+        if (nun == 0) continue;
+        int col = sz - 1;
+        for (int k = 0; k < sz; k++) {
+            int x = Acc<D2>::member(g, v, k);
+            if (snap_color(st[x]) >= 0) continue;
+            while (col >= 0 && ((F >> col) & 1ull)) col--;
+            if (col < 0) atomicOr(&ctrl->error, ERR_REVERSE_NEG);
+            if (owner[x] == v) {
+                st[x] = TENT | col;
+                local_max = max(local_max, col);
+            }
+            col--;
+        }
+    }
+    local_max = wave_max(local_max);
+    if (lane_id() == 0 && local_max >= 0) atomicMax(&ctrl->max_color, local_max);
+}
+
+// Block per net larger than SMALL_NET.  LDS: forbidden bitmap of |vtxs(v)|
+// bits and the suffix counts of its free colors per 32-bit word; the p-th
+// uncolored member (adjacency order) takes the p-th free color counted from
+// the top.
+template <bool D2>
+__global__ void k_ncolor_big(Graph g, int *st, const int *owner, const int *big, const int *n_big_p, Ctrl *ctrl,
+                             int lds_words)
+{
+    extern __shared__ uint32_t dyn[];
+    __shared__ int s_scan[20];
+    const int n_big = *n_big_p;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int bi = blockIdx.x; bi < n_big; bi += gridDim.x) {
+        int v = big[bi];
+        int sz = Acc<D2>::size(g, v);
+        int nwords = (sz + 31) >> 5;
+        if (2 * nwords + 1 > lds_words) {
+            if (tid == 0) atomicOr(&ctrl->error, ERR_NET_TOO_BIG);
+            continue;
+        }
+        uint32_t *bits = dyn;
+        int *suf = (int *)(dyn + nwords);
+        for (int i = tid; i < nwords; i += nt) bits[i] = 0;
+        __syncthreads();
+        int nun = 0;
+        for (int k = tid; k < sz; k += nt) {
+            int c = snap_color(st[Acc<D2>::member(g, v, k)]);
+            if (c < 0) nun++;
+            else if (c < sz) {
+                uint32_t old = atomicOr(&bits[c >> 5], 1u << (c & 31));
+                if (old & (1u << (c & 31))) atomicOr(&ctrl->error, ERR_NET_DUP);
+            }
+        }
+        nun = block_sum(nun, s_scan);
+        if (nun == 0) continue;
+        // free colors of word i, restricted to [0, sz); suffix sums from the top word
+        int carry = 0;
+        for (int top = nwords - 1; top >= 0; top -= nt) {
+            int wi = top - tid;
+            int cnt = 0;
+            if (wi >= 0) {
+                uint32_t fr = ~bits[wi];
+                int rem = sz - (wi << 5);
+                if (rem < 32) fr &= (1u << rem) - 1u;
+                cnt = __builtin_popcount(fr);
+            }
+            int total;
+            int ex = block_excl_scan(cnt, s_scan, &total);
+            if (wi >= 0) suf[wi] = carry + ex + cnt;   // free colors in words >= wi
+            carry += total;
+        }
+        if (tid == 0) suf[nwords] = 0;
+        __syncthreads();
+        int local_max = -1;
+        int base = 0;
+        for (int k0 = 0; k0 < sz; k0 += nt) {
+            int k = k0 + tid;
+            int x = k < sz ? Acc<D2>::member(g, v, k) : -1;
+            int unc = (x >= 0 && snap_color(st[x]) < 0) ? 1 : 0;
+            int total;
+            int p = base + block_excl_scan(unc, s_scan, &total);
+            if (unc && owner[x] == v) {
+                // word wi with suf[wi + 1] <= p < suf[wi]
+                int lo = 0, hi = nwords - 1;
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (suf[mid] > p) lo = mid;
+                    else hi = mid - 1;
+                }
+                int q = p - suf[lo + 1];
+                uint32_t fr = ~bits[lo];
+                int rem = sz - (lo << 5);
+                if (rem < 32) fr &= (1u << rem) - 1u;
+                if (p >= suf[0]) {
+                    atomicOr(&ctrl->error, ERR_REVERSE_NEG);
+                } else {
+                    for (int t = 0; t < q; t++) fr &= ~(1u << (31 - __builtin_clz(fr)));
+                    int col = (lo << 5) + 31 - __builtin_clz(fr);
+                    st[x] = TENT | col;
+                    local_max = max(local_max, col);
+                }
+            }
+            base += total;
+        }
+        local_max = block_max(local_max, s_scan);
+        if (tid == 0 && local_max >= 0) atomicMax(&ctrl->max_color, local_max);
+        __syncthreads();
+    }
+}
+
+// Worklist vertices without any net take color 0 (every policy's pick for an
+// empty forbidden set) in net-based rounds.
+__global__ void k_ncolor_isolated(Graph g, const int *W, Ctrl *ctrl, int par, int *st)
+{
+    const int n = ctrl->n_w[par];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int w = W[i];
+        if (g.a_off[w + 1] == g.a_off[w]) st[w] = TENT | 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// removal: per net, every holder of a color except its lowest-ranked one loses
+
+// members of a net in ascending rank; distance-2 merges the center into the
+// sorted neighbour list
+template <bool D2>
+struct RankIter {
+    const int *idx;
+    int pos, end, center;
+    bool center_pending;
+    __device__ RankIter(const Graph &g, int v)
+    {
+        idx = g.b_idx;
+        pos = g.b_off[v];
+        end = g.b_off[v + 1];
+        center = v;
+        center_pending = D2;
+    }
+    __device__ __forceinline__ bool next(int *x)
+    {
+        int nx = pos < end ? idx[pos] : 0x7fffffff;
+        if (D2 && center_pending && center < nx) {
+            center_pending = false;
+            *x = center;
+            return true;
+        }
+        if (pos < end) {
+            *x = nx;
+            pos++;
+            return true;
+        }
+        return false;
+    }
+};
+
+// Thread per net of at most SMALL_NET members, scanned in rank order: the
+// first holder of a color keeps it.  Colors below 64 use a bit set; larger
+// colors are compared pairwise against earlier members.  With tent_only, only
+// proposed colors take part (after a vertex-based round no colored vertex can
+// clash).
+template <bool D2>
+__global__ void k_conflict_small(Graph g, const int *st, uint8_t *lose, int tent_only)
+{
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n_b; v += gridDim.x * blockDim.x) {
+        int sz = Acc<D2>::size(g, v);
+        if (sz < 2 || sz > SMALL_NET) continue;
+        uint64_t seen = 0;
+        bool wide = false;
+        RankIter<D2> it(g, v);
+        int x;
+        while (it.next(&x)) {
+            int s = st[x];
+            if (tent_only && !(s >= 0 && (s & TENT))) continue;
+            int c = cur_color(s);
+            if (c < 0) continue;
+            if (c < 64) {
+                if ((seen >> c) & 1ull) lose[x] = 1;
+                seen |= 1ull << c;
+            } else {
+                wide = true;
+            }
+        }
+        if (!wide) continue;
+        RankIter<D2> outer(g, v);
+        while (outer.next(&x)) {
+            int s = st[x];
+            if (tent_only && !(s >= 0 && (s & TENT))) continue;
+            int c = cur_color(s);
+            if (c < 64) continue;
+            RankIter<D2> inner(g, v);
+            int y;
+            while (inner.next(&y) && y < x) {
+                int t = st[y];
+                if (tent_only && !(t >= 0 && (t & TENT))) continue;
+                if (cur_color(t) == c) {
+                    lose[x] = 1;
+                    break;
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ unsigned hash_color(int c) { return (unsigned)c * 2654435761u; }
+
+// Block per net larger than SMALL_NET.  Nets up to HASH_MAX members use an
+// LDS hash color -> lowest-ranked holder; larger nets sweep the colors in
+// windows of WIN_COLORS with a direct-mapped table.
+template <bool D2>
+__global__ void k_conflict_big(Graph g, const int *st, uint8_t *lose, const int *big, const int *n_big_p,
+                               Ctrl *ctrl, int tent_only)
+{
+    extern __shared__ int sh[];
+    const int n_big = *n_big_p;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int bi = blockIdx.x; bi < n_big; bi += gridDim.x) {
+        int v = big[bi];
+        int sz = Acc<D2>::size(g, v);
+        if (sz <= HASH_MAX) {
+            int cap = 64;
+            while (cap < 2 * sz) cap <<= 1;
+            int *keys = sh, *minr = sh + cap;
+            for (int i = tid; i < cap; i += nt) {
+                keys[i] = -1;
+                minr[i] = 0x7fffffff;
+            }
+            __syncthreads();
+            for (int k = tid; k < sz; k += nt) {
+                int x = Acc<D2>::member(g, v, k);
+                int s = st[x];
+                if (tent_only && !(s >= 0 && (s & TENT))) continue;
+                int c = cur_color(s);
+                if (c < 0) continue;
+                unsigned h = hash_color(c) & (cap - 1);
+                for (;;) {
+                    int prev = atomicCAS(&keys[h], -1, c);
+                    if (prev == -1 || prev == c) {
+                        atomicMin(&minr[h], x);
+                        break;
+                    }
+                    h = (h + 1) & (cap - 1);
+                }
+            }
+            __syncthreads();
+            for (int k = tid; k < sz; k += nt) {
+                int x = Acc<D2>::member(g, v, k);
+                int s = st[x];
+                if (tent_only && !(s >= 0 && (s & TENT))) continue;
+                int c = cur_color(s);
+                if (c < 0) continue;
+                unsigned h = hash_color(c) & (cap - 1);
+                while (keys[h] != c) h = (h + 1) & (cap - 1);
+                if (minr[h] != x) lose[x] = 1;
+            }
+            __syncthreads();
+        } else {
+            int maxc = ctrl->max_color;
+            for (int base = 0; base <= maxc; base += WIN_COLORS) {
+                for (int i = tid; i < WIN_COLORS; i += nt) sh[i] = 0x7fffffff;
+                __syncthreads();
+                for (int k = tid; k < sz; k += nt) {
+                    int x = Acc<D2>::member(g, v, k);
+                    int s = st[x];
+                    if (tent_only && !(s >= 0 && (s & TENT))) continue;
+                    int c = cur_color(s) - base;
+                    if (c >= 0 && c < WIN_COLORS) atomicMin(&sh[c], x);
+                }
+                __syncthreads();
+                for (int k = tid; k < sz; k += nt) {
+                    int x = Acc<D2>::member(g, v, k);
+                    int s = st[x];
+                    if (tent_only && !(s >= 0 && (s & TENT))) continue;
+                    int c = cur_color(s) - base;
+                    if (c >= 0 && c < WIN_COLORS && sh[c] != x) lose[x] = 1;
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// apply + compaction
+
+// Over the worklist (list != nullptr) or over every vertex (list == nullptr,
+// after a net-based round that may evict colored vertices): losers become
+// uncolored, winners keep their proposal and, when the masks are maintained
+// incrementally (update_masks), set its bit in the masks of their nets.
+// Writes the number of uncolored entries of each tile.
+template <bool D2>
+__global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, Ctrl *ctrl, int par, int *st,
+                                                      uint8_t *lose, uint64_t *mask0, int *tile_count,
+                                                      RoundRec *rec, int round, int update_masks)
+{
+    __shared__ int s_scan[8];
+    const int n = list ? ctrl->n_w[par] : g.n_a;
+    const int ntiles = (n + TILE - 1) / TILE;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctrl->n_w[par ^ 1] = 0;
+        ctrl->n_heavy = 0;
+    }
+    int evicted = 0, mx = -1;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int cnt = 0;
+        for (int k = 0; k < TILE / TILE_BLOCK; k++) {
+            int i = t * TILE + k * TILE_BLOCK + threadIdx.x;
+            if (i >= n) break;
+            int u = list ? list[i] : i;
+            int s = st[u];
+            if (lose[u]) {
+                lose[u] = 0;
+                if (s >= 0 && !(s & TENT)) evicted++;
+                st[u] = -1;
+                cnt++;
+            } else if (s < 0) {
+                cnt++;
+            } else {
+                int col = s & COLOR_MASK;
+                if (s & TENT) {
+                    st[u] = col;
+                    if (update_masks && col < 64) {
+                        uint64_t bit = 1ull << col;
+                        if (D2) atomicOr((unsigned long long *)&mask0[u], (unsigned long long)bit);
+                        for (int k2 = g.a_off[u]; k2 < g.a_off[u + 1]; k2++)
+                            atomicOr((unsigned long long *)&mask0[g.a_idx[k2]], (unsigned long long)bit);
+                    }
+                }
+                mx = max(mx, col);
+            }
+        }
+        cnt = block_sum(cnt, s_scan);
+        if (threadIdx.x == 0) tile_count[t] = cnt;
+    }
+    evicted = wave_sum(evicted);
+    mx = wave_max(mx);
+    if (lane_id() == 0) {
+        if (evicted) atomicAdd(&rec[round].evicted, evicted);
+        if (mx >= 0) atomicMax(&ctrl->pad[0], mx);
+    }
+}
+
+// Stable scatter of the uncolored entries into the next worklist.  Tile t's
+// offset is the sum of the counts of tiles < t; inside a tile, entries are
+// ranked by wave ballots in index order.
+// With count_round, a round whose worklist was empty leaves everything as is;
+// otherwise the round is counted and its record completed.
+__global__ void __launch_bounds__(TILE_BLOCK) k_compact(const int *list, int n_static, Ctrl *ctrl, int par,
+                                                        const int *st, const int *tile_count, int *out,
+                                                        RoundRec *rec, int round, int mode, int count_round)
+{
+    constexpr int KS = TILE / TILE_BLOCK;
+    constexpr int NWV = TILE_BLOCK / WAVE;
+    __shared__ int s_cnt[KS * NWV + 1];
+    __shared__ int s_scan[8];
+    if (count_round && ctrl->n_w[par] == 0) return;
+    const int n = list ? ctrl->n_w[par] : n_static;
+    const int ntiles = (n + TILE - 1) / TILE;
+    const int lane = lane_id(), wid = threadIdx.x / WAVE;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int pre = 0;
+        for (int j = threadIdx.x; j < t; j += TILE_BLOCK) pre += tile_count[j];
+        pre = block_sum(pre, s_scan);
+        int u_k[KS];
+        uint64_t bal[KS];
+        for (int k = 0; k < KS; k++) {
+            int i = t * TILE + k * TILE_BLOCK + threadIdx.x;
+            int u = -1;
+            bool f = false;
+            if (i < n) {
+                u = list ? list[i] : i;
+                f = st[u] < 0;
+            }
+            u_k[k] = u;
+            bal[k] = __ballot(f);
+            if (lane == 0) s_cnt[k * NWV + wid] = __builtin_popcountll(bal[k]);
+        }
+        __syncthreads();
+        if (threadIdx.x < WAVE) {
+            int c = threadIdx.x < KS * NWV ? s_cnt[threadIdx.x] : 0;
+            int inc = wave_incl_scan(c);
+            if (threadIdx.x < KS * NWV) s_cnt[threadIdx.x] = inc - c;
+            if (threadIdx.x == KS * NWV - 1) s_cnt[KS * NWV] = inc;
+        }
+        __syncthreads();
+        uint64_t below = lane ? (~0ull >> (WAVE - lane)) : 0ull;
+        for (int k = 0; k < KS; k++) {
+            if ((bal[k] >> lane) & 1ull) {
+                int r = __builtin_popcountll(bal[k] & below);
+                out[pre + s_cnt[k * NWV + wid] + r] = u_k[k];
+            }
+        }
+        if (t == ntiles - 1 && threadIdx.x == 0) {
+            int total = pre + s_cnt[KS * NWV];
+            ctrl->n_w[par ^ 1] = total;
+            if (count_round) {
+                ctrl->rounds += 1;
+                RoundRec &R = rec[round];
+                R.mode = mode;
+                R.w = ctrl->n_w[par];
+                R.losers = total;
+                R.max_color = ctrl->pad[0];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// counts of uncolored entries per tile over all vertices (resume set-up)
+__global__ void __launch_bounds__(TILE_BLOCK) k_count_uncolored(const int *st, int n, int *tile_count)
+{
+    __shared__ int s_scan[8];
+    const int ntiles = (n + TILE - 1) / TILE;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int cnt = 0;
+        for (int k = 0; k < TILE / TILE_BLOCK; k++) {
+            int i = t * TILE + k * TILE_BLOCK + threadIdx.x;
+            if (i < n && st[i] < 0) cnt++;
+        }
+        cnt = block_sum(cnt, s_scan);
+        if (threadIdx.x == 0) tile_count[t] = cnt;
+    }
+}
+
+__global__ void k_set_max_final(Ctrl *ctrl, int v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctrl->pad[0] = v;
+}
+
+// ---------------------------------------------------------------------------
+// color-set statistics
+
+__global__ void k_hist(const int *colors, long n, int *count, int ncolors)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        int c = colors[i];
+        if (c >= 0 && c < ncolors) atomicAdd(&count[c], 1);
+    }
+}
+
+__global__ void k_colors_max(const int *colors, long n, int *out)
+{
+    int local = -1;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        local = max(local, colors[i]);
+    local = wave_max(local);
+    if (lane_id() == 0) atomicMax(out, local);
+}
+
+// single block: reduce the histogram into the statistics
+__global__ void k_hist_reduce(const int *count, int ncolors, long long *out_i, double *out_d)
+{
+    __shared__ long long s_nd[16], s_min[16], s_max[16], s_sum[16];
+    __shared__ double s_sq[16];
+    const int tid = threadIdx.x, wid = tid / WAVE, lane = lane_id(), nw = blockDim.x / WAVE;
+    long long nd = 0, mn = 0x7fffffffffffffffll, mx = 0, sum = 0;
+    for (int c = tid; c < ncolors; c += blockDim.x) {
+        long long k = count[c];
+        if (k == 0) continue;
+        nd++;
+        mn = k < mn ? k : mn;
+        mx = k > mx ? k : mx;
+        sum += k;
+    }
+    for (int d = WAVE / 2; d > 0; d >>= 1) {
+        nd += __shfl_xor(nd, d);
+        long long o = __shfl_xor(mn, d);
+        mn = o < mn ? o : mn;
+        o = __shfl_xor(mx, d);
+        mx = o > mx ? o : mx;
+        sum += __shfl_xor(sum, d);
+    }
+    if (lane == 0) {
+        s_nd[wid] = nd;
+        s_min[wid] = mn;
+        s_max[wid] = mx;
+        s_sum[wid] = sum;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int i = 1; i < nw; i++) {
+            s_nd[0] += s_nd[i];
+            s_min[0] = s_min[i] < s_min[0] ? s_min[i] : s_min[0];
+            s_max[0] = s_max[i] > s_max[0] ? s_max[i] : s_max[0];
+            s_sum[0] += s_sum[i];
+        }
+    }
+    __syncthreads();
+    const double mean = s_nd[0] ? (double)s_sum[0] / (double)s_nd[0] : 0.0;
+    double sq = 0.0;
+    for (int c = tid; c < ncolors; c += blockDim.x) {
+        long long k = count[c];
+        if (k == 0) continue;
+        double d = (double)k - mean;
+        sq += d * d;
+    }
+    for (int d = WAVE / 2; d > 0; d >>= 1) sq += __shfl_xor(sq, d);
+    if (lane == 0) s_sq[wid] = sq;
+    __syncthreads();
+    if (tid == 0) {
+        double tot = 0.0;
+        for (int i = 0; i < nw; i++) tot += s_sq[i];
+        long long ndist = s_nd[0];
+        double var = ndist ? tot / (double)ndist : 0.0;
+        out_i[0] = ndist;
+        out_i[1] = ncolors - 1;
+        out_i[2] = ndist ? s_min[0] : 0;
+        out_i[3] = s_max[0];
+        out_i[4] = (long long)ncolors - ndist;
+        out_d[0] = mean;
+        out_d[1] = sqrt(var);
+    }
+}
+
+}  // namespace bgpc
