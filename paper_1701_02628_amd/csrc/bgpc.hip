@@ -24,7 +24,7 @@ using namespace bgpc;
 
 namespace {
 
-constexpr int LOOKAHEAD = 12;
+constexpr int LOOKAHEAD = 4;
 
 struct DevInfo {
     int cus = 256;
@@ -139,19 +139,6 @@ struct HostProgress {
     }
 };
 
-__global__ void k_publish(Ctrl *ctrl, int par_next, int round_issued, int *host)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int nw = ctrl->n_w[par_next];
-        int err = ctrl->error;
-        __atomic_store_n(&host[1], nw, __ATOMIC_RELAXED);
-        __atomic_store_n(&host[2], err, __ATOMIC_RELAXED);
-        __threadfence_system();
-        __atomic_store_n(&host[0], round_issued, __ATOMIC_RELEASE);
-        __threadfence_system();
-    }
-}
-
 struct RunArgs {
     Graph g;
     bool d2;
@@ -189,6 +176,7 @@ int run(const RunArgs &a)
                    + aligned(n_a + 1, 1)              // lose
                    + aligned(n_b + 1, 8)              // mask0
                    + aligned(n_b + 1, 4)              // big net list
+                   + aligned(n_b + 1, 1)              // done nets
                    + aligned(max_tiles, 4)            // tile counts
                    + aligned(1, sizeof(Ctrl))         //
                    + aligned(8, 4)                    // shape figures
@@ -203,6 +191,7 @@ int run(const RunArgs &a)
     uint8_t *lose = ar.take<uint8_t>(n_a + 1);
     uint64_t *mask0 = ar.take<uint64_t>(n_b + 1);
     int *big = ar.take<int>(n_b + 1);
+    uint8_t *done_net = ar.take<uint8_t>(n_b + 1);
     int *tile_count = ar.take<int>(max_tiles);
     Ctrl *ctrl = ar.take<Ctrl>(1);
     int *shape = ar.take<int>(8);
@@ -261,6 +250,7 @@ int run(const RunArgs &a)
 
         // ---- initial state
         k_fill_u8<<<g_a, nthr, 0, s>>>(lose, 0, n_a + 1);
+        k_fill_u8<<<g_b, nthr, 0, s>>>(done_net, 0, n_b + 1);
         if (!resume) {
             k_fill_i32<<<g_a, nthr, 0, s>>>(st, -1, n_a);
             k_iota<<<g_a, nthr, 0, s>>>(W0, n_a);
@@ -283,7 +273,7 @@ int run(const RunArgs &a)
             const int gt = grid_for(max_tiles, 1, di.cus * 4);
             k_count_uncolored<<<gt, TILE_BLOCK, 0, s>>>(st, n_a, tile_count);
             // identity compaction: the uncolored vertices in id order become W0
-            k_compact<<<gt, TILE_BLOCK, 0, s>>>(nullptr, n_a, ctrl, 1, st, tile_count, W0, rec, 0, 0, 0);
+            k_compact<<<gt, TILE_BLOCK, 0, s>>>(nullptr, n_a, ctrl, 1, st, tile_count, W0, rec, 0, 0, 0, nullptr);
         }
         LAUNCH_CHECK();
 
@@ -291,6 +281,7 @@ int run(const RunArgs &a)
             prog.h[0] = -1;
             prog.h[1] = -1;
             prog.h[2] = 0;
+            prog.h[3] = -1;
         }
 
         // ---- rounds
@@ -299,6 +290,16 @@ int run(const RunArgs &a)
         const int g_chunk = grid_for((n_a + chunk - 1) / chunk, 1, di.cus * 16);
         bool done = false;
         bool use_prog = prog.h && prog.d;
+        int net_round_issued = -1;   // last net-based round queued
+        // one wave per 64 items, grids a multiple of 8 (XCD-aware remap)
+        auto grid64 = [&](long items) {
+            long gsz = (items + 63) / 64;
+            gsz = std::min<long>(gsz, (long)di.cus * 32);
+            gsz = std::max<long>(8, (gsz + 7) / 8 * 8);
+            return (int)gsz;
+        };
+        const int g_w64a = grid64(n_a);
+        const int g_w64b = grid64(n_b);
         while (!done && issued < max_rounds) {
             // keep at most LOOKAHEAD rounds in flight beyond the last one seen
             if (use_prog) {
@@ -347,37 +348,54 @@ int run(const RunArgs &a)
             const int rid = start_round + r;
             const bool net_mode = rid >= 0 && rid < 64 && ((o.net_color_mask >> rid) & 1ull);
             int *Wc = Wb[par], *Wn = Wb[par ^ 1];
+            int *host = use_prog ? prog.d : nullptr;
             if (net_mode) {
                 k_ncolor_small<D2><<<g_b, nthr, 0, s>>>(g, st, owner, ctrl);
-                k_ncolor_big<D2><<<g_big, 256, ncolor_words * 4, s>>>(g, st, owner, big, &shape[1], ctrl,
-                                                                       ncolor_words);
+                if (n_big) k_ncolor_big<D2><<<g_big, 256, ncolor_words * 4, s>>>(g, st, owner, big, &shape[1], ctrl,
+                                                                                 ncolor_words);
                 if (!D2) k_ncolor_isolated<<<g_a, nthr, 0, s>>>(g, Wc, ctrl, par, st);
-                k_conflict_small<D2><<<g_b, nthr, 0, s>>>(g, st, lose, 0);
-                k_conflict_big<D2><<<g_big, 256, conflict_bytes, s>>>(g, st, lose, big, &shape[1], ctrl, 0);
+                k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 0);
+                if (n_big)
+                    k_conflict_big<D2><<<g_big, 256, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 0);
                 const bool full = r > 0 || resume;
                 if (full) {
                     k_set_max_final<<<1, 64, 0, s>>>(ctrl, -1);
                     k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, nullptr, ctrl, par, st, lose, mask0, tile_count, rec, rr, 0);
-                    k_compact<<<gt, TILE_BLOCK, 0, s>>>(nullptr, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 1, 1);
+                    k_compact<<<gt, TILE_BLOCK, 0, s>>>(nullptr, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 1, 1, host);
                     k_mask_rebuild<D2><<<g_b, nthr, 0, s>>>(g, st, mask0);
+                    k_fill_u8<<<g_b, nthr, 0, s>>>(done_net, 0, n_b + 1);
                 } else {
                     k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1);
-                    k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 1, 1);
+                    k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 1, 1, host);
                 }
+                net_round_issued = r;
             } else {
                 if (policy == BGPC_FIRST_FIT) {
-                    k_vcolor_ff<D2><<<g_a, nthr, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy);
-                    k_vcolor_wide<D2><<<di.cus * 2, 256, wide_bytes, s>>>(g, heavy, ctrl, st, lds_bits);
+                    k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy);
+                    // the wide path can only be needed once colors 0..63 all exist:
+                    // a vertex-based first-fit round raises the largest color by at
+                    // most one, a net-based round keeps it below the largest net
+                    bool need_wide = true;
+                    if (use_prog) {
+                        int seen = prog.h[0], mc = prog.h[3];
+                        if (seen >= 0 && net_round_issued <= seen) {
+                            long bound = (long)mc + (r - 1 - seen);
+                            need_wide = bound >= 63;
+                        } else if (seen < 0 && !resume && net_round_issued < 0) {
+                            need_wide = r >= 63;
+                        }
+                    }
+                    if (need_wide) k_vcolor_wide<D2><<<di.cus * 2, 256, wide_bytes, s>>>(g, heavy, ctrl, st, lds_bits);
                 } else {
                     k_vcolor_chunked<D2><<<g_chunk, 64, wide_bytes, s>>>(g, Wc, ctrl, par, st, mask0, policy, chunk,
                                                                           lds_bits);
                 }
-                k_conflict_small<D2><<<g_b, nthr, 0, s>>>(g, st, lose, 1);
-                k_conflict_big<D2><<<g_big, 256, conflict_bytes, s>>>(g, st, lose, big, &shape[1], ctrl, 1);
+                k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1);
+                if (n_big)
+                    k_conflict_big<D2><<<g_big, 256, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 1);
                 k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1);
-                k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 0, 1);
+                k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 0, 1, host);
             }
-            if (use_prog) k_publish<<<1, 64, 0, s>>>(ctrl, par ^ 1, r, prog.d);
             LAUNCH_CHECK();
             issued++;
         }

@@ -24,6 +24,26 @@ constexpr int TILE = 2048;          // worklist entries per compaction tile
 constexpr int TILE_BLOCK = 256;     // threads of the apply / compaction blocks
 constexpr int HASH_MAX = 4096;      // big nets up to this size use an LDS hash
 constexpr int WIN_COLORS = 16384;   // color window of the largest nets
+constexpr int STAGE = 2048;         // net-list entries staged in LDS per wave
+
+// Blocks are dealt to the 8 XCDs round-robin.  With a grid that is a multiple
+// of 8, logical block (x * nb/8 + k) runs on XCD x, so each XCD walks one
+// contiguous stretch of items and the neighbourhoods it gathers stay in its
+// own L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nb)
+{
+    return (nb & 7) ? bid : (bid & 7) * (nb >> 3) + (bid >> 3);
+}
+
+// largest j in [0, 64) with pre[j] <= f, for non-decreasing pre[] with pre[0] <= f
+__device__ __forceinline__ int row_of(const int *pre, int f)
+{
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+        if (pre[lo + step] <= f) lo += step;
+    return lo;
+}
 
 // ---------------------------------------------------------------------------
 // setup
@@ -290,30 +310,88 @@ __device__ int block_find_free_down(const uint32_t *bits, int cap_bits, int from
 // ---------------------------------------------------------------------------
 // vertex-based coloring, first-fit
 
-// Thread per worklist entry: F(w) restricted to colors 0..63 is the OR of the
-// masks of w's nets; the first clear bit is the first-fit color.  Entries
-// whose 64 low colors are all forbidden are queued for k_vcolor_wide.
+// One wave per 64 worklist entries: F(w) restricted to colors 0..63 is the OR
+// of the masks of w's nets.  The wave first copies the 64 rows of nets(w)
+// into LDS as one flat range (coalesced index loads, four in flight per
+// lane), then every lane ORs the masks of its own row, eight gathers in
+// flight.  The first clear bit is the first-fit color.  Entries whose 64 low
+// colors are all forbidden are queued for k_vcolor_wide.
 template <bool D2>
-__global__ void k_vcolor_ff(Graph g, const int *W, Ctrl *ctrl, int par, int *st, const uint64_t *mask0,
-                            int *heavy)
+__global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *ctrl, int par, int *st,
+                                                  const uint64_t *mask0, int *heavy)
 {
+    __shared__ int s_pre[65], s_beg[64];
+    __shared__ int s_idx[STAGE];
     const int n = ctrl->n_w[par];
+    const int lane = threadIdx.x, nb = gridDim.x, lb = xcd_remap(blockIdx.x, nb);
     int local_max = -1;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        int w = W[i];
-        uint64_t m = D2 ? mask0[w] : 0ull;
-        int b = g.a_off[w], e = g.a_off[w + 1];
-        for (int k = b; k < e; k++) m |= mask0[g.a_idx[k]];
-        if (~m) {
-            int col = __builtin_ctzll(~m);
-            st[w] = TENT | col;
-            local_max = max(local_max, col);
-        } else {
-            heavy[atomicAdd(&ctrl->n_heavy, 1)] = w;
+    for (int base = lb * 64; base < n; base += nb * 64) {
+        int i = base + lane;
+        int w = i < n ? W[i] : -1;
+        int beg = 0, d = 0;
+        uint64_t m = 0;
+        if (w >= 0) {
+            beg = g.a_off[w];
+            d = g.a_off[w + 1] - beg;
+            if (D2) m = mask0[w];
         }
+        int incl = wave_incl_scan(d);
+        int total = __shfl(incl, 63);
+        int pre = incl - d;
+        s_pre[lane] = pre;
+        s_beg[lane] = beg;
+        __syncthreads();
+        if (total <= STAGE) {
+            for (int f0 = 0; f0 < total; f0 += 1024) {
+                int v[16];
+#pragma unroll
+                for (int q = 0; q < 16; q++) {
+                    int f = f0 + q * 64 + lane;
+                    v[q] = 0;
+                    if (f < total) {
+                        int j = row_of(s_pre, f);
+                        v[q] = g.a_idx[s_beg[j] + f - s_pre[j]];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 16; q++) {
+                    int f = f0 + q * 64 + lane;
+                    if (f < total) s_idx[f] = v[q];
+                }
+            }
+            __syncthreads();
+            for (int k0 = 0; k0 < d; k0 += 8) {
+                uint64_t mm[8];
+#pragma unroll
+                for (int q = 0; q < 8; q++) mm[q] = (k0 + q < d) ? mask0[s_idx[pre + k0 + q]] : 0ull;
+#pragma unroll
+                for (int q = 0; q < 8; q++) m |= mm[q];
+            }
+        } else {
+            for (int k0 = 0; k0 < d; k0 += 8) {
+                int nets[8];
+#pragma unroll
+                for (int q = 0; q < 8; q++) nets[q] = (k0 + q < d) ? g.a_idx[beg + k0 + q] : -1;
+                uint64_t mm[8];
+#pragma unroll
+                for (int q = 0; q < 8; q++) mm[q] = nets[q] >= 0 ? mask0[nets[q]] : 0ull;
+#pragma unroll
+                for (int q = 0; q < 8; q++) m |= mm[q];
+            }
+        }
+        if (w >= 0) {
+            if (~m) {
+                int col = __builtin_ctzll(~m);
+                st[w] = TENT | col;
+                local_max = max(local_max, col);
+            } else {
+                heavy[atomicAdd(&ctrl->n_heavy, 1)] = w;
+            }
+        }
+        __syncthreads();
     }
     local_max = wave_max(local_max);
-    if (lane_id() == 0 && local_max >= 0) atomicMax(&ctrl->max_color, local_max);
+    if (lane == 0 && local_max >= 0) atomicMax(&ctrl->max_color, local_max);
 }
 
 // Block per queued vertex: full forbidden bitmap in LDS, first clear bit.
@@ -643,26 +721,54 @@ struct RankIter {
     }
 };
 
-// Thread per net of at most SMALL_NET members, scanned in rank order: the
-// first holder of a color keeps it.  Colors below 64 use a bit set; larger
-// colors are compared pairwise against earlier members.  With tent_only, only
-// proposed colors take part (after a vertex-based round no colored vertex can
-// clash).
-template <bool D2>
-__global__ void k_conflict_small(Graph g, const int *st, uint8_t *lose, int tent_only)
+// Scan of one net of at most SMALL_NET members in rank order (distance-2:
+// the center merged in at its rank); src[k - rel] is entry k of the net
+// lists.  The first holder of a color keeps it.  Colors below 64 use a bit
+// set; larger colors are compared pairwise against earlier members.  Colors
+// are gathered eight members at a time.  Returns the number of members still
+// uncolored or proposed (0: the net is finished).
+template <bool D2, class Src>
+__device__ __forceinline__ int scan_net(int v, int b, int e, Src src, int rel, const int *st, uint8_t *lose,
+                                        int tent_only)
 {
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n_b; v += gridDim.x * blockDim.x) {
-        int sz = Acc<D2>::size(g, v);
-        if (sz < 2 || sz > SMALL_NET) continue;
-        uint64_t seen = 0;
-        bool wide = false;
-        RankIter<D2> it(g, v);
-        int x;
-        while (it.next(&x)) {
-            int s = st[x];
-            if (tent_only && !(s >= 0 && (s & TENT))) continue;
-            int c = cur_color(s);
-            if (c < 0) continue;
+    const int size = e - b + (D2 ? 1 : 0);
+    int cpos = size;   // rank position of the center (distance-2)
+    if (D2) {
+        int lo = b, hi = e;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (src[mid - rel] < v) lo = mid + 1;
+            else hi = mid;
+        }
+        cpos = lo - b;
+    }
+    auto member = [&](int p) {
+        if (!D2) return (int)src[b + p - rel];
+        if (p < cpos) return (int)src[b + p - rel];
+        if (p == cpos) return v;
+        return (int)src[b + p - 1 - rel];
+    };
+    uint64_t seen = 0;
+    bool wide = false;
+    int pending = 0;
+    for (int p0 = 0; p0 < size; p0 += 8) {
+        int xs[8], ss[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) xs[q] = (p0 + q < size) ? member(p0 + q) : -1;
+#pragma unroll
+        for (int q = 0; q < 8; q++) ss[q] = xs[q] >= 0 ? st[xs[q]] : 0;
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            int x = xs[q], s = ss[q];
+            if (x < 0) continue;
+            if (s < 0) {
+                pending++;
+                continue;
+            }
+            bool tent = (s & TENT) != 0;
+            pending += tent;
+            if (tent_only && !tent) continue;
+            int c = s & COLOR_MASK;
             if (c < 64) {
                 if ((seen >> c) & 1ull) lose[x] = 1;
                 seen |= 1ull << c;
@@ -670,24 +776,76 @@ __global__ void k_conflict_small(Graph g, const int *st, uint8_t *lose, int tent
                 wide = true;
             }
         }
-        if (!wide) continue;
-        RankIter<D2> outer(g, v);
-        while (outer.next(&x)) {
-            int s = st[x];
-            if (tent_only && !(s >= 0 && (s & TENT))) continue;
-            int c = cur_color(s);
-            if (c < 64) continue;
-            RankIter<D2> inner(g, v);
-            int y;
-            while (inner.next(&y) && y < x) {
-                int t = st[y];
-                if (tent_only && !(t >= 0 && (t & TENT))) continue;
-                if (cur_color(t) == c) {
-                    lose[x] = 1;
-                    break;
-                }
+    }
+    if (!wide) return pending;
+    // pairwise for colors >= 64, in rank order
+    for (int p = 0; p < size; p++) {
+        int x = member(p);
+        int s = st[x];
+        if (s < 0 || (tent_only && !(s & TENT))) continue;
+        int c = s & COLOR_MASK;
+        if (c < 64) continue;
+        for (int p2 = 0; p2 < p; p2++) {
+            int t = st[member(p2)];
+            if (t < 0 || (tent_only && !(t & TENT))) continue;
+            if ((t & COLOR_MASK) == c) {
+                lose[x] = 1;
+                break;
             }
         }
+    }
+    return pending;
+}
+
+// One wave per 64 consecutive nets of at most SMALL_NET members.  The wave
+// copies its stretch of the net lists into LDS with coalesced loads, then
+// every lane scans its own net.  Nets whose members were all colored at an
+// earlier round are marked done and skipped: no vertex can join them again
+// until a net-based round evicts (the driver then clears the marks).  With
+// tent_only, only proposed colors take part (after a vertex-based round no
+// colored vertex can clash).
+template <bool D2>
+__global__ void __launch_bounds__(64) k_conflict_small(Graph g, const int *st, uint8_t *lose, uint8_t *done,
+                                                       int tent_only)
+{
+    __shared__ int s_idx[STAGE];
+    const int lane = threadIdx.x, nb = gridDim.x, lb = xcd_remap(blockIdx.x, nb);
+    for (int base = lb * 64; base < g.n_b; base += nb * 64) {
+        int v = base + lane;
+        bool act = false;
+        int b = 0, e = 0;
+        if (v < g.n_b) {
+            b = g.b_off[v];
+            e = g.b_off[v + 1];
+            int sz = e - b + (D2 ? 1 : 0);
+            act = sz >= 2 && sz <= SMALL_NET && !done[v];
+        }
+        if (!__ballot(act)) continue;
+        int vend = min(base + 64, g.n_b);
+        int off0 = g.b_off[base];
+        int seg = g.b_off[vend] - off0;
+        bool staged = seg <= STAGE;
+        if (staged) {
+            // every load of the stretch in flight before the first LDS store
+            int v32[STAGE / 64];
+#pragma unroll
+            for (int q = 0; q < STAGE / 64; q++) {
+                int f = q * 64 + lane;
+                v32[q] = f < seg ? g.b_idx[off0 + f] : 0;
+            }
+#pragma unroll
+            for (int q = 0; q < STAGE / 64; q++) {
+                int f = q * 64 + lane;
+                if (f < seg) s_idx[f] = v32[q];
+            }
+        }
+        __syncthreads();
+        if (act) {
+            int pending = staged ? scan_net<D2>(v, b, e, (const int *)s_idx, off0, st, lose, tent_only)
+                                 : scan_net<D2>(v, b, e, g.b_idx, 0, st, lose, tent_only);
+            if (pending == 0) done[v] = 1;
+        }
+        __syncthreads();
     }
 }
 
@@ -697,15 +855,27 @@ __device__ __forceinline__ unsigned hash_color(int c) { return (unsigned)c * 265
 // LDS hash color -> lowest-ranked holder; larger nets sweep the colors in
 // windows of WIN_COLORS with a direct-mapped table.
 template <bool D2>
-__global__ void k_conflict_big(Graph g, const int *st, uint8_t *lose, const int *big, const int *n_big_p,
-                               Ctrl *ctrl, int tent_only)
+__global__ void k_conflict_big(Graph g, const int *st, uint8_t *lose, uint8_t *done, const int *big,
+                               const int *n_big_p, Ctrl *ctrl, int tent_only)
 {
     extern __shared__ int sh[];
+    __shared__ int s_scan[20];
     const int n_big = *n_big_p;
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int bi = blockIdx.x; bi < n_big; bi += gridDim.x) {
         int v = big[bi];
+        if (done[v]) continue;
         int sz = Acc<D2>::size(g, v);
+        int pending = 0;
+        for (int k = tid; k < sz; k += nt) {
+            int s = st[Acc<D2>::member(g, v, k)];
+            pending += (s < 0 || (s & TENT)) ? 1 : 0;
+        }
+        pending = block_sum(pending, s_scan);
+        if (pending == 0) {
+            if (tid == 0) done[v] = 1;
+            continue;
+        }
         if (sz <= HASH_MAX) {
             int cap = 64;
             while (cap < 2 * sz) cap <<= 1;
@@ -775,47 +945,94 @@ __global__ void k_conflict_big(Graph g, const int *st, uint8_t *lose, const int 
 // Over the worklist (list != nullptr) or over every vertex (list == nullptr,
 // after a net-based round that may evict colored vertices): losers become
 // uncolored, winners keep their proposal and, when the masks are maintained
-// incrementally (update_masks), set its bit in the masks of their nets.
-// Writes the number of uncolored entries of each tile.
+// incrementally (update_masks), set its bit in the masks of their nets (each
+// wave walks its winners' rows as one flat range).  Writes the number of
+// uncolored entries of each tile.
 template <bool D2>
 __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, Ctrl *ctrl, int par, int *st,
                                                       uint8_t *lose, uint64_t *mask0, int *tile_count,
                                                       RoundRec *rec, int round, int update_masks)
 {
+    constexpr int NWV = TILE_BLOCK / WAVE;
     __shared__ int s_scan[8];
+    __shared__ int s_pre[NWV][64], s_beg[NWV][64];
+    __shared__ unsigned long long s_bit[NWV][64];
     const int n = list ? ctrl->n_w[par] : g.n_a;
     const int ntiles = (n + TILE - 1) / TILE;
+    const int lane = lane_id(), wid = threadIdx.x / WAVE;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctrl->n_w[par ^ 1] = 0;
         ctrl->n_heavy = 0;
     }
+    constexpr int KS = TILE / TILE_BLOCK;
     int evicted = 0, mx = -1;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         int cnt = 0;
-        for (int k = 0; k < TILE / TILE_BLOCK; k++) {
+        int us[KS], ss[KS];
+        uint8_t ls[KS];
+#pragma unroll
+        for (int k = 0; k < KS; k++) {
             int i = t * TILE + k * TILE_BLOCK + threadIdx.x;
-            if (i >= n) break;
-            int u = list ? list[i] : i;
-            int s = st[u];
-            if (lose[u]) {
-                lose[u] = 0;
-                if (s >= 0 && !(s & TENT)) evicted++;
-                st[u] = -1;
-                cnt++;
-            } else if (s < 0) {
-                cnt++;
-            } else {
-                int col = s & COLOR_MASK;
-                if (s & TENT) {
-                    st[u] = col;
-                    if (update_masks && col < 64) {
-                        uint64_t bit = 1ull << col;
-                        if (D2) atomicOr((unsigned long long *)&mask0[u], (unsigned long long)bit);
-                        for (int k2 = g.a_off[u]; k2 < g.a_off[u + 1]; k2++)
-                            atomicOr((unsigned long long *)&mask0[g.a_idx[k2]], (unsigned long long)bit);
+            us[k] = i < n ? (list ? list[i] : i) : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < KS; k++) {
+            ss[k] = us[k] >= 0 ? st[us[k]] : -1;
+            ls[k] = us[k] >= 0 ? lose[us[k]] : 0;
+        }
+        for (int k = 0; k < KS; k++) {
+            int beg = 0, d = 0;
+            unsigned long long bit = 0;
+            if (us[k] >= 0) {
+                int u = us[k];
+                int s = ss[k];
+                if (ls[k]) {
+                    lose[u] = 0;
+                    if (s >= 0 && !(s & TENT)) evicted++;
+                    st[u] = -1;
+                    cnt++;
+                } else if (s < 0) {
+                    cnt++;
+                } else {
+                    int col = s & COLOR_MASK;
+                    if (s & TENT) {
+                        st[u] = col;
+                        if (update_masks && col < 64) {
+                            bit = 1ull << col;
+                            beg = g.a_off[u];
+                            d = g.a_off[u + 1] - beg;
+                            if (D2) atomicOr((unsigned long long *)&mask0[u], bit);
+                        }
                     }
+                    mx = max(mx, col);
                 }
-                mx = max(mx, col);
+            }
+            if (update_masks) {   // uniform: every wave runs every k
+                int incl = wave_incl_scan(d);
+                int total = __shfl(incl, 63);
+                s_pre[wid][lane] = incl - d;
+                s_beg[wid][lane] = beg;
+                s_bit[wid][lane] = bit;
+                __syncthreads();
+                for (int f0 = 0; f0 < total; f0 += 256) {
+                    int tgt[4];
+                    unsigned long long bt[4];
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        int f = f0 + q * 64 + lane;
+                        tgt[q] = -1;
+                        bt[q] = 0;
+                        if (f < total) {
+                            int j = row_of(s_pre[wid], f);
+                            tgt[q] = g.a_idx[s_beg[wid][j] + f - s_pre[wid][j]];
+                            bt[q] = s_bit[wid][j];
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; q++)
+                        if (tgt[q] >= 0) atomicOr((unsigned long long *)&mask0[tgt[q]], bt[q]);
+                }
+                __syncthreads();
             }
         }
         cnt = block_sum(cnt, s_scan);
@@ -823,7 +1040,7 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
     }
     evicted = wave_sum(evicted);
     mx = wave_max(mx);
-    if (lane_id() == 0) {
+    if (lane == 0) {
         if (evicted) atomicAdd(&rec[round].evicted, evicted);
         if (mx >= 0) atomicMax(&ctrl->pad[0], mx);
     }
@@ -836,7 +1053,8 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
 // otherwise the round is counted and its record completed.
 __global__ void __launch_bounds__(TILE_BLOCK) k_compact(const int *list, int n_static, Ctrl *ctrl, int par,
                                                         const int *st, const int *tile_count, int *out,
-                                                        RoundRec *rec, int round, int mode, int count_round)
+                                                        RoundRec *rec, int round, int mode, int count_round,
+                                                        int *host)
 {
     constexpr int KS = TILE / TILE_BLOCK;
     constexpr int NWV = TILE_BLOCK / WAVE;
@@ -889,6 +1107,15 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_compact(const int *list, int n_s
                 R.w = ctrl->n_w[par];
                 R.losers = total;
                 R.max_color = ctrl->pad[0];
+                if (host) {
+                    // pinned host mirror: (round, worklist, error, max color)
+                    __atomic_store_n(&host[1], total, __ATOMIC_RELAXED);
+                    __atomic_store_n(&host[2], ctrl->error, __ATOMIC_RELAXED);
+                    __atomic_store_n(&host[3], ctrl->pad[0], __ATOMIC_RELAXED);
+                    __threadfence_system();
+                    __atomic_store_n(&host[0], round, __ATOMIC_RELAXED);
+                    __threadfence_system();
+                }
             }
         }
         __syncthreads();

@@ -265,3 +265,11 @@ def test_repeatable(cuda):
         if first is None:
             first = colors
         assert np.array_equal(colors, first)
+
+
+@pytest.mark.parametrize("mask", [0, 0b1, 0b10, 0b11])
+def test_stencil_small(cuda, mask):
+    g = synth.stencil27(24)
+    ref = oracle.bgpc(g, net_color_mask=mask)
+    res, colors = _gpu_bgpc(cuda, g, net_color_mask=mask)
+    _compare_full(res, colors, ref)
