@@ -87,8 +87,10 @@ enum {
 
 /* opts->flags */
 enum {
-    BGPC_STRICT = 1u,     /* validate sortedness, transpose / symmetry before coloring */
-    BGPC_RESUME = 2u      /* colors_out holds a conflict-free partial coloring to continue from */
+    BGPC_STRICT = 1u,      /* validate sortedness, transpose / symmetry before coloring */
+    BGPC_RESUME = 2u,      /* colors_out holds a conflict-free partial coloring to continue from */
+    BGPC_INCREMENTAL = 4u  /* first-fit vertex rounds recompute only the vertices whose neighbourhood
+                              changed (same results; pays off when few proposals change per round) */
 };
 
 /*
@@ -109,17 +111,38 @@ typedef struct {
     int32_t *max_color;
 } bgpc_round_log;
 
+/*
+ * Optional kernel timing: when opts->prof is set, the driver records a HIP
+ * event pair on opts->stream around every launch of the kernel named by
+ * `kernel` and returns the summed event time, the number of launches and the
+ * algorithmic bytes those launches had to move: the compulsory streams only
+ * (row offsets and ids of every row the launch walks, each vertex state or
+ * net mask once, the proposals written), never cache re-reads.
+ */
+enum {
+    BGPC_PROF_CONFLICT = 0,   /* net-side removal scan of small nets */
+    BGPC_PROF_COLOR = 1       /* vertex-based first-fit coloring of the worklist */
+};
+
+typedef struct {
+    int32_t kernel;           /* BGPC_PROF_* */
+    int32_t launches;         /* out */
+    double ms;                /* out: summed event time of those launches */
+    double bytes;             /* out: summed algorithmic bytes of those launches */
+} bgpc_profile;
+
 typedef struct {
     uint64_t net_color_mask;  /* bit r (r < 64): round r is net-based */
     int32_t policy;           /* BGPC_FIRST_FIT, BGPC_B1 or BGPC_B2 */
     int32_t chunk;            /* worklist entries per balancing state, >= 1 (default 64) */
     int32_t max_rounds;       /* rounds to run at most; 0: n + 65 */
     int32_t start_round;      /* index of the first round (selects mask bits); with BGPC_RESUME */
-    uint32_t flags;           /* BGPC_STRICT | BGPC_RESUME */
+    uint32_t flags;           /* BGPC_STRICT | BGPC_RESUME | BGPC_INCREMENTAL */
     int32_t reserved;
     void *stream;             /* hipStream_t; NULL = default stream */
     bgpc_round_log *log;      /* optional */
     int32_t *rounds_out;      /* optional, host: rounds run */
+    bgpc_profile *prof;       /* optional kernel timing */
 } bgpc_opts;
 
 /* Fills *opts with the defaults: vertex-based first-fit rounds, chunk 64. */
@@ -133,8 +156,8 @@ BGPC_API void bgpc_opts_default(bgpc_opts *opts);
  *   order    NULL for the natural order, else a device int32[|V_A|]
  *            permutation: order[k] is the vertex of rank k
  *   colors_out  device int32[|V_A|]; with BGPC_RESUME it is read first
- * Limits: |V_A|, |V_B| < 2^30; nnz < 2^31; a net of at most 1,048,576
- * vertices; colors below 1,048,576.
+ * Limits: |V_A|, |V_B| < 2^30; nnz < 2^31; when net-based rounds run, no
+ * net above 220,000 vertices; colors below 440,000 (BGPC_E_UNSUPPORTED).
  */
 BGPC_API int bgpc_color(const bgpc_csr *csr_A, const bgpc_csr *csr_B, const int32_t *order,
                         const bgpc_opts *opts, int32_t *colors_out);

@@ -33,11 +33,20 @@ class RoundLog(ctypes.Structure):
                 ("max_color", ctypes.c_void_p)]
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("launches", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+PROF_CONFLICT, PROF_COLOR = 0, 1
+INCREMENTAL = 4
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("net_color_mask", ctypes.c_uint64), ("policy", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("start_round", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p), ("log", ctypes.POINTER(RoundLog)),
-                ("rounds_out", ctypes.POINTER(ctypes.c_int32))]
+                ("rounds_out", ctypes.POINTER(ctypes.c_int32)), ("prof", ctypes.POINTER(Profile))]
 
 
 class Stats(ctypes.Structure):
@@ -138,7 +147,7 @@ class Result:
         return f"Result(status={self.status}, rounds={self.rounds})"
 
 
-def _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags, stream, log_cap):
+def _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags, stream, log_cap, prof=None):
     lib = load()
     o = Opts()
     lib.bgpc_opts_default(ctypes.byref(o))
@@ -159,6 +168,9 @@ def _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags, st
                       log_arrays["max_color"].ctypes.data)
         o.log = ctypes.pointer(lg)
         keep.append(lg)
+    if prof is not None:
+        o.prof = ctypes.pointer(prof)
+        keep.append(prof)
     return o, rounds, log_arrays, keep
 
 
@@ -171,11 +183,12 @@ def _finish(status, rounds, log_arrays, o):
 
 
 def bgpc_color(csr_A: DeviceCsr, csr_B: DeviceCsr, order, colors_out, net_color_mask=0, policy=FIRST_FIT,
-               chunk=64, max_rounds=0, start_round=0, flags=0, stream=None, log_cap=0) -> Result:
-    """Bipartite-graph partial coloring; colors_out is an int32 GPU tensor of |V_A|."""
+               chunk=64, max_rounds=0, start_round=0, flags=0, stream=None, log_cap=0, prof=None) -> Result:
+    """Bipartite-graph partial coloring; colors_out is an int32 GPU tensor of |V_A|.
+    prof: optional Profile struct (kernel timing), filled in place."""
     lib = load()
     o, rounds, log_arrays, keep = _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags,
-                                             stream, log_cap)
+                                             stream, log_cap, prof)
     a, b = csr_A.as_struct(), csr_B.as_struct()
     order_p = _dev_ptr(order, "order") if order is not None else None
     st = lib.bgpc_color(ctypes.byref(a), ctypes.byref(b), order_p, ctypes.byref(o), _dev_ptr(colors_out, "colors_out"))
@@ -184,11 +197,11 @@ def bgpc_color(csr_A: DeviceCsr, csr_B: DeviceCsr, order, colors_out, net_color_
 
 
 def d2gc_color(adj: DeviceCsr, order, colors_out, net_color_mask=0, policy=FIRST_FIT, chunk=64, max_rounds=0,
-               start_round=0, flags=0, stream=None, log_cap=0) -> Result:
+               start_round=0, flags=0, stream=None, log_cap=0, prof=None) -> Result:
     """Distance-2 coloring of a symmetric graph; colors_out is an int32 GPU tensor of n."""
     lib = load()
     o, rounds, log_arrays, keep = _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags,
-                                             stream, log_cap)
+                                             stream, log_cap, prof)
     a = adj.as_struct()
     order_p = _dev_ptr(order, "order") if order is not None else None
     st = lib.d2gc_color(ctypes.byref(a), order_p, ctypes.byref(o), _dev_ptr(colors_out, "colors_out"))

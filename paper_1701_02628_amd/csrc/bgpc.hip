@@ -139,6 +139,21 @@ struct HostProgress {
     }
 };
 
+// HIP events bracketing the launches of one kernel (opts->prof)
+struct EventPool {
+    std::vector<hipEvent_t> ev;
+    int used = 0;
+    hipEvent_t next()
+    {
+        if (used == (int)ev.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            ev.push_back(e);
+        }
+        return ev[used++];
+    }
+};
+
 struct RunArgs {
     Graph g;
     bool d2;
@@ -168,7 +183,8 @@ int run(const RunArgs &a)
 
     // ---- workspace
     const int max_tiles = (n_a + TILE - 1) / TILE + 1;
-    const int rec_cap = std::min(max_rounds, 1 << 20) + 2;
+    const int rec_cap = std::min(max_rounds, 65536) + 2;   // the round log keeps 65,536 rounds
+    const int prof_rounds = o.prof ? std::min(max_rounds, PROF_ROUNDS) : 0;
     bool any_net_round = false;
     for (int r = 0; r < max_rounds && start_round + r < 64; r++)
         if (start_round + r >= 0 && ((o.net_color_mask >> (start_round + r)) & 1ull)) any_net_round = true;
@@ -181,7 +197,13 @@ int run(const RunArgs &a)
                    + aligned(1, sizeof(Ctrl))         //
                    + aligned(8, 4)                    // shape figures
                    + aligned(rec_cap, sizeof(RoundRec))
-                   + (any_net_round ? aligned(n_a + 1, 4) : 0);
+                   + aligned((size_t)prof_rounds * PROF_SLOTS * 3 + 1, 8)
+                   + (any_net_round ? aligned(n_a + 1, 4) : 0)
+                   + aligned(1, sizeof(IncCtrl))
+                   + aligned(n_a + 1, 4) * 4          // incremental lists D0, D1, A, winners
+                   + aligned(n_b + 1, 4) * 2          // nets with a changed proposal / a winner
+                   + aligned(n_a / 32 + 2, 4) * 2     // dirty, affected bit sets
+                   + aligned(n_b / 32 + 2, 4) * 2;    // net bit sets
     Arena ar;
     int rc = ar.reserve(bytes, s);
     if (rc != BGPC_OK) return rc;
@@ -196,7 +218,18 @@ int run(const RunArgs &a)
     Ctrl *ctrl = ar.take<Ctrl>(1);
     int *shape = ar.take<int>(8);
     RoundRec *rec = ar.take<RoundRec>(rec_cap);
+    unsigned long long *pcnt = ar.take<unsigned long long>((size_t)prof_rounds * PROF_SLOTS * 3 + 1);
     int *owner = any_net_round ? ar.take<int>(n_a + 1) : nullptr;
+    IncCtrl *ic = ar.take<IncCtrl>(1);
+    int *Dl[2] = {ar.take<int>(n_a + 1), ar.take<int>(n_a + 1)};
+    int *Al = ar.take<int>(n_a + 1);
+    int *WINl = ar.take<int>(n_a + 1);
+    int *TCNl = ar.take<int>(n_b + 1);
+    int *CNl = ar.take<int>(n_b + 1);
+    unsigned *dirty_bits = ar.take<unsigned>(n_a / 32 + 2);
+    unsigned *aff_bits = ar.take<unsigned>(n_a / 32 + 2);
+    unsigned *tchg_bits = ar.take<unsigned>(n_b / 32 + 2);
+    unsigned *cn_bits = ar.take<unsigned>(n_b / 32 + 2);
     int *Wb[2] = {W0, W1};
 
     int st_code = BGPC_OK;
@@ -211,6 +244,32 @@ int run(const RunArgs &a)
     // thread exit could run after the HIP runtime has shut down)
     static thread_local HostProgress *prog_p = new HostProgress();
     HostProgress &prog = *prog_p;
+    static thread_local EventPool *evpool_p = new EventPool();
+    EventPool &evpool = *evpool_p;
+    evpool.used = 0;
+    const int prof_kernel = o.prof ? o.prof->kernel : -1;
+    if (o.prof) {
+        o.prof->launches = 0;
+        o.prof->ms = 0.0;
+        o.prof->bytes = 0.0;
+    }
+#define PCNT(r) ((r) < prof_rounds ? pcnt + (size_t)(r) * PROF_SLOTS * 3 : nullptr)
+    if (prof_rounds)
+        k_fill_i32<<<grid_for((long)prof_rounds * PROF_SLOTS * 6, nthr, di.cus * 4), nthr, 0, s>>>(
+            (int *)pcnt, 0, (long)prof_rounds * PROF_SLOTS * 6);
+#define LAUNCH_PROF(kid, launch)                                  \
+    do {                                                          \
+        hipEvent_t e0_ = nullptr, e1_ = nullptr;                  \
+        if (prof_kernel == (kid)) {                               \
+            e0_ = evpool.next();                                  \
+            if (e0_) hipEventRecord(e0_, s);                      \
+        }                                                         \
+        launch;                                                   \
+        if (prof_kernel == (kid) && e0_) {                        \
+            e1_ = evpool.next();                                  \
+            if (e1_) hipEventRecord(e1_, s);                      \
+        }                                                         \
+    } while (0)
 
     // ---- shape of the graph: largest net, big nets, distance-2 bound
     k_fill_i32<<<1, 64, 0, s>>>(shape, 0, 8);
@@ -251,6 +310,10 @@ int run(const RunArgs &a)
         // ---- initial state
         k_fill_u8<<<g_a, nthr, 0, s>>>(lose, 0, n_a + 1);
         k_fill_u8<<<g_b, nthr, 0, s>>>(done_net, 0, n_b + 1);
+        k_fill_i32<<<g_a, nthr, 0, s>>>((int *)dirty_bits, 0, n_a / 32 + 2);
+        k_fill_i32<<<g_a, nthr, 0, s>>>((int *)aff_bits, 0, n_a / 32 + 2);
+        k_fill_i32<<<g_b, nthr, 0, s>>>((int *)tchg_bits, 0, n_b / 32 + 2);
+        k_fill_i32<<<g_b, nthr, 0, s>>>((int *)cn_bits, 0, n_b / 32 + 2);
         if (!resume) {
             k_fill_i32<<<g_a, nthr, 0, s>>>(st, -1, n_a);
             k_iota<<<g_a, nthr, 0, s>>>(W0, n_a);
@@ -288,8 +351,18 @@ int run(const RunArgs &a)
         const int gt = grid_for(max_tiles, 1, di.cus * 4);
         const int g_big = std::max(1, std::min(n_big, di.cus * 4));
         const int g_chunk = grid_for((n_a + chunk - 1) / chunk, 1, di.cus * 16);
+        // first-fit vertex rounds after the last net-based round run
+        // incrementally (graphs whose nets all run thread-per-net)
+        const bool inc_ok = (o.flags & BGPC_INCREMENTAL) && policy == BGPC_FIRST_FIT && n_big == 0 &&
+                            max_net <= SMALL_NET;
+        int last_net = -1;
+        for (int r = 0; r < max_rounds && start_round + r < 64; r++)
+            if ((o.net_color_mask >> (start_round + r)) & 1ull) last_net = r;
+        const int inc_start = inc_ok ? last_net + 1 : 0x7fffffff;
+        const int g_inc = di.cus * 4;
         bool done = false;
         bool use_prog = prog.h && prog.d;
+        bool inc_used = false;
         int net_round_issued = -1;   // last net-based round queued
         // one wave per 64 items, grids a multiple of 8 (XCD-aware remap)
         auto grid64 = [&](long items) {
@@ -354,7 +427,7 @@ int run(const RunArgs &a)
                 if (n_big) k_ncolor_big<D2><<<g_big, 256, ncolor_words * 4, s>>>(g, st, owner, big, &shape[1], ctrl,
                                                                                  ncolor_words);
                 if (!D2) k_ncolor_isolated<<<g_a, nthr, 0, s>>>(g, Wc, ctrl, par, st);
-                k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 0);
+                LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 0, PCNT(r))));
                 if (n_big)
                     k_conflict_big<D2><<<g_big, 256, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 0);
                 const bool full = r > 0 || resume;
@@ -364,14 +437,49 @@ int run(const RunArgs &a)
                     k_compact<<<gt, TILE_BLOCK, 0, s>>>(nullptr, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 1, 1, host);
                     k_mask_rebuild<D2><<<g_b, nthr, 0, s>>>(g, st, mask0);
                     k_fill_u8<<<g_b, nthr, 0, s>>>(done_net, 0, n_b + 1);
+        k_fill_i32<<<g_a, nthr, 0, s>>>((int *)dirty_bits, 0, n_a / 32 + 2);
+        k_fill_i32<<<g_a, nthr, 0, s>>>((int *)aff_bits, 0, n_a / 32 + 2);
+        k_fill_i32<<<g_b, nthr, 0, s>>>((int *)tchg_bits, 0, n_b / 32 + 2);
+        k_fill_i32<<<g_b, nthr, 0, s>>>((int *)cn_bits, 0, n_b / 32 + 2);
                 } else {
                     k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1);
                     k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 1, 1, host);
                 }
                 net_round_issued = r;
+            } else if (r >= inc_start) {
+                // the wide path can only be needed once colors 0..63 all exist
+                bool need_wide = true;
+                if (use_prog) {
+                    int seen = prog.h[0], mc = prog.h[3];
+                    if (seen >= 0 && net_round_issued <= seen) need_wide = (long)mc + (r - 1 - seen) >= 63;
+                    else if (seen < 0 && !resume && net_round_issued < 0) need_wide = r >= 63;
+                }
+                if (r == inc_start) {
+                    // full round whose losers keep their proposals
+                    k_inc_reset<<<1, 64, 0, s>>>(ic);
+                    LAUNCH_PROF(BGPC_PROF_COLOR, (k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy, PCNT(r))));
+                    if (need_wide)
+                        k_vcolor_wide<D2><<<di.cus * 2, 256, wide_bytes, s>>>(g, heavy, ctrl, st, lds_bits, nullptr,
+                                                                               nullptr, nullptr, nullptr, nullptr);
+                    LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r))));
+                    k_inc_apply_full<D2><<<g_inc, nthr, 0, s>>>(g, ic, ctrl, par, Wc, st, lose, mask0, cn_bits, CNl);
+                } else {
+                    k_inc_color<D2><<<g_inc, nthr, 0, s>>>(g, ic, par, Dl[par], dirty_bits, st, mask0, aff_bits, Al,
+                                                           tchg_bits, TCNl, heavy, ctrl);
+                    if (need_wide)
+                        k_vcolor_wide<D2><<<di.cus * 2, 256, wide_bytes, s>>>(g, heavy, ctrl, st, lds_bits, ic,
+                                                                               aff_bits, Al, tchg_bits, TCNl);
+                    k_expand<D2><<<g_inc, nthr, 0, s>>>(g, TCNl, &ic->n_tcn, tchg_bits, st, aff_bits, Al, &ic->n_a);
+                    k_inc_conflict<D2><<<g_inc, nthr, 0, s>>>(g, ic, par, Al, aff_bits, st, WINl, ctrl);
+                    k_inc_apply<D2><<<g_inc, nthr, 0, s>>>(g, ic, WINl, st, mask0, cn_bits, CNl, ctrl);
+                }
+                k_expand<D2><<<g_inc, nthr, 0, s>>>(g, CNl, &ic->n_cn, cn_bits, st, dirty_bits, Dl[par ^ 1],
+                                                    &ic->n_d[par ^ 1]);
+                k_inc_close<<<1, 64, 0, s>>>(ic, ctrl, par, rec, rr, host);
+                inc_used = true;
             } else {
                 if (policy == BGPC_FIRST_FIT) {
-                    k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy);
+                    LAUNCH_PROF(BGPC_PROF_COLOR, (k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy, PCNT(r))));
                     // the wide path can only be needed once colors 0..63 all exist:
                     // a vertex-based first-fit round raises the largest color by at
                     // most one, a net-based round keeps it below the largest net
@@ -385,12 +493,14 @@ int run(const RunArgs &a)
                             need_wide = r >= 63;
                         }
                     }
-                    if (need_wide) k_vcolor_wide<D2><<<di.cus * 2, 256, wide_bytes, s>>>(g, heavy, ctrl, st, lds_bits);
+                    if (need_wide)
+                        k_vcolor_wide<D2><<<di.cus * 2, 256, wide_bytes, s>>>(g, heavy, ctrl, st, lds_bits, nullptr,
+                                                                               nullptr, nullptr, nullptr, nullptr);
                 } else {
                     k_vcolor_chunked<D2><<<g_chunk, 64, wide_bytes, s>>>(g, Wc, ctrl, par, st, mask0, policy, chunk,
                                                                           lds_bits);
                 }
-                k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1);
+                LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r))));
                 if (n_big)
                     k_conflict_big<D2><<<g_big, 256, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 1);
                 k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1);
@@ -399,6 +509,8 @@ int run(const RunArgs &a)
             LAUNCH_CHECK();
             issued++;
         }
+        if (inc_used) k_drop_proposals<<<g_a, nthr, 0, s>>>(st, n_a);
+        LAUNCH_CHECK();
     }
 
 finish:
@@ -410,6 +522,42 @@ finish:
         if (h_ctrl.error & (ERR_COLOR_CAP | ERR_NET_TOO_BIG)) st_code = BGPC_E_UNSUPPORTED;
         else if (h_ctrl.error) st_code = BGPC_E_INTERNAL;
         else if (h_ctrl.n_w[issued & 1] != 0) st_code = BGPC_E_NOT_CONVERGED;
+    }
+    if (o.prof && evpool.used >= 2 && (st_code == BGPC_OK || st_code == BGPC_E_NOT_CONVERGED)) {
+        double ms = 0.0;
+        for (int i = 0; i + 1 < evpool.used; i += 2) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, evpool.ev[i], evpool.ev[i + 1]) == hipSuccess) ms += t;
+        }
+        o.prof->ms = ms;
+        o.prof->launches = evpool.used / 2;
+        // algorithmic bytes from the per-round counters
+        int k = std::min(std::min(h_ctrl.rounds, rec_cap - 2), prof_rounds);
+        std::vector<RoundRec> rr_h(std::max(k, 1));
+        std::vector<unsigned long long> pc_h((size_t)std::max(k, 1) * PROF_SLOTS * 3);
+        if (k > 0 && hipMemcpy(rr_h.data(), rec, sizeof(RoundRec) * k, hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(pc_h.data(), pcnt, sizeof(unsigned long long) * k * PROF_SLOTS * 3,
+                      hipMemcpyDeviceToHost) == hipSuccess) {
+            double bytes = 0.0;
+            for (int i = 0; i < k; i++) {
+                double nets = 0, mem = 0, rows = 0;
+                for (int q = 0; q < PROF_SLOTS; q++) {
+                    nets += (double)pc_h[((size_t)i * PROF_SLOTS + q) * 3 + 0];
+                    mem += (double)pc_h[((size_t)i * PROF_SLOTS + q) * 3 + 1];
+                    rows += (double)pc_h[((size_t)i * PROF_SLOTS + q) * 3 + 2];
+                }
+                if (prof_kernel == BGPC_PROF_CONFLICT) {
+                    // per walked net: its end offset + member ids; every member
+                    // state once (at most n_a distinct)
+                    bytes += 4.0 * nets + 4.0 * mem + 4.0 * std::min(mem, (double)n_a);
+                } else if (prof_kernel == BGPC_PROF_COLOR && rr_h[i].mode == 0) {
+                    // per entry: id, two row offsets, proposal; per incidence: net
+                    // id; every net mask once (at most n_b distinct)
+                    bytes += 16.0 * rr_h[i].w + 4.0 * rows + 8.0 * std::min(rows, (double)n_b);
+                }
+            }
+            o.prof->bytes = bytes;
+        }
     }
     if (st_code == BGPC_OK || st_code == BGPC_E_NOT_CONVERGED) {
         if (o.rounds_out) *o.rounds_out = h_ctrl.rounds;

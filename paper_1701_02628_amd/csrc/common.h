@@ -81,6 +81,13 @@ struct RoundRec {
     int pad[3];
 };
 
+// Profiling counters of one round (opts->prof only), 64 slots each so that
+// concurrent waves rarely hit the same address: per slot (nets walked by the
+// small-net removal scan, memberships walked by it, nets(w) entries walked by
+// first-fit coloring).
+constexpr int PROF_SLOTS = 64;
+constexpr int PROF_ROUNDS = 8192;
+
 enum : int {
     ERR_COLOR_CAP = 1,      // a color needed more bitmap capacity than reserved
     ERR_NET_DUP = 2,        // two colored members of one net share a color at round start

@@ -45,6 +45,51 @@ __device__ __forceinline__ int row_of(const int *pre, int f)
     return lo;
 }
 
+// atomicMax that skips the atomic when a plain read already shows a value
+// at least as large: many waves end with the same value, and same-address
+// atomics serialize at the L2.
+__device__ __forceinline__ void max_to(int *p, int v)
+{
+    if (*(volatile int *)p < v) atomicMax(p, v);
+}
+
+// Counters and helpers of the incremental first-fit rounds (see below).
+struct IncCtrl {
+    int n_d[2];     // dirty list, double-buffered by round parity
+    int n_a;        // vertices whose removal test is redone
+    int n_win;      // winners of the round
+    int n_tcn;      // nets holding a changed proposal
+    int n_cn;       // nets holding a winner
+    int pad[2];
+};
+
+// set bit id once; true for the caller that set it
+__device__ __forceinline__ bool set_once(unsigned *bits, int id)
+{
+    unsigned b = 1u << (id & 31);
+    if (bits[id >> 5] & b) return false;
+    return !(atomicOr(&bits[id >> 5], b) & b);
+}
+
+__device__ __forceinline__ void clear_bit(unsigned *bits, int id)
+{
+    atomicAnd(&bits[id >> 5], ~(1u << (id & 31)));
+}
+
+__device__ __forceinline__ bool is_tent(int s) { return s >= 0 && (s & TENT); }
+
+// record that w's proposal changed: its nets are queued for k_expand into A
+template <bool D2>
+__device__ __forceinline__ void mark_proposal_change(const Graph &g, int w, unsigned *tchg_bits, int *tcn,
+                                                     IncCtrl *ic)
+{
+    int k = Acc<D2>::nets_count(g, w);
+    for (int j = 0; j < k; j++) {
+        int v = Acc<D2>::net_at(g, w, j);
+        if (set_once(tchg_bits, v)) tcn[atomicAdd(&ic->n_tcn, 1)] = v;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // setup
 
@@ -94,7 +139,7 @@ __global__ void k_net_shape(Graph g, int *max_net, int *big_list, int *n_big)
         if (sz > SMALL_NET) big_list[atomicAdd(n_big, 1)] = v;
     }
     local = wave_max(local);
-    if (lane_id() == 0) atomicMax(max_net, local);
+    if (lane_id() == 0) max_to(max_net, local);
 }
 
 template <bool D2>
@@ -109,7 +154,7 @@ __global__ void k_two_hop_bound(Graph g, int *bound)
     }
     int l32 = (int)min(local, (long)0x3fffffff);
     l32 = wave_max(l32);
-    if (lane_id() == 0) atomicMax(bound, l32);
+    if (lane_id() == 0) max_to(bound, l32);
 }
 
 // owner(u): the largest net containing u, ties to the lowest net id
@@ -210,8 +255,8 @@ __global__ void k_max_color(const int *st, int n, Ctrl *ctrl)
         local = max(local, cur_color(st[i]));
     local = wave_max(local);
     if (lane_id() == 0 && local >= 0) {
-        atomicMax(&ctrl->max_color, local);
-        atomicMax(&ctrl->pad[0], local);
+        max_to(&ctrl->max_color, local);
+        max_to(&ctrl->pad[0], local);
     }
 }
 
@@ -318,8 +363,9 @@ __device__ int block_find_free_down(const uint32_t *bits, int cap_bits, int from
 // colors are all forbidden are queued for k_vcolor_wide.
 template <bool D2>
 __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *ctrl, int par, int *st,
-                                                  const uint64_t *mask0, int *heavy)
+                                                  const uint64_t *mask0, int *heavy, unsigned long long *prof)
 {
+    unsigned long long rows = 0;
     __shared__ int s_pre[65], s_beg[64];
     __shared__ int s_idx[STAGE];
     const int n = ctrl->n_w[par];
@@ -338,6 +384,7 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
         int incl = wave_incl_scan(d);
         int total = __shfl(incl, 63);
         int pre = incl - d;
+        rows += total;
         s_pre[lane] = pre;
         s_beg[lane] = beg;
         __syncthreads();
@@ -391,12 +438,14 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
         __syncthreads();
     }
     local_max = wave_max(local_max);
-    if (lane == 0 && local_max >= 0) atomicMax(&ctrl->max_color, local_max);
+    if (lane == 0 && local_max >= 0) max_to(&ctrl->max_color, local_max);
+    if (prof && lane == 0 && rows) atomicAdd(&prof[3 * (blockIdx.x & 63) + 2], rows);
 }
 
 // Block per queued vertex: full forbidden bitmap in LDS, first clear bit.
 template <bool D2>
-__global__ void k_vcolor_wide(Graph g, const int *heavy, Ctrl *ctrl, int *st, int lds_bits)
+__global__ void k_vcolor_wide(Graph g, const int *heavy, Ctrl *ctrl, int *st, int lds_bits, IncCtrl *ic,
+                              unsigned *aff_bits, int *A, unsigned *tchg_bits, int *tcn)
 {
     extern __shared__ uint32_t dyn[];
     __shared__ int s_net[1025], s_pre[1025], s_scan[20], s_res;
@@ -415,8 +464,17 @@ __global__ void k_vcolor_wide(Graph g, const int *heavy, Ctrl *ctrl, int *st, in
         build_forbidden<D2>(g, st, w, dyn, cap, s_net, s_pre, s_scan);
         int col = block_find_free_up(dyn, cap, 0, &s_res);
         if (threadIdx.x == 0) {
-            st[w] = TENT | col;
-            atomicMax(&ctrl->max_color, col);
+            int nw = TENT | col;
+            if (ic) {   // incremental rounds: note a changed proposal, join A
+                if (st[w] != nw) {
+                    st[w] = nw;
+                    mark_proposal_change<D2>(g, w, tchg_bits, tcn, ic);
+                }
+                if (set_once(aff_bits, w)) A[atomicAdd(&ic->n_a, 1)] = w;
+            } else {
+                st[w] = nw;
+            }
+            max_to(&ctrl->max_color, col);
         }
         __syncthreads();
     }
@@ -536,7 +594,7 @@ __global__ void __launch_bounds__(64) k_vcolor_chunked(Graph g, const int *W, Ct
                 policy_update(policy, col, s);
                 if (lane == 0) {
                     st[wj] = TENT | col;
-                    atomicMax(&ctrl->max_color, col);
+                    max_to(&ctrl->max_color, col);
                 }
             }
         }
@@ -582,7 +640,7 @@ __global__ void k_ncolor_small(Graph g, int *st, const int *owner, Ctrl *ctrl)
         }
     }
     local_max = wave_max(local_max);
-    if (lane_id() == 0 && local_max >= 0) atomicMax(&ctrl->max_color, local_max);
+    if (lane_id() == 0 && local_max >= 0) max_to(&ctrl->max_color, local_max);
 }
 
 // Block per net larger than SMALL_NET.  LDS: forbidden bitmap of |vtxs(v)|
@@ -670,7 +728,7 @@ __global__ void k_ncolor_big(Graph g, int *st, const int *owner, const int *big,
             base += total;
         }
         local_max = block_max(local_max, s_scan);
-        if (tid == 0 && local_max >= 0) atomicMax(&ctrl->max_color, local_max);
+        if (tid == 0 && local_max >= 0) max_to(&ctrl->max_color, local_max);
         __syncthreads();
     }
 }
@@ -806,8 +864,9 @@ __device__ __forceinline__ int scan_net(int v, int b, int e, Src src, int rel, c
 // colored vertex can clash).
 template <bool D2>
 __global__ void __launch_bounds__(64) k_conflict_small(Graph g, const int *st, uint8_t *lose, uint8_t *done,
-                                                       int tent_only)
+                                                       int tent_only, unsigned long long *prof)
 {
+    int walked_nets = 0, walked_members = 0;
     __shared__ int s_idx[STAGE];
     const int lane = threadIdx.x, nb = gridDim.x, lb = xcd_remap(blockIdx.x, nb);
     for (int base = lb * 64; base < g.n_b; base += nb * 64) {
@@ -845,7 +904,16 @@ __global__ void __launch_bounds__(64) k_conflict_small(Graph g, const int *st, u
                                  : scan_net<D2>(v, b, e, g.b_idx, 0, st, lose, tent_only);
             if (pending == 0) done[v] = 1;
         }
+        walked_nets += act ? 1 : 0;
+        walked_members += act ? e - b + (D2 ? 1 : 0) : 0;
         __syncthreads();
+    }
+    if (prof) {
+        int wn = wave_sum(walked_nets), wm = wave_sum(walked_members);
+        if (lane == 0 && wn) {
+            atomicAdd(&prof[3 * (blockIdx.x & 63) + 0], (unsigned long long)wn);
+            atomicAdd(&prof[3 * (blockIdx.x & 63) + 1], (unsigned long long)wm);
+        }
     }
 }
 
@@ -1042,7 +1110,7 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
     mx = wave_max(mx);
     if (lane == 0) {
         if (evicted) atomicAdd(&rec[round].evicted, evicted);
-        if (mx >= 0) atomicMax(&ctrl->pad[0], mx);
+        if (mx >= 0) max_to(&ctrl->pad[0], mx);
     }
 }
 
@@ -1141,6 +1209,240 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_count_uncolored(const int *st, i
 __global__ void k_set_max_final(Ctrl *ctrl, int v)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) ctrl->pad[0] = v;
+}
+
+// ---------------------------------------------------------------------------
+// incremental first-fit vertex rounds
+//
+// Between two first-fit vertex-based rounds only two things can change the
+// outcome for a worklist vertex w: a neighbour got colored (F(w) changes, so
+// its proposal may change), or w or a lower-ranked neighbour changed its
+// proposal (its removal test may change).  Everything else repeats: w makes
+// the same proposal and loses again.  The incremental rounds therefore keep
+// every worklist vertex's last proposal (TENT | col) and recompute only
+//   D_r = worklist vertices sharing a net with a winner of round r-1
+//         (first-fit again, k_inc_color),
+//   A_r = D_r plus the worklist members of nets holding a vertex whose
+//         proposal changed (removal test again, k_inc_conflict).
+// The round's result is exactly the full round's result.  Sets are
+// deduplicated with bit sets and kept as unordered lists; the order of a
+// list never reaches a result.
+
+__global__ void k_inc_reset(IncCtrl *ic)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ic->n_d[0] = ic->n_d[1] = 0;
+        ic->n_a = ic->n_win = ic->n_tcn = ic->n_cn = 0;
+    }
+}
+
+// Thread per dirty vertex: first-fit through the masks of its nets (eight
+// gathers in flight).  A changed proposal queues w's nets; w itself always
+// joins A.  Entries needing colors >= 64 go to k_vcolor_wide (incremental).
+template <bool D2>
+__global__ void k_inc_color(Graph g, IncCtrl *ic, int par, const int *D, unsigned *dirty_bits, int *st,
+                            const uint64_t *mask0, unsigned *aff_bits, int *A, unsigned *tchg_bits, int *tcn,
+                            int *heavy, Ctrl *ctrl)
+{
+    const int n = ic->n_d[par];
+    if (blockIdx.x == 0 && threadIdx.x == 0) ic->n_win = 0;
+    int local_max = -1;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int w = D[i];
+        clear_bit(dirty_bits, w);
+        uint64_t m = D2 ? mask0[w] : 0ull;
+        int beg = g.a_off[w], d = g.a_off[w + 1] - beg;
+        for (int k0 = 0; k0 < d; k0 += 8) {
+            int nets[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++) nets[q] = (k0 + q < d) ? g.a_idx[beg + k0 + q] : -1;
+            uint64_t mm[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++) mm[q] = nets[q] >= 0 ? mask0[nets[q]] : 0ull;
+#pragma unroll
+            for (int q = 0; q < 8; q++) m |= mm[q];
+        }
+        if (~m) {
+            int col = __builtin_ctzll(~m);
+            int nw = TENT | col;
+            if (st[w] != nw) {
+                st[w] = nw;
+                mark_proposal_change<D2>(g, w, tchg_bits, tcn, ic);
+            }
+            if (set_once(aff_bits, w)) A[atomicAdd(&ic->n_a, 1)] = w;
+            local_max = max(local_max, col);
+        } else {
+            heavy[atomicAdd(&ctrl->n_heavy, 1)] = w;
+        }
+    }
+    local_max = wave_max(local_max);
+    if (lane_id() == 0 && local_max >= 0) max_to(&ctrl->max_color, local_max);
+}
+
+// Thread per listed net: every worklist member (a vertex holding a proposal)
+// joins `out` once.  Clears the net's bit.
+template <bool D2>
+__global__ void k_expand(Graph g, const int *nets, const int *n_nets_p, unsigned *net_bits, const int *st,
+                         unsigned *item_bits, int *out, int *n_out)
+{
+    const int n = *n_nets_p;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int v = nets[i];
+        clear_bit(net_bits, v);
+        int sz = Acc<D2>::size(g, v);
+        for (int k0 = 0; k0 < sz; k0 += 8) {
+            int xs[8], ss[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++) xs[q] = (k0 + q < sz) ? Acc<D2>::member(g, v, k0 + q) : -1;
+#pragma unroll
+            for (int q = 0; q < 8; q++) ss[q] = xs[q] >= 0 ? st[xs[q]] : -1;
+#pragma unroll
+            for (int q = 0; q < 8; q++)
+                if (is_tent(ss[q]) && set_once(item_bits, xs[q])) out[atomicAdd(n_out, 1)] = xs[q];
+        }
+    }
+}
+
+// Thread per vertex of A: w loses iff a lower-ranked worklist vertex sharing
+// a net proposes the same color (members are sorted, so each net is read
+// only up to w).  Winners are listed.
+template <bool D2>
+__global__ void k_inc_conflict(Graph g, IncCtrl *ic, int par, const int *A, unsigned *aff_bits, const int *st,
+                               int *win, Ctrl *ctrl)
+{
+    const int n = ic->n_a;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ic->n_d[par ^ 1] = 0;
+        ic->n_cn = 0;
+        ic->n_tcn = 0;
+        ctrl->n_heavy = 0;
+    }
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int w = A[i];
+        clear_bit(aff_bits, w);
+        int c = st[w] & COLOR_MASK;
+        bool lost = false;
+        int nn = Acc<D2>::nets_count(g, w);
+        for (int j = 0; j < nn && !lost; j++) {
+            int v = Acc<D2>::net_at(g, w, j);
+            if (D2 && v < w) {
+                int sv = st[v];
+                if (is_tent(sv) && (sv & COLOR_MASK) == c) {
+                    lost = true;
+                    break;
+                }
+            }
+            int b = g.b_off[v], e = g.b_off[v + 1];
+            for (int k0 = b; k0 < e && !lost; k0 += 8) {
+                int xs[8], ss[8];
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    int x = (k0 + q < e) ? g.b_idx[k0 + q] : 0x7fffffff;
+                    xs[q] = x < w ? x : -1;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; q++) ss[q] = xs[q] >= 0 ? st[xs[q]] : -1;
+#pragma unroll
+                for (int q = 0; q < 8; q++)
+                    if (is_tent(ss[q]) && (ss[q] & COLOR_MASK) == c) lost = true;
+                if (xs[7] < 0) break;   // reached members >= w
+            }
+        }
+        if (!lost) win[atomicAdd(&ic->n_win, 1)] = w;
+    }
+}
+
+// Thread per winner: its proposal becomes its color; the masks of its nets
+// take the color; its nets are queued for the next round's dirty set.
+template <bool D2>
+__global__ void k_inc_apply(Graph g, IncCtrl *ic, const int *win, int *st, uint64_t *mask0, unsigned *cn_bits,
+                            int *cn, Ctrl *ctrl)
+{
+    const int n = ic->n_win;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ic->n_a = 0;
+    int mx = -1;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int w = win[i];
+        int col = st[w] & COLOR_MASK;
+        st[w] = col;
+        mx = max(mx, col);
+        int k = Acc<D2>::nets_count(g, w);
+        for (int j = 0; j < k; j++) {
+            int v = Acc<D2>::net_at(g, w, j);
+            if (col < 64) atomicOr((unsigned long long *)&mask0[v], 1ull << col);
+            if (set_once(cn_bits, v)) cn[atomicAdd(&ic->n_cn, 1)] = v;
+        }
+    }
+    mx = wave_max(mx);
+    if (lane_id() == 0 && mx >= 0) max_to(&ctrl->pad[0], mx);
+}
+
+// Over the worklist of a full round whose removal ran net-side: losers keep
+// their proposal (lose flag cleared), winners are applied as in k_inc_apply.
+template <bool D2>
+__global__ void k_inc_apply_full(Graph g, IncCtrl *ic, Ctrl *ctrl, int par, const int *W, int *st, uint8_t *lose,
+                                 uint64_t *mask0, unsigned *cn_bits, int *cn)
+{
+    const int n = ctrl->n_w[par];
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->n_heavy = 0;
+    int mx = -1, wins = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int w = W[i];
+        if (lose[w]) {
+            lose[w] = 0;
+            continue;
+        }
+        int col = st[w] & COLOR_MASK;
+        st[w] = col;
+        mx = max(mx, col);
+        wins++;
+        int k = Acc<D2>::nets_count(g, w);
+        for (int j = 0; j < k; j++) {
+            int v = Acc<D2>::net_at(g, w, j);
+            if (col < 64) atomicOr((unsigned long long *)&mask0[v], 1ull << col);
+            if (set_once(cn_bits, v)) cn[atomicAdd(&ic->n_cn, 1)] = v;
+        }
+    }
+    mx = wave_max(mx);
+    wins = wave_sum(wins);
+    if (lane_id() == 0) {
+        if (mx >= 0) max_to(&ctrl->pad[0], mx);
+        if (wins) atomicAdd(&ic->n_win, wins);
+    }
+}
+
+// Closes an incremental round: worklist size, record, host mirror.
+__global__ void k_inc_close(IncCtrl *ic, Ctrl *ctrl, int par, RoundRec *rec, int round, int *host)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int nw = ctrl->n_w[par];
+    if (nw == 0) {
+        ctrl->n_w[par ^ 1] = 0;
+        return;
+    }
+    int next = nw - ic->n_win;
+    ctrl->n_w[par ^ 1] = next;
+    ctrl->rounds += 1;
+    RoundRec &R = rec[round];
+    R.mode = 0;
+    R.w = nw;
+    R.losers = next;
+    R.max_color = ctrl->pad[0];
+    if (host) {
+        __atomic_store_n(&host[1], next, __ATOMIC_RELAXED);
+        __atomic_store_n(&host[2], ctrl->error, __ATOMIC_RELAXED);
+        __atomic_store_n(&host[3], ctrl->pad[0], __ATOMIC_RELAXED);
+        __threadfence_system();
+        __atomic_store_n(&host[0], round, __ATOMIC_RELAXED);
+        __threadfence_system();
+    }
+}
+
+// proposals still pending when the call stops become -1
+__global__ void k_drop_proposals(int *st, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        if (is_tent(st[i])) st[i] = -1;
 }
 
 // ---------------------------------------------------------------------------

@@ -273,3 +273,43 @@ def test_stencil_small(cuda, mask):
     ref = oracle.bgpc(g, net_color_mask=mask)
     res, colors = _gpu_bgpc(cuda, g, net_color_mask=mask)
     _compare_full(res, colors, ref)
+
+
+@pytest.mark.parametrize("shape", GRAPHS + [(4000, 4000, 30, 60, 14)], ids=lambda s: f"{s[0]}x{s[1]}k{s[2]}-{s[3]}")
+@pytest.mark.parametrize("mask", [0, 0b1, 0b101])
+def test_incremental_rounds(cuda, shape, mask):
+    """BGPC_INCREMENTAL recomputes only changed vertices: same results."""
+    n_a, n_b, kmin, kmax, seed = shape
+    g = synth.random_uniform(n_a, n_b, kmin, kmax, seed)
+    ref = oracle.bgpc(g, net_color_mask=mask)
+    res, colors = _gpu_bgpc(cuda, g, net_color_mask=mask, flags=bgpc.INCREMENTAL)
+    _compare_full(res, colors, ref)
+    for k in (1, 2, 3, 5):
+        part = oracle.bgpc(g, net_color_mask=mask, max_rounds=k)
+        res, colors = _gpu_bgpc(cuda, g, net_color_mask=mask, flags=bgpc.INCREMENTAL, max_rounds=k)
+        assert np.array_equal(colors, part.colors) and res.status == part.status
+
+
+def test_incremental_stencil_and_d2(cuda):
+    g = synth.stencil27(20)
+    ref = oracle.bgpc(g)
+    res, colors = _gpu_bgpc(cuda, g, flags=bgpc.INCREMENTAL)
+    _compare_full(res, colors, ref)
+    adj = synth.adjacency_from_edges(3000, [(i, (i * 7 + 3) % 3000) for i in range(3000)] +
+                                     [(i, (i + 1) % 3000) for i in range(3000)])
+    ref = oracle.d2gc(adj)
+    res, colors = _gpu_d2(cuda, adj, flags=bgpc.INCREMENTAL)
+    _compare_full(res, colors, ref)
+
+
+def test_profile_counters(cuda):
+    import torch
+    g = synth.stencil27(32)
+    A, B = bgpc.upload_bipartite(g)
+    out = torch.empty(g.n_a, dtype=torch.int32, device=cuda)
+    for kid in (bgpc.PROF_CONFLICT, bgpc.PROF_COLOR):
+        pr = bgpc.Profile(kid, 0, 0.0, 0.0)
+        r = bgpc.bgpc_color(A, B, None, out, prof=pr)
+        assert r.status == 0
+        # the lookahead may queue a few empty rounds after the last one
+        assert r.rounds <= pr.launches <= r.rounds + 8 and pr.ms > 0 and pr.bytes > 0
