@@ -46,7 +46,7 @@ def _load():
         lib = ctypes.CDLL(_LIB_PATH)
         P = ctypes.c_void_p
         i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
-        lib.oracle_color.argtypes = [i32, i32, P, P, P, P, i32, u64, i32, i32, i32, i32,
+        lib.oracle_color.argtypes = [i32, i32, P, P, P, P, i32, u64, i32, i32, i32, i32, i32,
                                      P, P, i32, P, P, P, P, P]
         lib.oracle_color.restype = ctypes.c_int
         lib.oracle_seq_greedy.argtypes = [i32, i32, P, P, P, P, i32, P]
@@ -123,7 +123,7 @@ class Result:
 
 
 def _run(n_a, n_b, a_off, a_idx, b_off, b_idx, d2, net_color_mask, policy, chunk,
-         max_rounds, start_round, init_colors, log_cap):
+         max_rounds, start_round, init_colors, log_cap, literal_ff=False):
     lib = _load()
     a_off, b_off = _c64(a_off), _c64(b_off)
     a_idx, b_idx = _c32(a_idx), _c32(b_idx)
@@ -136,7 +136,7 @@ def _run(n_a, n_b, a_off, a_idx, b_off, b_idx, d2, net_color_mask, policy, chunk
     lc = np.zeros(log_cap, dtype=np.int32)
     st = lib.oracle_color(n_a, n_b, _ptr(a_off), _ptr(a_idx), _ptr(b_off), _ptr(b_idx),
                           int(d2), ctypes.c_uint64(net_color_mask & (2 ** 64 - 1)), int(policy), int(chunk),
-                          int(max_rounds), int(start_round), _ptr(colors), _ptr(rounds),
+                          int(max_rounds), int(start_round), int(bool(literal_ff)), _ptr(colors), _ptr(rounds),
                           log_cap, _ptr(lm), _ptr(lw), _ptr(ll), _ptr(le), _ptr(lc))
     r = int(rounds[0])
     k = min(r, log_cap)
@@ -147,8 +147,10 @@ def _run(n_a, n_b, a_off, a_idx, b_off, b_idx, d2, net_color_mask, policy, chunk
 
 def bgpc(g, net_color_mask: int = 0, policy: int = FIRST_FIT, chunk: int = 64,
          max_rounds: int = 0, order=None, init_colors=None, start_round: int = 0,
-         log_cap: int = 4096) -> Result:
-    """Bipartite-graph partial coloring of V_A (Sections II-III, V)."""
+         log_cap: int = 4096, literal_ff: bool = False) -> Result:
+    """Bipartite-graph partial coloring of V_A (Sections II-III, V).
+    literal_ff: first-fit rounds gather F(w) member by member instead of
+    through per-net color sets (same result, much slower on large nets)."""
     n_a, n_b = int(g.n_a), int(g.n_b)
     a_off, a_idx, b_off, b_idx = g.a_off, g.a_idx, g.b_off, g.b_idx
     inv = None
@@ -159,7 +161,7 @@ def bgpc(g, net_color_mask: int = 0, policy: int = FIRST_FIT, chunk: int = 64,
         if init_colors is not None:
             init_colors = np.asarray(init_colors)[order]
     st, colors, r, log = _run(n_a, n_b, a_off, a_idx, b_off, b_idx, 0, net_color_mask, policy, chunk,
-                              max_rounds, start_round, init_colors, log_cap)
+                              max_rounds, start_round, init_colors, log_cap, literal_ff)
     if inv is not None:
         colors = colors[inv]
     return Result(st, colors, r, log)
@@ -167,7 +169,7 @@ def bgpc(g, net_color_mask: int = 0, policy: int = FIRST_FIT, chunk: int = 64,
 
 def d2gc(adj, net_color_mask: int = 0, policy: int = FIRST_FIT, chunk: int = 64,
          max_rounds: int = 0, order=None, init_colors=None, start_round: int = 0,
-         log_cap: int = 4096) -> Result:
+         log_cap: int = 4096, literal_ff: bool = False) -> Result:
     """Distance-2 coloring of a symmetric graph without self loops (Section IV)."""
     n = int(adj.n)
     off, idx = adj.off, adj.idx
@@ -178,7 +180,7 @@ def d2gc(adj, net_color_mask: int = 0, policy: int = FIRST_FIT, chunk: int = 64,
         if init_colors is not None:
             init_colors = np.asarray(init_colors)[order]
     st, colors, r, log = _run(n, n, off, idx, off, idx, 1, net_color_mask, policy, chunk,
-                              max_rounds, start_round, init_colors, log_cap)
+                              max_rounds, start_round, init_colors, log_cap, literal_ff)
     if inv is not None:
         colors = colors[inv]
     return Result(st, colors, r, log)

@@ -216,6 +216,90 @@ static int color_vertex_round(const graph_t *g, const int32_t *s, int32_t *t,
     return err ? OR_E_INTERNAL : OR_OK;
 }
 
+/* ascending int comparison for qsort */
+static int cmp_int(const void *a, const void *b)
+{
+    int x = *(const int *)a, y = *(const int *)b;
+    return (x > y) - (x < y);
+}
+
+/* is col in the ascending array a[0..n)? */
+static int sorted_has(const int32_t *a, int64_t n, int32_t col)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (a[mid] == col) return 1;
+        if (a[mid] < col) lo = mid + 1;
+        else hi = mid;
+    }
+    return 0;
+}
+
+/*
+ * Vertex-based first-fit through per-net color sets (same result as
+ * color_vertex_round with first-fit, for graphs whose neighbourhoods are too
+ * large to gather vertex by vertex).  F(w) is the union over v in nets(w) of
+ * C_v, the snapshot colors of v's colored members (w itself is uncolored, so
+ * excluding it changes nothing).  First-fit is the smallest color in no C_v.
+ * Every color below ff_v (the smallest color missing from C_v) lies in C_v and
+ * hence in F(w), so the search starts at the largest ff_v over w's nets; each
+ * candidate is then tested against every C_v (kept sorted).
+ */
+static int color_vertex_round_sets(const graph_t *g, const int32_t *s, int32_t *t,
+                                   const int32_t *W, int64_t nw)
+{
+    int err = 0;
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * ((size_t)g->n_b + 1));
+    int32_t *ff = (int32_t *)malloc(sizeof(int32_t) * ((size_t)g->n_b + 1));
+    if (!off || !ff) { free(off); free(ff); return OR_E_INTERNAL; }
+    off[0] = 0;
+    for (int32_t v = 0; v < g->n_b; v++) off[v + 1] = off[v] + vtxs_count(g, v);
+    int32_t *col = (int32_t *)malloc(sizeof(int32_t) * ((size_t)off[g->n_b] + 1));
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * ((size_t)g->n_b + 1));
+    if (!col || !cnt) { free(off); free(ff); free(col); free(cnt); return OR_E_INTERNAL; }
+    /* C_v, sorted, and ff_v */
+    #pragma omp parallel for schedule(dynamic, 256) reduction(| : err)
+    for (int32_t v = 0; v < g->n_b; v++) {
+        int32_t *c = col + off[v];
+        int64_t k = 0, kv = vtxs_count(g, v);
+        for (int64_t b = 0; b < kv; b++) {
+            int32_t x = vtx_at(g, v, b);
+            if (s[x] != -1) c[k++] = s[x];
+        }
+        qsort(c, (size_t)k, sizeof(int32_t), cmp_int);
+        int32_t f = 0;
+        for (int64_t i = 0; i < k; i++) {
+            if (i > 0 && c[i] == c[i - 1]) err |= 4;   /* colored members of a net differ */
+            if (c[i] == f) f++;
+        }
+        cnt[v] = k;
+        ff[v] = f;
+    }
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < nw; i++) {
+        int32_t w = W[i];
+        int64_t kn = nets_count(g, w);
+        int32_t c = 0;
+        for (int64_t a = 0; a < kn; a++) {
+            int32_t v = net_at(g, w, a);
+            if (ff[v] > c) c = ff[v];
+        }
+        for (;;) {
+            int used = 0;
+            for (int64_t a = 0; a < kn && !used; a++) {
+                int32_t v = net_at(g, w, a);
+                used = sorted_has(col + off[v], cnt[v], c);
+            }
+            if (!used) break;
+            c++;
+        }
+        t[w] = c;
+    }
+    free(off); free(ff); free(col); free(cnt);
+    return err ? OR_E_INTERNAL : OR_OK;
+}
+
 /*
  * Net-based coloring (Algorithm 8; Algorithm 9 in distance-2 mode): every net
  * with an uncolored member gathers the colors of its colored members into F,
@@ -330,6 +414,8 @@ static int remove_conflicts(const graph_t *g, const int32_t *t, uint8_t *lose, i
  *   colors     in: starting coloring (all -1, or a conflict-free partial one
  *              to resume from); out: the coloring reached.
  *   start_round  index of the first round (selects the net_color_mask bit).
+ *   literal_ff   first-fit rounds gather F(w) member by member (Algorithm 4
+ *              as printed) instead of through the per-net color sets.
  *   max_rounds   rounds to run at most (0: n_a + 65); status -6 when the
  *              worklist is still non-empty after them.
  *   log_*      optional per-round records (mode, |W_r|, losers, evicted
@@ -339,7 +425,7 @@ int oracle_color(int32_t n_a, int32_t n_b,
                  const int64_t *a_off, const int32_t *a_idx,
                  const int64_t *b_off, const int32_t *b_idx,
                  int32_t d2, uint64_t net_color_mask, int32_t policy, int32_t chunk,
-                 int32_t max_rounds, int32_t start_round,
+                 int32_t max_rounds, int32_t start_round, int32_t literal_ff,
                  int32_t *colors, int32_t *rounds_out,
                  int32_t log_cap, int32_t *log_mode, int64_t *log_w, int64_t *log_losers,
                  int64_t *log_evicted, int32_t *log_maxc)
@@ -377,8 +463,10 @@ int oracle_color(int32_t n_a, int32_t n_b,
         if (max_size + 2 > cap) cap = max_size + 2;
 
         memcpy(t, s, sizeof(int32_t) * (size_t)n_a);
-        int e = net_mode ? color_net_round(&g, s, t, owner, W, nw, policy, cap, max_size)
-                         : color_vertex_round(&g, s, t, W, nw, policy, chunk, cap);
+        int e;
+        if (net_mode) e = color_net_round(&g, s, t, owner, W, nw, policy, cap, max_size);
+        else if (policy == POL_FF && !literal_ff) e = color_vertex_round_sets(&g, s, t, W, nw);
+        else e = color_vertex_round(&g, s, t, W, nw, policy, chunk, cap);
         if (e) { status = e; break; }
         int64_t tmax = -1;
         for (int32_t u = 0; u < n_a; u++)

@@ -324,3 +324,29 @@ def test_color_stats_against_numpy():
         assert s["n_empty_below_max"] == valid.max() + 1 - len(vals)
         assert s["card_mean"] == pytest.approx(counts.mean(), rel=1e-12)
         assert s["card_std"] == pytest.approx(counts.std(), rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# the two first-fit forms of the oracle agree
+
+
+@pytest.mark.parametrize("kind", ["random", "skewed", "stencil", "rmat"])
+def test_first_fit_set_form_equals_literal_gather(kind):
+    """First-fit through per-net color sets (the default) and the member-by-
+    member gather of Algorithm 4 give the same rounds."""
+    if kind == "rmat":
+        adj = synth.rmat(10, 8, 0.57, 0.19, 0.19, seed=12)
+        for mask in (0, 1, 0b10):
+            a = oracle.d2gc(adj, net_color_mask=mask)
+            b = oracle.d2gc(adj, net_color_mask=mask, literal_ff=True)
+            assert np.array_equal(a.colors, b.colors) and a.rounds == b.rounds
+            assert np.array_equal(a.log["w"], b.log["w"])
+        return
+    g = {"random": lambda: synth.random_uniform(4000, 3000, 2, 40, 13),
+         "skewed": lambda: synth.skewed(8000, 8000, seed=14, kmax=1500),
+         "stencil": lambda: synth.stencil27(10)}[kind]()
+    for mask in (0, 1, 0b10):
+        a = oracle.bgpc(g, net_color_mask=mask)
+        b = oracle.bgpc(g, net_color_mask=mask, literal_ff=True)
+        assert np.array_equal(a.colors, b.colors) and a.rounds == b.rounds
+        assert np.array_equal(a.log["w"], b.log["w"])
