@@ -190,6 +190,77 @@ typedef struct {
 
 BGPC_API int color_stats(const int32_t *colors, int64_t n, void *stream, bgpc_stats *out);
 
+/*
+ * Batched coloring: many independent bipartite graphs in one persistent
+ * launch (vertex-based first-fit rounds, the schedule of the batched
+ * workload; other options return BGPC_E_UNSUPPORTED).  Workgroups take whole
+ * graphs, largest first, and run all of a graph's rounds; every graph's
+ * colors equal what bgpc_color returns for it alone.
+ *   items    host array; csr_A / csr_B / colors_out device pointers as in
+ *            bgpc_color; status and rounds are written per item
+ *   opts     NULL or: stream, max_rounds (per graph), flags 0
+ * Returns BGPC_OK, or the first non-OK item status (BGPC_E_NOT_CONVERGED).
+ */
+typedef struct {
+    bgpc_csr csr_A;
+    bgpc_csr csr_B;
+    int32_t *colors_out;
+    int32_t status;       /* out */
+    int32_t rounds;       /* out */
+} bgpc_batch_item;
+
+BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items, const bgpc_opts *opts);
+
+/*
+ * Serving: a session colors requests as they arrive (continuous batching).
+ * A worker thread admits waiting requests in arrival order while one of
+ * `max_slots` slots is free and its device pool of `mem_budget` bytes has room
+ * for the request (CSR arrays, colors, scratch); each admission pass launches
+ * its group (at most `max_group` requests, one workgroup each, vertex-based
+ * first-fit rounds) on the next of four streams, so groups admitted while
+ * others run overlap on the device.  A request's colors equal what
+ * bgpc_color returns for its graph alone.
+ *
+ * bgpc_request: host arrays (csr_A offsets / indices = a_off / a_idx, csr_B =
+ * b_off / b_idx), read when the request is admitted; colors_out (host,
+ * int32[n_a]) is written before its completion is reported; all must stay
+ * valid until then.  tag is returned with the completion.
+ * bgpc_session_create returns NULL on failure.  submit returns BGPC_E_OOM for
+ * a request larger than the pool.  poll hands out up to `cap` completions
+ * (waiting up to wait_ms for the first) and returns the session's error
+ * status (BGPC_OK normally).  destroy completes every submitted request,
+ * then frees the session.  Times are steady-clock seconds.
+ */
+typedef struct bgpc_session bgpc_session;
+
+typedef struct {
+    int32_t n_a;
+    int32_t n_b;
+    int64_t nnz;
+    const int32_t *a_off;
+    const int32_t *a_idx;
+    const int32_t *b_off;
+    const int32_t *b_idx;
+    int32_t *colors_out;
+    uint64_t tag;
+} bgpc_request;
+
+typedef struct {
+    uint64_t tag;
+    int32_t status;
+    int32_t rounds;
+    double t_submit;
+    double t_admit;
+    double t_done;
+} bgpc_completion;
+
+BGPC_API bgpc_session *bgpc_session_create(size_t mem_budget, int32_t max_slots, int32_t max_group,
+                                           int32_t max_rounds);
+BGPC_API int bgpc_session_submit(bgpc_session *session, const bgpc_request *request);
+BGPC_API int bgpc_session_poll(bgpc_session *session, bgpc_completion *out, int32_t cap, int32_t *n_out,
+                               int32_t wait_ms);
+BGPC_API void bgpc_session_destroy(bgpc_session *session);
+
 /* Human-readable name of a status code (static storage). */
 BGPC_API const char *bgpc_status_string(int status);
 

@@ -301,6 +301,89 @@ static int color_vertex_round_sets(const graph_t *g, const int32_t *s, int32_t *
 }
 
 /*
+ * Explicit neighbour lists nbor(u) (Section II: the vertices other than u
+ * sharing a net with u), built once per call when they are small (dense
+ * graphs, where walking the nets of every worklist vertex every round repeats
+ * the same vertices many times).  off[n_a + 1], idx: ascending per vertex.
+ */
+typedef struct { int64_t *off; int32_t *idx; } nbor_t;
+
+static int build_nbor(const graph_t *g, nbor_t *nb)
+{
+    int err = 0;
+    int64_t *cnt = (int64_t *)calloc((size_t)g->n_a + 1, sizeof(int64_t));
+    nb->off = (int64_t *)malloc(sizeof(int64_t) * ((size_t)g->n_a + 1));
+    nb->idx = NULL;
+    if (!cnt || !nb->off) { free(cnt); return -1; }
+    for (int pass = 0; pass < 2 && !err; pass++) {
+        #pragma omp parallel reduction(| : err)
+        {
+            int64_t *mark = (int64_t *)malloc(sizeof(int64_t) * ((size_t)g->n_a + 1));
+            if (!mark) err |= 1;
+            else {
+                for (int32_t i = 0; i <= g->n_a; i++) mark[i] = -1;
+                #pragma omp for schedule(dynamic, 64)
+                for (int32_t u = 0; u < g->n_a; u++) {
+                    int64_t k = 0, base = pass ? nb->off[u] : 0;
+                    int64_t kn = nets_count(g, u);
+                    for (int64_t a = 0; a < kn; a++) {
+                        int32_t v = net_at(g, u, a);
+                        int64_t kv = vtxs_count(g, v);
+                        for (int64_t b = 0; b < kv; b++) {
+                            int32_t x = vtx_at(g, v, b);
+                            if (x == u || mark[x] == u) continue;
+                            mark[x] = u;
+                            if (pass) nb->idx[base + k] = x;
+                            k++;
+                        }
+                    }
+                    if (pass) qsort(nb->idx + base, (size_t)k, sizeof(int32_t), cmp_int);
+                    else cnt[u] = k;
+                }
+                free(mark);
+            }
+        }
+        if (pass == 0 && !err) {
+            nb->off[0] = 0;
+            for (int32_t u = 0; u < g->n_a; u++) nb->off[u + 1] = nb->off[u] + cnt[u];
+            nb->idx = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nb->off[g->n_a] + 1));
+            if (!nb->idx) err |= 1;
+        }
+    }
+    free(cnt);
+    if (err) { free(nb->off); free(nb->idx); nb->off = NULL; nb->idx = NULL; return -1; }
+    return 0;
+}
+
+/* first-fit over F(w) = colors of the colored vertices of nbor(w) (Algorithm 2) */
+static int color_vertex_round_nbor(const graph_t *g, const nbor_t *nb, const int32_t *s, int32_t *t,
+                                   const int32_t *W, int64_t nw)
+{
+    int err = 0;
+    #pragma omp parallel reduction(| : err)
+    {
+        fset_t F;
+        if (fset_init(&F, (int64_t)g->n_a + 2)) err |= 1;
+        else {
+            #pragma omp for schedule(dynamic, 64)
+            for (int64_t i = 0; i < nw; i++) {
+                int32_t w = W[i];
+                fset_clear(&F);
+                for (int64_t k = nb->off[w]; k < nb->off[w + 1]; k++) {
+                    int32_t x = nb->idx[k];
+                    if (s[x] != -1 && s[x] <= g->n_a) fset_add(&F, s[x]);
+                }
+                int64_t col = 0;
+                while (fset_has(&F, col)) col++;
+                t[w] = (int32_t)col;
+            }
+            fset_free(&F);
+        }
+    }
+    return err ? OR_E_INTERNAL : OR_OK;
+}
+
+/*
  * Net-based coloring (Algorithm 8; Algorithm 9 in distance-2 mode): every net
  * with an uncolored member gathers the colors of its colored members into F,
  * queues the rest, and hands out colors from the top of [0, |vtxs(v)|)
@@ -440,11 +523,25 @@ int oracle_color(int32_t n_a, int32_t n_b,
     int32_t *W = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_a + 1));
     int32_t *owner = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_a + 1));
     uint8_t *lose = (uint8_t *)malloc((size_t)(n_a + 1));
+    nbor_t nb = {NULL, NULL};
     int status = OR_OK;
     if (!s || !t || !W || !owner || !lose) { status = OR_E_INTERNAL; goto done; }
 
     compute_owner(&g, owner);
     int64_t max_size = max_net_size(&g);
+    /* dense graphs: walking nets would revisit the same vertices many times;
+     * use explicit neighbour lists (at most n_a^2 entries) for first-fit */
+    if (policy == POL_FF && !literal_ff && (int64_t)n_a * n_a <= (int64_t)1 << 28) {
+        double walk = 0.0;
+        for (int32_t v = 0; v < n_b; v++) {
+            double k = (double)vtxs_count(&g, v);
+            walk += k * k;
+        }
+        if (walk > 4.0 * (double)n_a * (double)n_a && build_nbor(&g, &nb)) {
+            status = OR_E_INTERNAL;
+            goto done;
+        }
+    }
     int32_t r = 0;
     for (;;) {
         /* snapshot and worklist of the uncolored vertices, ascending rank */
@@ -465,6 +562,7 @@ int oracle_color(int32_t n_a, int32_t n_b,
         memcpy(t, s, sizeof(int32_t) * (size_t)n_a);
         int e;
         if (net_mode) e = color_net_round(&g, s, t, owner, W, nw, policy, cap, max_size);
+        else if (policy == POL_FF && !literal_ff && nb.off) e = color_vertex_round_nbor(&g, &nb, s, t, W, nw);
         else if (policy == POL_FF && !literal_ff) e = color_vertex_round_sets(&g, s, t, W, nw);
         else e = color_vertex_round(&g, s, t, W, nw, policy, chunk, cap);
         if (e) { status = e; break; }
@@ -497,6 +595,7 @@ int oracle_color(int32_t n_a, int32_t n_b,
     if (rounds_out) *rounds_out = r;
 done:
     free(s); free(t); free(W); free(owner); free(lose);
+    free(nb.off); free(nb.idx);
     return status;
 }
 

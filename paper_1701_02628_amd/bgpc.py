@@ -49,6 +49,22 @@ class Opts(ctypes.Structure):
                 ("rounds_out", ctypes.POINTER(ctypes.c_int32)), ("prof", ctypes.POINTER(Profile))]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("csr_A", Csr), ("csr_B", Csr), ("colors_out", ctypes.c_void_p), ("status", ctypes.c_int32),
+                ("rounds", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n_a", ctypes.c_int32), ("n_b", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("a_off", ctypes.c_void_p), ("a_idx", ctypes.c_void_p), ("b_off", ctypes.c_void_p),
+                ("b_idx", ctypes.c_void_p), ("colors_out", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("n_distinct", ctypes.c_int64), ("max_color", ctypes.c_int64), ("card_min", ctypes.c_int64),
                 ("card_max", ctypes.c_int64), ("n_empty_below_max", ctypes.c_int64),
@@ -75,13 +91,26 @@ def load():
         lib.d2gc_color.restype = ctypes.c_int
         lib.color_stats.argtypes = [P, ctypes.c_int64, P, ctypes.POINTER(Stats)]
         lib.color_stats.restype = ctypes.c_int
+        lib.bgpc_color_batch.argtypes = [ctypes.POINTER(BatchItem), ctypes.c_int32, ctypes.POINTER(Opts)]
+        lib.bgpc_color_batch.restype = ctypes.c_int
+        lib.bgpc_session_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        lib.bgpc_session_create.restype = ctypes.c_void_p
+        lib.bgpc_session_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(Request)]
+        lib.bgpc_session_submit.restype = ctypes.c_int
+        lib.bgpc_session_poll.argtypes = [ctypes.c_void_p, ctypes.POINTER(Completion), ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+        lib.bgpc_session_poll.restype = ctypes.c_int
+        lib.bgpc_session_destroy.argtypes = [ctypes.c_void_p]
+        lib.bgpc_session_destroy.restype = None
         lib.bgpc_status_string.argtypes = [ctypes.c_int]
         lib.bgpc_status_string.restype = ctypes.c_char_p
         _lib = lib
     return _lib
 
 
-EXPORTED = ("bgpc_opts_default", "bgpc_color", "d2gc_color", "color_stats", "bgpc_status_string")
+EXPORTED = ("bgpc_opts_default", "bgpc_color", "d2gc_color", "color_stats", "bgpc_status_string",
+            "bgpc_color_batch", "bgpc_session_create", "bgpc_session_submit", "bgpc_session_poll",
+            "bgpc_session_destroy")
 
 
 def status_string(code: int) -> str:
@@ -219,3 +248,73 @@ def color_stats(colors, stream=None) -> dict:
     return {"n_distinct": out.n_distinct, "max_color": out.max_color, "card_min": out.card_min,
             "card_max": out.card_max, "n_empty_below_max": out.n_empty_below_max,
             "card_mean": out.card_mean, "card_std": out.card_std}
+
+
+def bgpc_color_batch(graphs, colors, max_rounds=0, stream=None):
+    """Color many graphs in one persistent launch.
+
+    graphs: list of (csr_A, csr_B) DeviceCsr pairs; colors: list of int32 GPU
+    tensors (|V_A| each).  Returns (status, per-item statuses, per-item rounds).
+    """
+    lib = load()
+    n = len(graphs)
+    items = (BatchItem * max(n, 1))()
+    for i, ((A, B), c) in enumerate(zip(graphs, colors)):
+        items[i].csr_A = A.as_struct()
+        items[i].csr_B = B.as_struct()
+        items[i].colors_out = _dev_ptr(c, "colors").value
+    o, rounds, _, keep = _make_opts(0, FIRST_FIT, 64, max_rounds, 0, 0, stream, 0)
+    st = lib.bgpc_color_batch(items, n, ctypes.byref(o))
+    del keep
+    return int(st), [items[i].status for i in range(n)], [items[i].rounds for i in range(n)]
+
+
+class Session:
+    """Serving session (continuous batching) over host-resident requests.
+
+    submit() takes numpy int32 arrays; they and the colors array returned are
+    kept alive here until the request's completion has been polled.
+    """
+
+    def __init__(self, mem_budget: int, max_slots: int = 512, max_group: int = 256, max_rounds: int = 0):
+        self._lib = load()
+        self._h = self._lib.bgpc_session_create(int(mem_budget), int(max_slots), int(max_group), int(max_rounds))
+        if not self._h:
+            raise RuntimeError("bgpc_session_create failed")
+        self._live = {}
+
+    def submit(self, tag: int, n_a: int, n_b: int, a_off, a_idx, b_off, b_idx):
+        arrs = [np.ascontiguousarray(x, dtype=np.int32) for x in (a_off, a_idx, b_off, b_idx)]
+        colors = np.empty(max(n_a, 1), dtype=np.int32)
+        r = Request(int(n_a), int(n_b), int(arrs[1].shape[0]), arrs[0].ctypes.data, arrs[1].ctypes.data,
+                    arrs[2].ctypes.data, arrs[3].ctypes.data, colors.ctypes.data, int(tag))
+        self._live[int(tag)] = (arrs, colors)
+        st = self._lib.bgpc_session_submit(self._h, ctypes.byref(r))
+        if st != OK:
+            del self._live[int(tag)]
+        return st
+
+    def poll(self, cap: int = 256, wait_ms: int = 0):
+        """List of (tag, status, rounds, t_submit, t_admit, t_done, colors)."""
+        buf = (Completion * cap)()
+        n = ctypes.c_int32(0)
+        err = self._lib.bgpc_session_poll(self._h, buf, cap, ctypes.byref(n), int(wait_ms))
+        if err != OK:
+            raise RuntimeError(f"serving session error: {status_string(err)}")
+        out = []
+        for i in range(n.value):
+            c = buf[i]
+            arrs, colors = self._live.pop(int(c.tag))
+            out.append((int(c.tag), int(c.status), int(c.rounds), c.t_submit, c.t_admit, c.t_done, colors))
+        return out
+
+    def close(self):
+        if self._h:
+            self._lib.bgpc_session_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbgpc.so")
-SOURCES = ["bgpc.hip"]
+SOURCES = ["bgpc.hip", "batch.hip"]
 ARCH = os.environ.get("BGPC_OFFLOAD_ARCH", "gfx950")
 
 

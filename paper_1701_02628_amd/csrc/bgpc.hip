@@ -20,6 +20,12 @@
 #include "bgpc.h"
 #include "kernels.h"
 
+namespace bgpc {
+constexpr int DENSE_ROUTE_N = 4096;   // same bound as the batch kernel's dense mode
+int color_one_workgroup(const Graph &g, int *colors, int max_rounds, hipStream_t s, int log_cap,
+                        std::vector<int> *log, int *rounds_out);
+}  // namespace bgpc
+
 using namespace bgpc;
 
 namespace {
@@ -275,7 +281,7 @@ int run(const RunArgs &a)
     k_fill_i32<<<1, 64, 0, s>>>(shape, 0, 8);
     k_fill_i32<<<grid_for(rec_cap * (long)sizeof(RoundRec) / 4, nthr, di.cus * 4), nthr, 0, s>>>(
         (int *)rec, 0, rec_cap * (long)sizeof(RoundRec) / 4);
-    k_net_shape<D2><<<g_b, nthr, 0, s>>>(g, &shape[0], big, &shape[1]);
+    k_net_shape<D2><<<g_b, nthr, 0, s>>>(g, &shape[0], big, &shape[1], (unsigned long long *)&shape[4]);
     k_two_hop_bound<D2><<<g_a, nthr, 0, s>>>(g, &shape[2]);
     LAUNCH_CHECK();
     if (hipMemcpyAsync(h_shape, shape, sizeof(h_shape), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -287,6 +293,34 @@ int run(const RunArgs &a)
         const int max_net = h_shape[0];
         const int n_big = h_shape[1];
         const long two_hop = h_shape[2];
+        unsigned long long walk;
+        std::memcpy(&walk, &h_shape[4], sizeof(walk));
+        // small dense graphs under plain first-fit vertex rounds: one workgroup
+        // with an explicit conflict bit matrix (the batch kernel's dense mode)
+        if (!D2 && !any_net_round && policy == BGPC_FIRST_FIT && !resume && !(o.flags & BGPC_INCREMENTAL) &&
+            !o.prof && n_a <= DENSE_ROUTE_N && (double)walk > 4.0 * (double)n_a * (double)n_a) {
+            std::vector<int> lg;
+            int rounds = 0;
+            const int lcap = o.log ? std::min(o.log->cap, max_rounds) : 0;
+            st_code = color_one_workgroup(g, st, max_rounds, s, lcap, &lg, &rounds);
+            if (st_code == BGPC_OK || st_code == BGPC_E_NOT_CONVERGED) {
+                if (o.rounds_out) *o.rounds_out = rounds;
+                if (o.log) {
+                    int k = (int)lg.size() / 3;
+                    for (int i = 0; i < k; i++) {
+                        if (o.log->mode) o.log->mode[i] = 0;
+                        if (o.log->w_size) o.log->w_size[i] = lg[3 * i];
+                        if (o.log->losers) o.log->losers[i] = lg[3 * i + 1];
+                        if (o.log->evicted) o.log->evicted[i] = 0;
+                        if (o.log->max_color) o.log->max_color[i] = lg[3 * i + 2];
+                    }
+                    o.log->n = k;
+                }
+            }
+            ar.release();
+            hipStreamSynchronize(s);
+            return st_code;
+        }
         const int lds_total = std::min(di.lds_max, 65536);
         const int lds_budget = lds_total - 10240;   // beside the kernels' static LDS
         // bitmap capacity of the wide vertex paths, in bits

@@ -130,16 +130,19 @@ __global__ void k_init_ctrl(Ctrl *c, int n_w, int max_color)
 // Per-graph shape figures: largest net, and a bound on every vertex's
 // distance-2 neighbourhood (sum of the sizes of its nets); big-net list.
 template <bool D2>
-__global__ void k_net_shape(Graph g, int *max_net, int *big_list, int *n_big)
+__global__ void k_net_shape(Graph g, int *max_net, int *big_list, int *n_big, unsigned long long *walk)
 {
     int local = 0;
+    unsigned long long w = 0;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n_b; v += gridDim.x * blockDim.x) {
         int sz = Acc<D2>::size(g, v);
         local = max(local, sz);
+        w += (unsigned long long)sz * (unsigned long long)sz;
         if (sz > SMALL_NET) big_list[atomicAdd(n_big, 1)] = v;
     }
     local = wave_max(local);
     if (lane_id() == 0) max_to(max_net, local);
+    if (w) atomicAdd(walk, w);
 }
 
 template <bool D2>

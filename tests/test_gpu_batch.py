@@ -1,0 +1,144 @@
+"""Batched coloring: every graph of a batch equals the oracle and the
+single-graph call, whatever the rest of the batch is."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1701_02628_amd import bgpc, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(cuda, graphs, **kw):
+    import torch
+    dev = [bgpc.upload_bipartite(g) for g in graphs]
+    outs = [torch.full((g.n_a,), -7, dtype=torch.int32, device=cuda) for g in graphs]
+    st, statuses, rounds = bgpc.bgpc_color_batch(dev, outs, **kw)
+    torch.cuda.synchronize()
+    return st, statuses, rounds, [o.cpu().numpy() for o in outs]
+
+
+def test_batch_matches_oracle(cuda):
+    graphs = [synth.random_uniform(n_a, n_b, kmin, kmax, seed)
+              for (n_a, n_b, kmin, kmax, seed) in
+              [(1000, 1500, 3, 30, 1), (5003, 2000, 3, 30, 2), (2500, 9000, 2, 8, 3), (700, 700, 1, 4, 4),
+               (12000, 12000, 3, 30, 5), (64, 30, 5, 20, 6), (3000, 100, 20, 60, 7)]]
+    graphs.append(synth.stencil27(9))
+    graphs.append(synth.from_nets(50, []))
+    st, statuses, rounds, colors = _batch(cuda, graphs)
+    assert st == 0 and all(s == 0 for s in statuses)
+    for g, c, r in zip(graphs, colors, rounds):
+        ref = oracle.bgpc(g)
+        assert np.array_equal(c, ref.colors) and r == ref.rounds
+
+
+def test_batch_isolation_and_order(cuda):
+    import torch
+    graphs = [synth.batch_graph(i) for i in range(12)]
+    st, statuses, rounds, colors = _batch(cuda, graphs)
+    assert st == 0
+    # alone, through bgpc_color
+    for g, c, r in zip(graphs, colors, rounds):
+        A, B = bgpc.upload_bipartite(g)
+        out = torch.empty(g.n_a, dtype=torch.int32, device=cuda)
+        res = bgpc.bgpc_color(A, B, None, out)
+        assert res.status == 0 and res.rounds == r
+        assert np.array_equal(out.cpu().numpy(), c)
+    # the same graphs in another batch composition
+    st2, _, rounds2, colors2 = _batch(cuda, graphs[::-1][:7])
+    for c1, c2 in zip(colors[::-1][:7], colors2):
+        assert np.array_equal(c1, c2)
+    for g, c in zip(graphs[:4], colors[:4]):
+        ref = oracle.bgpc(g)
+        assert np.array_equal(c, ref.colors)
+
+
+def test_batch_not_converged(cuda):
+    graphs = [synth.random_uniform(3000, 3000, 3, 30, 9), synth.from_nets(4, [[0, 1, 2, 3]])]
+    st, statuses, rounds, colors = _batch(cuda, graphs, max_rounds=2)
+    assert st == bgpc.E_NOT_CONVERGED
+    for g, c, s, r in zip(graphs, colors, statuses, rounds):
+        ref = oracle.bgpc(g, max_rounds=2)
+        assert s == ref.status and r == 2
+        assert np.array_equal(c, ref.colors)
+
+
+def test_batch_rejects_other_schedules(cuda):
+    import ctypes
+    lib = bgpc.load()
+    o = bgpc.Opts()
+    lib.bgpc_opts_default(ctypes.byref(o))
+    o.net_color_mask = 1
+    items = (bgpc.BatchItem * 1)()
+    assert lib.bgpc_color_batch(items, 0, ctypes.byref(o)) == bgpc.E_UNSUPPORTED
+
+
+def _serve(graphs, rate, seed, budget=2 << 30, max_slots=64, max_group=16):
+    import time
+    s = bgpc.Session(budget, max_slots=max_slots, max_group=max_group)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(graphs)))
+    results = {}
+    t0 = time.perf_counter()
+    for i, g in enumerate(graphs):
+        while time.perf_counter() - t0 < arrivals[i]:
+            for c in s.poll(wait_ms=0):
+                results[c[0]] = c
+            time.sleep(0.0002)
+        assert s.submit(i, g.n_a, g.n_b, g.a_off, g.a_idx, g.b_off, g.b_idx) == 0
+    while len(results) < len(graphs):
+        for c in s.poll(wait_ms=100):
+            results[c[0]] = c
+        assert time.perf_counter() - t0 < 120
+    s.close()
+    return results
+
+
+def _mixed_graphs():
+    shapes = [(1000, 1500, 3, 30, 11), (5003, 2000, 3, 30, 12), (2500, 9000, 2, 8, 13), (700, 700, 1, 4, 14),
+              (12000, 12000, 3, 30, 15), (64, 30, 5, 20, 16), (3000, 100, 20, 60, 17), (300, 20000, 3, 30, 18),
+              (9000, 4000, 3, 30, 19), (200, 9000, 3, 30, 20), (20000, 30000, 3, 30, 21), (4000, 4000, 10, 40, 22)]
+    gs = [synth.random_uniform(*sh) for sh in shapes]
+    gs += [synth.stencil27(7), synth.from_nets(10, [])]
+    return gs
+
+
+def test_serving_same_as_alone(cuda):
+    """Requests arriving while others run: each result equals the oracle for
+    the graph alone, and a burstier mix with a tight pool gives the same."""
+    graphs = _mixed_graphs()
+    res = _serve(graphs * 2, rate=400.0, seed=7)
+    for i, g in enumerate(graphs * 2):
+        tag, st, rounds, t_sub, t_adm, t_done, colors = res[i]
+        assert st == 0 and t_sub <= t_adm <= t_done
+    for i, g in enumerate(graphs):
+        ref = oracle.bgpc(g)
+        for j in (i, i + len(graphs)):
+            assert res[j][2] == ref.rounds
+            assert np.array_equal(res[j][6][:g.n_a], ref.colors)
+    res2 = _serve(graphs[::-1], rate=5000.0, seed=8, budget=300 << 20, max_slots=5, max_group=3)
+    for i, g in enumerate(graphs[::-1]):
+        assert np.array_equal(res2[i][6][:g.n_a], res[len(graphs) - 1 - i][6][:g.n_a])
+
+
+def test_serving_batched_workload_graphs(cuda):
+    """The first graphs of the batched workload (some dense): served, batched
+    and alone agree; the oracle checks the ones it colors quickly."""
+    import torch
+    graphs = [synth.batch_graph(i) for i in range(16)]
+    res = _serve(graphs, rate=2000.0, seed=7)
+    st, statuses, rounds, colors = _batch(cuda, graphs)
+    assert st == 0
+    for i, g in enumerate(graphs):
+        assert res[i][1] == 0 and res[i][2] == rounds[i]
+        assert np.array_equal(res[i][6][:g.n_a], colors[i])
+    for i in (0, 2, 3, 4, 9):
+        ref = oracle.bgpc(graphs[i])
+        assert np.array_equal(colors[i], ref.colors) and rounds[i] == ref.rounds
+
+
+def test_serving_rejects_oversized(cuda):
+    s = bgpc.Session(1 << 20, max_slots=4, max_group=4)
+    g = synth.batch_graph(3)
+    assert s.submit(0, g.n_a, g.n_b, g.a_off, g.a_idx, g.b_off, g.b_idx) == bgpc.E_OOM
+    s.close()

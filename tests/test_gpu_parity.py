@@ -313,3 +313,21 @@ def test_profile_counters(cuda):
         assert r.status == 0
         # the lookahead may queue a few empty rounds after the last one
         assert r.rounds <= pr.launches <= r.rounds + 8 and pr.ms > 0 and pr.bytes > 0
+
+
+@pytest.mark.parametrize("shape", [(300, 20000, 3, 30, 5), (1200, 60000, 3, 30, 6), (64, 5000, 2, 9, 7)],
+                         ids=lambda s: f"{s[0]}x{s[1]}")
+def test_dense_small_graphs(cuda, shape):
+    """Few vertices, many nets: nearly every pair conflicts (one-workgroup
+    dense route); round by round on the first rounds, then whole."""
+    n_a, n_b, kmin, kmax, seed = shape
+    g = synth.random_uniform(n_a, n_b, kmin, kmax, seed)
+    ref = oracle.bgpc(g)
+    res, colors = _gpu_bgpc(cuda, g)
+    _compare_full(res, colors, ref)
+    for k in (1, 2, 7):
+        part = oracle.bgpc(g, max_rounds=k)
+        res, colors = _gpu_bgpc(cuda, g, max_rounds=k)
+        assert res.status == part.status and np.array_equal(colors, part.colors)
+        for key in ("w", "losers", "max_color"):
+            assert np.array_equal(res.log[key], part.log[key]), key
