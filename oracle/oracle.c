@@ -258,9 +258,20 @@ static int color_vertex_round_sets(const graph_t *g, const int32_t *s, int32_t *
     int32_t *col = (int32_t *)malloc(sizeof(int32_t) * ((size_t)off[g->n_b] + 1));
     int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * ((size_t)g->n_b + 1));
     if (!col || !cnt) { free(off); free(ff); free(col); free(cnt); return OR_E_INTERNAL; }
-    /* C_v, sorted, and ff_v */
+    /* C_v, sorted, and ff_v, for the nets of worklist vertices (no other
+     * net is looked at this round) */
+    uint8_t *need = (uint8_t *)calloc((size_t)g->n_b + 1, 1);
+    if (!need) { free(off); free(ff); free(col); free(cnt); return OR_E_INTERNAL; }
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < nw; i++) {
+        int64_t kn = nets_count(g, W[i]);
+        for (int64_t a = 0; a < kn; a++) need[net_at(g, W[i], a)] = 1;
+    }
     #pragma omp parallel for schedule(dynamic, 256) reduction(| : err)
     for (int32_t v = 0; v < g->n_b; v++) {
+        cnt[v] = 0;
+        ff[v] = 0;
+        if (!need[v]) continue;
         int32_t *c = col + off[v];
         int64_t k = 0, kv = vtxs_count(g, v);
         for (int64_t b = 0; b < kv; b++) {
@@ -296,7 +307,7 @@ static int color_vertex_round_sets(const graph_t *g, const int32_t *s, int32_t *
         }
         t[w] = c;
     }
-    free(off); free(ff); free(col); free(cnt);
+    free(off); free(ff); free(col); free(cnt); free(need);
     return err ? OR_E_INTERNAL : OR_OK;
 }
 

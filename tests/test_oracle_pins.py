@@ -350,3 +350,15 @@ def test_first_fit_set_form_equals_literal_gather(kind):
         b = oracle.bgpc(g, net_color_mask=mask, literal_ff=True)
         assert np.array_equal(a.colors, b.colors) and a.rounds == b.rounds
         assert np.array_equal(a.log["w"], b.log["w"])
+
+
+def test_first_fit_neighbour_list_form_equals_literal_gather():
+    """Dense graphs (few vertices, many overlapping nets) use explicit
+    neighbour lists for first-fit: same rounds as the literal gather."""
+    for shape in ((300, 20000, 3, 30, 5), (120, 3000, 2, 12, 6)):
+        g = synth.random_uniform(*shape)
+        a = oracle.bgpc(g)
+        b = oracle.bgpc(g, literal_ff=True)
+        assert np.array_equal(a.colors, b.colors) and a.rounds == b.rounds
+        assert np.array_equal(a.log["w"], b.log["w"])
+        assert a.rounds == g.n_a or len(np.unique(a.colors)) < g.n_a
