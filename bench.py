@@ -21,6 +21,9 @@ sys.path.insert(0, ROOT)
 WORKLOADS = {
     "stencil128": dict(config=1, mask=0, policy=0, desc="3D 27-point stencil 128^3, vertex-based first-fit rounds"),
     "random20k": dict(config=0, mask=0, policy=0, desc="20,000 x 20,000 random nets k~U{2..8}, vertex-based first-fit"),
+    "batch4096": dict(config=4, mask=0, policy=0,
+                      desc="4,096 graphs, |V_A|,|V_B| log-uniform in [1e3, 2e5], nets U{3..30}, seeds 1000+i; "
+                           "one persistent launch vs one call per graph; Poisson 2,000 req/s serving replay"),
 }
 
 
@@ -31,6 +34,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--workload", default="stencil128", choices=sorted(WORKLOADS))
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--batch-graphs", type=int, default=4096, help="graphs of the batch4096 workload")
+    p.add_argument("--rate", type=float, default=2000.0, help="serving arrivals per second (batch4096)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="first copy 256 MiB device to device (a kernel of known traffic for HBM counters)")
     return p.parse_args()
@@ -54,6 +59,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     wl = WORKLOADS[args.workload]
+    if args.workload == "batch4096":
+        run_batch(args, wl)
+        return
     g = synth.config(wl["config"])
     dev = torch.device("cuda:0")
     A, B = bgpc.upload_bipartite(g, dev)
@@ -143,6 +151,167 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, wl, out.cpu().numpy())
+    print(json.dumps(line), flush=True)
+
+
+def _gen(i):
+    from paper_1701_02628_amd import synth
+    return synth.batch_graph(i)
+
+
+def generate_batch(n):
+    import multiprocessing as mp
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with mp.get_context("fork").Pool(workers) as pool:
+        return list(pool.imap(_gen, range(n), chunksize=8))
+
+
+def batch_route(g):
+    """Route of one graph in bgpc_color_batch, restated from the library's
+    rule: 'dense' (conflict matrix), 'forbidden_bitmaps', 'net_masks', or
+    'whole_device' (bgpc_color on a second stream)."""
+    import numpy as np
+    sizes = np.diff(np.asarray(g.b_off, dtype=np.int64))
+    walk = float((sizes ** 2).sum())
+    heavy = walk > 128.0 * g.n_a or walk > 4.0 * g.n_a * g.n_a
+    if g.n_a > 0 and heavy and g.n_a <= 16384:
+        return "dense"
+    per = np.repeat(np.arange(g.n_a), np.diff(np.asarray(g.a_off, dtype=np.int64)))
+    wmax = int(np.bincount(per, weights=sizes[g.a_idx], minlength=g.n_a).max()) if g.n_a else 0
+    cap = min(wmax + 2, g.n_a + 1)
+    forb = g.n_a > 0 and heavy and g.n_a * ((cap + 31) // 32) * 4 <= (64 << 20)
+    if (forb and g.nnz > 50000) or g.nnz > 1000000:
+        return "whole_device"
+    return "forbidden_bitmaps" if forb else "net_masks"
+
+
+def batch_modes(graphs):
+    """How many graphs take each route of the batched call."""
+    out = {"dense": 0, "forbidden_bitmaps": 0, "net_masks": 0, "whole_device": 0}
+    for g in graphs:
+        out[batch_route(g)] += 1
+    return out
+
+
+def run_batch(args, wl):
+    """Batched graphs/s (one persistent launch) vs plain per-graph calls, and
+    p50 / p99 latency of a Poisson request stream through the serving loop."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_1701_02628_amd import bgpc
+    n = args.batch_graphs
+
+    def note(msg):
+        print(f"[bench batch] {msg}", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    graphs = generate_batch(n)
+    t_gen = time.perf_counter() - t0
+    note(f"generated {n} graphs in {t_gen:.1f} s")
+    dev = torch.device("cuda:0")
+    devg = [bgpc.upload_bipartite(g, dev) for g in graphs]
+    outs = [torch.empty(g.n_a, dtype=torch.int32, device=dev) for g in graphs]
+    total_nnz = sum(g.nnz for g in graphs)
+    stream = torch.cuda.current_stream()
+    # batched
+    st, statuses, rounds = bgpc.bgpc_color_batch(devg, outs, stream=stream)
+    if st != 0:
+        raise RuntimeError(f"bgpc_color_batch failed: {bgpc.status_string(st)}")
+    torch.cuda.synchronize()
+    note(f"warm-up batch done in {time.perf_counter() - t0 - t_gen:.1f} s")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        bgpc.bgpc_color_batch(devg, outs, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1) / args.steps
+    note(f"batched: {ms_batch:.1f} ms per batch")
+    batched = [o.cpu().numpy() for o in outs]
+    # plain: one bgpc_color per graph, same stream, same resident inputs
+    for (A, B), o in list(zip(devg, outs))[:8]:
+        bgpc.bgpc_color(A, B, None, o, stream=stream)
+    torch.cuda.synchronize()
+    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e2.record(stream)
+    for i, ((A, B), o) in enumerate(zip(devg, outs)):
+        r = bgpc.bgpc_color(A, B, None, o, stream=stream)
+        if r.status != 0:
+            raise RuntimeError("bgpc_color failed in the plain leg")
+        if i % 64 == 63:
+            note(f"plain: {i + 1} graphs")
+    e3.record(stream)
+    torch.cuda.synchronize()
+    ms_plain = e2.elapsed_time(e3)
+    same_plain = all(np.array_equal(o.cpu().numpy(), b) for o, b in zip(outs, batched))
+    note(f"plain: {ms_plain:.1f} ms for all graphs")
+    del devg, outs
+    torch.cuda.empty_cache()
+    # serving replay: requests in pinned host memory, Poisson arrivals
+    pinned = []
+    for g in graphs:
+        pinned.append([torch.from_numpy(np.ascontiguousarray(x, dtype=np.int32)).pin_memory()
+                       for x in (g.a_off, g.a_idx, g.b_off, g.b_idx)] +
+                      [torch.empty(max(g.n_a, 1), dtype=torch.int32).pin_memory()])
+    rng = np.random.Generator(np.random.PCG64(7))
+    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, size=n))
+    sess = bgpc.Session(8 << 30, max_slots=1024, max_group=256)
+    done = {}
+    stop = threading.Event()
+
+    def poller():
+        while len(done) < n and not stop.is_set():
+            for c in sess.poll(cap=1024, wait_ms=5):
+                done[c[0]] = c
+
+    th = threading.Thread(target=poller)
+    th.start()
+    ts = time.perf_counter()
+    for i, g in enumerate(graphs):
+        while time.perf_counter() - ts < arrivals[i]:
+            time.sleep(0.00005)
+        p = pinned[i]
+        if sess.submit(i, g.n_a, g.n_b, p[0], p[1], p[2], p[3], colors=p[4]) != 0:
+            raise RuntimeError("submit failed")
+    note("serving: all requests submitted")
+    th.join(timeout=600)
+    stop.set()
+    sess.close()
+    note(f"serving: {len(done)} completions")
+    lat = np.array([done[i][5] - done[i][3] for i in range(n)]) * 1e3
+    span = max(done[i][5] for i in range(n)) - min(done[i][3] for i in range(n))
+    same_served = all(np.array_equal(pinned[i][4][:graphs[i].n_a].numpy(), batched[i]) for i in range(n))
+    line = {
+        "metric": "BGPC nnz/s at 1 GPU & colors vs seq greedy; batched graphs/s + p99 latency",
+        "value": n / (ms_batch / 1e3), "unit": "graphs/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "batch4096", "description": wl["desc"], "graphs": n, "total_nnz": total_nnz},
+        "nnz_per_s_batched": total_nnz / (ms_batch / 1e3),
+        "plain_graphs_per_s": n / (ms_plain / 1e3), "plain_ms_all": ms_plain,
+        "batched_over_plain": ms_plain / ms_batch,
+        "graphs_by_mode": batch_modes(graphs),
+        "serve": {"rate_req_per_s": args.rate, "p50_ms": float(np.percentile(lat, 50)),
+                  "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+                  "graphs_per_s": n / span, "span_s": span},
+        "identical": {"plain_vs_batched": bool(same_plain), "served_vs_batched": bool(same_served)},
+        "rounds_max": int(max(rounds)), "generation_s": t_gen, "roofline": None,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        k = 0
+        t1 = time.perf_counter()
+        while k < n and (k == 0 or time.perf_counter() - t1 < 15.0):
+            oracle.bgpc(graphs[k])
+            k += 1
+        dt = time.perf_counter() - t1
+        note(f"cpu baseline: {k} graphs in {dt:.1f} s")
+        line["cpu_baseline"] = {"value": k / dt, "unit": "graphs/s", "cores": oracle.num_threads(), "kind": "oracle",
+                                "sample": f"the first {k} graphs of the batch (graphs in index order until 15 s "
+                                          "of oracle time), one oracle call each"}
     print(json.dumps(line), flush=True)
 
 

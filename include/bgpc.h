@@ -191,15 +191,29 @@ typedef struct {
 BGPC_API int color_stats(const int32_t *colors, int64_t n, void *stream, bgpc_stats *out);
 
 /*
- * Batched coloring: many independent bipartite graphs in one persistent
- * launch (vertex-based first-fit rounds, the schedule of the batched
- * workload; other options return BGPC_E_UNSUPPORTED).  Workgroups take whole
- * graphs, largest first, and run all of a graph's rounds; every graph's
- * colors equal what bgpc_color returns for it alone.
+ * Batched coloring: many independent bipartite graphs, the vertex-based
+ * first-fit rounds of Algorithm 1 for each (other options return
+ * BGPC_E_UNSUPPORTED).  Every graph's colors and rounds equal what
+ * bgpc_color returns for it alone.  A shape pass on the device measures each
+ * graph (and checks its arrays, below); then one persistent launch gives whole
+ * graphs, largest first, to workgroups that run all of a graph's rounds.  Per
+ * graph the workgroup keeps per-net masks of colors 0..127 (sparse graphs),
+ * a conflict bit matrix (n_A <= 16384 and colors expected past 127, or nets
+ * overlapping more than the vertex pairs), or per-vertex forbidden-color
+ * bitmaps.  Graphs that one workgroup would color far slower than the whole
+ * device (more than 10^6 memberships, or colors past 127 on more than 16384
+ * vertices with more than 5 * 10^4 memberships) are colored by bgpc_color on a
+ * second stream while the launch runs.
  *   items    host array; csr_A / csr_B / colors_out device pointers as in
  *            bgpc_color; status and rounds are written per item
- *   opts     NULL or: stream, max_rounds (per graph), flags 0
+ *   opts     NULL or: stream, max_rounds (per graph), flags 0 or BGPC_STRICT
+ * Checks: offsets start at 0, never decrease and end at nnz, indices in range
+ * (else BGPC_E_INVALID for the batch, that item's status BGPC_E_INVALID and
+ * nothing colored).  The two CSRs must be transposes of each other, with
+ * sorted rows; unlike bgpc_color this is not checked.
  * Returns BGPC_OK, or the first non-OK item status (BGPC_E_NOT_CONVERGED).
+ * Scratch: allocated per call, split into several launches when the sum over
+ * the graphs exceeds half of the free device memory.
  */
 typedef struct {
     bgpc_csr csr_A;
@@ -216,20 +230,29 @@ BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items, const bgp
  * A worker thread admits waiting requests in arrival order while one of
  * `max_slots` slots is free and its device pool of `mem_budget` bytes has room
  * for the request (CSR arrays, colors, scratch); each admission pass launches
- * its group (at most `max_group` requests, one workgroup each, vertex-based
- * first-fit rounds) on the next of four streams, so groups admitted while
- * others run overlap on the device.  A request's colors equal what
- * bgpc_color returns for its graph alone.
+ * its group (at most `max_group` requests, one workgroup each, the rounds and
+ * per-graph modes of bgpc_color_batch) on the next of four streams, so
+ * groups admitted while others run overlap on the device.  A request
+ * completes as soon as its own graph is done: its workgroup copies the colors
+ * to host memory and then sets a done word that the worker polls.  Requests
+ * that bgpc_color_batch would give to the whole device are colored by
+ * bgpc_color on a second thread and stream, one at a time; their arrays are
+ * allocated outside the pool.  A request's colors equal what bgpc_color
+ * returns for its graph alone.
  *
  * bgpc_request: host arrays (csr_A offsets / indices = a_off / a_idx, csr_B =
- * b_off / b_idx), read when the request is admitted; colors_out (host,
- * int32[n_a]) is written before its completion is reported; all must stay
- * valid until then.  tag is returned with the completion.
- * bgpc_session_create returns NULL on failure.  submit returns BGPC_E_OOM for
- * a request larger than the pool.  poll hands out up to `cap` completions
- * (waiting up to wait_ms for the first) and returns the session's error
- * status (BGPC_OK normally).  destroy completes every submitted request,
- * then frees the session.  Times are steady-clock seconds.
+ * b_off / b_idx), read at submit (shape and checks, as in bgpc_color_batch)
+ * and when the request is admitted; colors_out (host, int32[n_a]) is written
+ * before its completion is reported; all must stay valid until then.  With
+ * BGPC_REQ_PINNED every array is pinned host memory (hipHostMalloc) and is
+ * copied directly, without the session's staging area.  tag is returned with
+ * the completion.
+ * bgpc_session_create returns NULL on failure.  submit returns BGPC_E_INVALID
+ * for malformed arrays and BGPC_E_OOM for a request larger than the pool.
+ * poll hands out up to `cap` completions (waiting up to wait_ms for the
+ * first) and returns the session's error status (BGPC_OK normally).  destroy
+ * completes every submitted request, then frees the session.  Times are
+ * steady-clock seconds.
  */
 typedef struct bgpc_session bgpc_session;
 
@@ -243,7 +266,13 @@ typedef struct {
     const int32_t *b_idx;
     int32_t *colors_out;
     uint64_t tag;
+    uint32_t flags;       /* BGPC_REQ_PINNED: the arrays above are pinned host memory */
+    uint32_t reserved;
 } bgpc_request;
+
+enum {
+    BGPC_REQ_PINNED = 1u  /* upload / download directly, without the session's staging copy */
+};
 
 typedef struct {
     uint64_t tag;

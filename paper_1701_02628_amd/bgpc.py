@@ -57,7 +57,11 @@ class BatchItem(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("n_a", ctypes.c_int32), ("n_b", ctypes.c_int32), ("nnz", ctypes.c_int64),
                 ("a_off", ctypes.c_void_p), ("a_idx", ctypes.c_void_p), ("b_off", ctypes.c_void_p),
-                ("b_idx", ctypes.c_void_p), ("colors_out", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
+                ("b_idx", ctypes.c_void_p), ("colors_out", ctypes.c_void_p), ("tag", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+REQ_PINNED = 1
 
 
 class Completion(ctypes.Structure):
@@ -283,11 +287,23 @@ class Session:
             raise RuntimeError("bgpc_session_create failed")
         self._live = {}
 
-    def submit(self, tag: int, n_a: int, n_b: int, a_off, a_idx, b_off, b_idx):
-        arrs = [np.ascontiguousarray(x, dtype=np.int32) for x in (a_off, a_idx, b_off, b_idx)]
-        colors = np.empty(max(n_a, 1), dtype=np.int32)
-        r = Request(int(n_a), int(n_b), int(arrs[1].shape[0]), arrs[0].ctypes.data, arrs[1].ctypes.data,
-                    arrs[2].ctypes.data, arrs[3].ctypes.data, colors.ctypes.data, int(tag))
+    def submit(self, tag: int, n_a: int, n_b: int, a_off, a_idx, b_off, b_idx, colors=None):
+        """numpy arrays (staged by the session), or pinned int32 CPU torch
+        tensors with a pinned `colors` tensor (uploaded directly)."""
+        import torch
+        if isinstance(a_off, torch.Tensor):
+            arrs = [a_off, a_idx, b_off, b_idx]
+            for t in arrs + [colors]:
+                if t.dtype != torch.int32 or t.is_cuda or not t.is_pinned() or not t.is_contiguous():
+                    raise TypeError("pinned requests need contiguous pinned int32 CPU tensors")
+            ptrs = [t.data_ptr() for t in arrs]
+            nnz, cptr, flags = int(a_idx.numel()), colors.data_ptr(), REQ_PINNED
+        else:
+            arrs = [np.ascontiguousarray(x, dtype=np.int32) for x in (a_off, a_idx, b_off, b_idx)]
+            colors = np.empty(max(n_a, 1), dtype=np.int32)
+            ptrs = [x.ctypes.data for x in arrs]
+            nnz, cptr, flags = int(arrs[1].shape[0]), colors.ctypes.data, 0
+        r = Request(int(n_a), int(n_b), nnz, ptrs[0], ptrs[1], ptrs[2], ptrs[3], cptr, int(tag), flags, 0)
         self._live[int(tag)] = (arrs, colors)
         st = self._lib.bgpc_session_submit(self._h, ctypes.byref(r))
         if st != OK:

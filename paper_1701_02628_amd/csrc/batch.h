@@ -6,36 +6,151 @@
 // A graph's rounds are the vertex-based first-fit rounds of Algorithm 1 with
 // the rules of bgpc_color (snapshot, lower rank keeps, losers -> -1): the
 // result of a graph depends on that graph only, never on the rest of the
-// batch or on which workgroup ran it.
+// batch, on its mode or on the workgroup that ran it.  Three modes, chosen per
+// graph from its shape (same results, different costs):
+//   MASKS  per-net masks of colors 0..127 held by colored members; first-fit
+//          ORs the masks of nets(w); removal scans the active nets
+//   FORB   per-vertex forbidden-color bitmaps: a winner sets its color in the
+//          bitmap of every vertex sharing a net with it; first-fit is the
+//          first clear bit; removal scans the active nets (graphs whose
+//          colors run far past 127)
+//   DENSE  an explicit conflict bit matrix (n_A <= DENSE_N); removal buckets
+//          the worklist by proposal and tests lower-ranked bucket members
+//          against the matrix (short list per small bucket, member bitmap per
+//          large one); the forbidden-color bitmaps take the winners' colors by
+//          pull (each loser tests the round's winners against its matrix row)
+//          or push (each winner walks its row), whichever touches less
+// A net stays active while it has two or more uncolored members: with one or
+// none left, no two of its members can ever propose in the same round again.
 #pragma once
+
+#include <algorithm>
 
 #include "common.h"
 
 namespace bgpc {
 
 constexpr int BATCH_BLOCK = 512;   // threads per workgroup
+constexpr int DENSE_N = 16384;     // largest graph of the DENSE mode
+constexpr int BUCKET_T = 32;       // DENSE: buckets up to this size are lists, larger ones bitmaps
+enum { MODE_MASKS = 0, MODE_FORB = 1, MODE_DENSE = 2 };
 
 struct BatchItem {
     int n_a, n_b;
     const int *a_off, *a_idx;   // nets(u)
     const int *b_off, *b_idx;   // vtxs(v)
     int *colors;                // int32[n_a]
-    char *scratch;              // own scratch (serving) or nullptr (the workgroup's slot)
+    char *scratch;              // batch_scratch_bytes(mode, n_a, n_b, cap) bytes
     int *log;                   // optional: per round (|W| at its start, losers, largest color after it)
     int log_cap;                // rounds the log can hold
     int max_rounds;
+    int mode;                   // MODE_*
+    int cap;                    // FORB / DENSE: every color stays below cap
     int status;                 // out: 0 ok, -6 not converged
     int rounds;                 // out
-    int dense;                  // out: 1 if the graph ran in dense mode
+    double walk;                // shape: sum over nets of |vtxs(v)|^2, or -1 if the arrays are malformed
+    int walk_max;               // shape: largest sum of |vtxs(v)| over the nets of one vertex
+    int nnz;                    // memberships
+    int *host_colors;           // optional, host memory: the colors, copied there when the graph is done
+    long long *host_done;       // optional, host memory: set to (rounds << 32) | (status + 256) after that copy
 };
 
-// Graphs with at most DENSE_N vertices whose nets overlap heavily (walking
-// every vertex's nets would visit far more memberships than there are vertex
-// pairs) run in dense mode: an explicit conflict bit matrix and per-vertex
-// forbidden-color bitmaps.
-constexpr int DENSE_N = 4096;
+__host__ __device__ inline long long words32(long long n) { return (n + 31) >> 5; }
+__host__ __device__ inline long long al256(long long x) { return (x + 255) & ~255ll; }
 
-__host__ __device__ inline int dense_words(int n) { return (n + 31) >> 5; }
+// Mode of a graph from its shape.  The first-fit color of u is at most the
+// number of other members of its nets, so colors stay below walk_max + 1
+// (and below n_a); FORB and DENSE size their bitmaps by that bound.  Graphs
+// whose colors are expected past the net masks (walk > 128 n_a) or whose
+// nets overlap so much that walking them costs more than the vertex pairs
+// (walk > 4 n_a^2) take DENSE when the matrix is small enough, else FORB.
+__host__ inline int batch_mode(int n_a, double walk, long long walk_max, int *cap)
+{
+    const long long c = std::min<long long>(walk_max + 2, (long long)n_a + 1);
+    const bool heavy = walk > 128.0 * (double)n_a || walk > 4.0 * (double)n_a * (double)n_a;
+    if (n_a > 0 && heavy && n_a <= DENSE_N) {
+        *cap = (int)c;
+        return MODE_DENSE;
+    }
+    if (n_a > 0 && heavy && (long long)n_a * words32(c) * 4 <= (64ll << 20)) {
+        *cap = (int)c;
+        return MODE_FORB;
+    }
+    *cap = 128;
+    return MODE_MASKS;
+}
+
+// words per conflict-matrix row (a multiple of 4 for 16-byte loads)
+__host__ __device__ inline long long dense_wpr(long long n) { return ((n + 127) >> 7) << 2; }
+
+__host__ __device__ inline long long batch_scratch_bytes(int mode, int n_a, int n_b, int cap)
+{
+    long long b = 2 * al256(4ll * (n_a + 1)) + al256(n_a + 1ll);
+    if (mode != MODE_DENSE) b += 2 * al256(4ll * (n_b + 1));
+    if (mode == MODE_MASKS) return b + al256(16ll * (n_b + 1));
+    b += al256(4ll * n_a * words32(cap)) + al256(4ll * (n_a + 2));
+    if (mode == MODE_DENSE) {
+        const long long wpr = dense_wpr(n_a);
+        b += al256(4ll * n_a * wpr) + 2 * al256(4ll * (cap + 2)) + al256(4ll * (cap + 2) * BUCKET_T) +
+             al256(4ll * (n_a / BUCKET_T + 2) * wpr) + al256(4ll * (n_a + 1));
+    }
+    return b;
+}
+
+struct Scratch {
+    int *w0, *w1;               // worklists
+    uint8_t *lose;              // loser flags
+    int *nl0, *nl1;             // active net lists (MASKS, FORB)
+    unsigned long long *mask;   // MASKS: two words per net
+    unsigned *forb;             // FORB, DENSE: n_a rows of words32(cap)
+    int *ff;                    // FORB, DENSE: last proposal per vertex
+    unsigned *adj;              // DENSE: n_a rows of dense_wpr(n_a) words
+    int *cnt, *slot;            // DENSE: bucket sizes, bitmap row of each large bucket
+    int *small;                 // DENSE: BUCKET_T members per small bucket
+    unsigned *bits;             // DENSE: member bitmaps of the large buckets
+    int *win;                   // DENSE: the round's winners
+};
+
+__device__ inline Scratch batch_scratch(const BatchItem &it)
+{
+    char *p = it.scratch;
+    Scratch sc = {};
+    sc.w0 = (int *)p;
+    p += al256(4ll * (it.n_a + 1));
+    sc.w1 = (int *)p;
+    p += al256(4ll * (it.n_a + 1));
+    sc.lose = (uint8_t *)p;
+    p += al256(it.n_a + 1ll);
+    if (it.mode != MODE_DENSE) {
+        sc.nl0 = (int *)p;
+        p += al256(4ll * (it.n_b + 1));
+        sc.nl1 = (int *)p;
+        p += al256(4ll * (it.n_b + 1));
+    }
+    if (it.mode == MODE_MASKS) {
+        sc.mask = (unsigned long long *)p;
+        return sc;
+    }
+    sc.forb = (unsigned *)p;
+    p += al256(4ll * it.n_a * words32(it.cap));
+    sc.ff = (int *)p;
+    p += al256(4ll * (it.n_a + 2));
+    if (it.mode == MODE_DENSE) {
+        const long long wpr = dense_wpr(it.n_a);
+        sc.adj = (unsigned *)p;
+        p += al256(4ll * it.n_a * wpr);
+        sc.cnt = (int *)p;
+        p += al256(4ll * (it.cap + 2));
+        sc.slot = (int *)p;
+        p += al256(4ll * (it.cap + 2));
+        sc.small = (int *)p;
+        p += al256(4ll * (it.cap + 2) * BUCKET_T);
+        sc.bits = (unsigned *)p;
+        p += al256(4ll * (it.n_a / BUCKET_T + 2) * wpr);
+        sc.win = (int *)p;
+    }
+    return sc;
+}
 
 // raise *p to v; reads first so that equal values skip the atomic
 __device__ __forceinline__ void max_to(int *p, int v)
@@ -43,206 +158,90 @@ __device__ __forceinline__ void max_to(int *p, int v)
     if (*(volatile int *)p < v) atomicMax(p, v);
 }
 
-// scratch of one graph: two worklists, loser flags, done flags per net, two
-// mask words per net (colors 0..127 of its colored members); dense mode adds
-// the conflict bit matrix, the forbidden bitmaps, the first-fit cursor per
-// vertex and the color buckets
-struct BatchSlot {
-    int *w0, *w1;
-    uint8_t *lose;
-    uint8_t *done;
-    unsigned long long *mask;
-    unsigned *adj, *forb;
-    int *ff, *cnt, *cur, *list;
-    int dense_cap;   // vertices the dense arrays can hold
-};
-
-__host__ __device__ inline long long batch_slot_bytes(int cap_a, int cap_b)
+// Shape pass, one workgroup per graph: walk and walk_max of each item, and a
+// check that every offset lies in [0, nnz], offsets never decrease, and every
+// index is in range (walk = -1 otherwise).  An index is read only after the
+// offsets around it passed, so malformed arrays are never followed.
+__global__ void __launch_bounds__(BATCH_BLOCK) k_batch_shape(BatchItem *items, int n_items)
 {
-    auto al = [](long long x) { return (x + 255) & ~255ll; };
-    long long dn = cap_a < DENSE_N ? cap_a : DENSE_N;
-    long long dense = 2 * al(4ll * dn * dense_words((int)dn)) + 4 * al(4ll * (dn + 2));
-    return 2 * al(4ll * (cap_a + 1)) + al(16ll * (cap_b + 1)) + al(cap_a + 1ll) + al(cap_b + 1ll) + dense;
-}
-
-__device__ inline BatchSlot batch_slot(char *p, int cap_a, int cap_b)
-{
-    auto al = [](long long x) { return (x + 255) & ~255ll; };
-    BatchSlot sl;
-    sl.w0 = (int *)p;
-    p += al(4ll * (cap_a + 1));
-    sl.w1 = (int *)p;
-    p += al(4ll * (cap_a + 1));
-    sl.mask = (unsigned long long *)p;
-    p += al(16ll * (cap_b + 1));
-    sl.lose = (uint8_t *)p;
-    p += al(cap_a + 1ll);
-    sl.done = (uint8_t *)p;
-    p += al(cap_b + 1ll);
-    const long long dn = cap_a < DENSE_N ? cap_a : DENSE_N;
-    sl.dense_cap = (int)dn;
-    sl.adj = (unsigned *)p;
-    p += al(4ll * dn * dense_words((int)dn));
-    sl.forb = (unsigned *)p;
-    p += al(4ll * dn * dense_words((int)dn));
-    sl.ff = (int *)p;
-    p += al(4ll * (dn + 2));
-    sl.cnt = (int *)p;
-    p += al(4ll * (dn + 2));
-    sl.cur = (int *)p;
-    p += al(4ll * (dn + 2));
-    sl.list = (int *)p;
-    return sl;
-}
-
-// Dense mode: all rounds of one graph.  adj row u holds bit x iff x != u
-// shares a net with u; forb row u holds bit c iff a colored vertex of u's
-// row has color c (colors stay below n_a in first-fit rounds).  A round:
-// first-fit = first clear bit of forb[w] (from the vertex's last answer, which
-// can only grow); the worklist is bucketed by proposed color; w loses iff a
-// lower-ranked vertex of its bucket is in its adj row; winners set their
-// color in the forb rows of their adj row.  Returns the rounds run; *nw_out
-// the worklist left.
-__device__ int batch_dense(const BatchItem &it, const BatchSlot &sl, int *st, int *s_scan, int *s_maxc, int *nw_out)
-{
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int n = it.n_a, wpr = dense_words(n);
-    for (long long i = tid; i < (long long)n * wpr; i += nt) {
-        sl.adj[i] = 0;
-        sl.forb[i] = 0;
-    }
-    for (int u = tid; u < n; u += nt) sl.ff[u] = 0;
-    __syncthreads();
-    for (int v = tid; v < it.n_b; v += nt) {
-        int b = it.b_off[v], e = it.b_off[v + 1];
-        for (int i = b; i < e; i++) {
-            int x = it.b_idx[i];
+    __shared__ double s_walk;
+    __shared__ int s_max;
+    __shared__ int s_bad;
+    for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
+        const BatchItem it = items[k];
+        const int nnz = it.nnz;
+        if (threadIdx.x == 0) {
+            s_walk = 0.0;
+            s_max = 0;
+            s_bad = (it.a_off[0] != 0 || it.a_off[it.n_a] != nnz || it.b_off[0] != 0 || it.b_off[it.n_b] != nnz);
+        }
+        __syncthreads();
+        int bad = 0;
+        double walk = 0.0;
+        for (int v = threadIdx.x; v < it.n_b; v += blockDim.x) {
+            int b = it.b_off[v], e = it.b_off[v + 1];
+            if (b < 0 || e < b || e > nnz) {
+                bad = 1;
+                continue;
+            }
             for (int j = b; j < e; j++) {
-                int y = it.b_idx[j];
-                if (y != x) atomicOr(&sl.adj[(long long)x * wpr + (y >> 5)], 1u << (y & 31));
+                unsigned x = (unsigned)it.b_idx[j];
+                bad |= x >= (unsigned)it.n_a;
             }
+            walk += (double)(e - b) * (double)(e - b);
         }
-    }
-    __syncthreads();
-    int *W = sl.w0, *Wn = sl.w1;
-    int nw = n, rounds = 0, maxc = -1;
-    while (nw > 0 && rounds < it.max_rounds) {
-        // first-fit from the bitmaps; bucket counts
-        for (int c = tid; c <= n; c += nt) sl.cnt[c] = 0;
-        __syncthreads();
-        for (int i = tid; i < nw; i += nt) {
-            int w = W[i];
-            const unsigned *row = sl.forb + (long long)w * wpr;
-            int c = sl.ff[w];
-            for (;;) {
-                unsigned fr = ~row[c >> 5] & (~0u << (c & 31));
-                if (fr) {
-                    c = (c & ~31) + __builtin_ctz(fr);
-                    break;
+        if (__syncthreads_or(bad | s_bad) == 0) {
+            int mx = 0;
+            for (int u = threadIdx.x; u < it.n_a; u += blockDim.x) {
+                int b = it.a_off[u], e = it.a_off[u + 1];
+                if (b < 0 || e < b || e > nnz) {
+                    bad = 1;
+                    continue;
                 }
-                c = (c & ~31) + 32;
-            }
-            sl.ff[w] = c;
-            st[w] = TENT | c;
-            atomicAdd(&sl.cnt[c], 1);
-        }
-        __syncthreads();
-        // bucket starts (exclusive scan over colors 0..n)
-        int carry = 0;
-        for (int c0 = 0; c0 <= n; c0 += nt) {
-            int c = c0 + tid;
-            int v = c <= n ? sl.cnt[c] : 0;
-            int total;
-            int ex = block_excl_scan(v, s_scan, &total);
-            if (c <= n) {
-                sl.cnt[c] = carry + ex;
-                sl.cur[c] = carry + ex;
-            }
-            carry += total;
-        }
-        __syncthreads();
-        for (int i = tid; i < nw; i += nt) {
-            int w = W[i];
-            int c = st[w] & COLOR_MASK;
-            sl.list[atomicAdd(&sl.cur[c], 1)] = w;
-        }
-        __syncthreads();
-        // removal: a lower-ranked conflicting vertex with the same proposal
-        for (int i = tid; i < nw; i += nt) {
-            int w = W[i];
-            int c = st[w] & COLOR_MASK;
-            const unsigned *row = sl.adj + (long long)w * wpr;
-            int b = sl.cnt[c], e = sl.cur[c];
-            for (int j = b; j < e; j++) {
-                int x = sl.list[j];
-                if (x < w && ((row[x >> 5] >> (x & 31)) & 1u)) {
-                    sl.lose[w] = 1;
-                    break;
-                }
-            }
-        }
-        __syncthreads();
-        // apply + stable compaction; winners feed their neighbours' bitmaps
-        int base_out = 0;
-        for (int i0 = 0; i0 < nw; i0 += nt) {
-            int i = i0 + tid;
-            int flag = 0;
-            if (i < nw) {
-                int w = W[i];
-                if (sl.lose[w]) {
-                    sl.lose[w] = 0;
-                    flag = 1;
-                } else {
-                    int c = st[w] & COLOR_MASK;
-                    st[w] = c;
-                    max_to(s_maxc, c);
-                    const unsigned *row = sl.adj + (long long)w * wpr;
-                    const unsigned bit = 1u << (c & 31);
-                    for (int q = 0; q < wpr; q++) {
-                        unsigned m = row[q];
-                        while (m) {
-                            int y = (q << 5) + __builtin_ctz(m);
-                            m &= m - 1;
-                            atomicOr(&sl.forb[(long long)y * wpr + (c >> 5)], bit);
-                        }
+                long long sum = 0;
+                for (int q = b; q < e; q++) {
+                    unsigned v = (unsigned)it.a_idx[q];
+                    if (v >= (unsigned)it.n_b) {
+                        bad = 1;
+                        break;
                     }
+                    sum += it.b_off[v + 1] - it.b_off[v];
                 }
+                mx = max(mx, (int)min(sum, (long long)0x3fffffff));
             }
-            int total;
-            int pos = block_excl_scan(flag, s_scan, &total);
-            if (flag) Wn[base_out + pos] = W[i];
-            base_out += total;
+            for (int d = WAVE / 2; d > 0; d >>= 1) {
+                walk += __shfl_xor(walk, d);
+                mx = max(mx, __shfl_xor(mx, d));
+            }
+            if (lane_id() == 0) {
+                atomicAdd(&s_walk, walk);
+                atomicMax(&s_max, mx);
+            }
         }
+        if (bad) s_bad = 1;
         __syncthreads();
-        maxc = *s_maxc;
-        if (tid == 0 && it.log && rounds < it.log_cap) {
-            it.log[3 * rounds] = nw;
-            it.log[3 * rounds + 1] = base_out;
-            it.log[3 * rounds + 2] = maxc;
+        if (threadIdx.x == 0) {
+            items[k].walk = s_bad ? -1.0 : s_walk;
+            items[k].walk_max = s_max;
         }
-        int *tmp = W;
-        W = Wn;
-        Wn = tmp;
-        nw = base_out;
-        rounds++;
         __syncthreads();
     }
-    // proposals of vertices still uncolored (round cap reached) become -1
-    for (int i = tid; i < nw; i += nt) st[W[i]] = -1;
-    __syncthreads();
-    *nw_out = nw;
-    return rounds;
 }
 
-__device__ __forceinline__ int batch_block_scan(int v, int *scratch, int *total)
+// first clear bit of a forbidden-color row at or after c (one exists below
+// the row's width: a vertex has fewer colored neighbours than the width)
+__device__ __forceinline__ int first_clear(const unsigned *row, int c)
 {
-    return block_excl_scan(v, scratch, total);
+    for (;;) {
+        unsigned fr = ~row[c >> 5] & (~0u << (c & 31));
+        if (fr) return (c & ~31) + __builtin_ctz(fr);
+        c = (c & ~31) + 32;
+    }
 }
 
-// First-fit color of w for colors >= `from`: window by window of 128 colors,
-// walking the distance-2 neighbourhood (used once colors 0..127 are all
-// forbidden).
-__device__ int batch_first_fit_above(const BatchItem &it, const int *st, int w, int from)
+// MASKS: first-fit at or above `from` once colors 0..from-1 are forbidden,
+// window by window of 128 colors over the distance-2 neighbourhood
+__device__ int masks_first_fit_above(const BatchItem &it, const int *st, int w, int from)
 {
     for (int base = from;; base += 128) {
         unsigned long long m0 = 0, m1 = 0;
@@ -261,15 +260,185 @@ __device__ int batch_first_fit_above(const BatchItem &it, const int *st, int w, 
     }
 }
 
-__global__ void __launch_bounds__(BATCH_BLOCK) k_batch(BatchItem *items, const int *order, int n_items,
-                                                       int *next, char *slot_base, long long slot_bytes,
-                                                       int slot_cap_a, int slot_cap_b)
+// Removal over the active nets: in a net, the first proposer of a color in
+// rank order keeps it, later ones lose.  Nets with two or more proposals stay
+// active (appended to Ln through the LDS counter *s_nl).
+__device__ void net_removal(const BatchItem &it, const Scratch &sc, const int *st, const int *L, int nl, int *Ln,
+                            int *s_nl)
+{
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) {
+        const int v = L[i];
+        const int b = it.b_off[v], e = it.b_off[v + 1];
+        unsigned long long s0 = 0, s1 = 0;
+        bool wide = false;
+        int pending = 0;
+        for (int j = b; j < e; j++) {
+            int x = it.b_idx[j];
+            int s = st[x];
+            if (s >= 0 && !(s & TENT)) continue;
+            pending++;
+            if (s < 0) continue;
+            int c = s & COLOR_MASK;
+            if (c < 64) {
+                if ((s0 >> c) & 1ull) sc.lose[x] = 1;
+                s0 |= 1ull << c;
+            } else if (c < 128) {
+                if ((s1 >> (c - 64)) & 1ull) sc.lose[x] = 1;
+                s1 |= 1ull << (c - 64);
+            } else {
+                wide = true;
+            }
+        }
+        if (wide) {
+            // colors past 127: compare with the earlier proposers of the net
+            for (int j = b; j < e; j++) {
+                int x = it.b_idx[j];
+                int s = st[x];
+                if (s < 0 || !(s & TENT) || (s & COLOR_MASK) < 128) continue;
+                for (int j2 = b; j2 < j; j2++) {
+                    if (st[it.b_idx[j2]] == s) {
+                        sc.lose[x] = 1;
+                        break;
+                    }
+                }
+            }
+        }
+        if (pending >= 2) Ln[atomicAdd(s_nl, 1)] = v;
+    }
+}
+
+__device__ __forceinline__ bool adj_bit(const unsigned *row, int x) { return (row[x >> 5] >> (x & 31)) & 1u; }
+
+// DENSE removal.  Proposals of the round lie in [cmin, cmax]; the worklist is
+// bucketed by proposal.  w loses iff a lower-ranked member of its bucket is in
+// its matrix row: a small bucket (<= BUCKET_T members) is a list that w scans,
+// a large one a member bitmap that w ANDs with the part of its row below w.
+__device__ void dense_removal(const BatchItem &it, const Scratch &sc, const int *st, const int *W, int nw, int cmin,
+                              int cmax, int *s_nslot)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int R = cmax - cmin + 1;
+    const long long wpr = dense_wpr(it.n_a);
+    for (int c = tid; c < R; c += nt) sc.cnt[c] = 0;
+    if (tid == 0) *s_nslot = 0;
+    __syncthreads();
+    for (int i = tid; i < nw; i += nt) {
+        int w = W[i];
+        int c = (st[w] & COLOR_MASK) - cmin;
+        int k = atomicAdd(&sc.cnt[c], 1);
+        if (k < BUCKET_T) sc.small[c * BUCKET_T + k] = w;
+    }
+    __syncthreads();
+    for (int c = tid; c < R; c += nt)
+        if (sc.cnt[c] > BUCKET_T) sc.slot[c] = atomicAdd(s_nslot, 1);
+    __syncthreads();
+    const long long nbits = (long long)(*s_nslot) * wpr;
+    for (long long i = tid; i < nbits; i += nt) sc.bits[i] = 0;
+    __syncthreads();
+    for (int i = tid; i < nw; i += nt) {
+        int w = W[i];
+        int c = (st[w] & COLOR_MASK) - cmin;
+        if (sc.cnt[c] > BUCKET_T) atomicOr(&sc.bits[sc.slot[c] * wpr + (w >> 5)], 1u << (w & 31));
+    }
+    __syncthreads();
+    for (int i = tid; i < nw; i += nt) {
+        const int w = W[i];
+        const int c = (st[w] & COLOR_MASK) - cmin;
+        const int n = sc.cnt[c];
+        const unsigned *row = sc.adj + w * wpr;
+        bool lost = false;
+        if (n <= BUCKET_T) {
+            const int *lst = sc.small + c * BUCKET_T;
+            for (int k = 0; k < n && !lost; k++) {
+                int x = lst[k];
+                lost = x < w && adj_bit(row, x);
+            }
+        } else {
+            const unsigned *P = sc.bits + sc.slot[c] * wpr;
+            const int qw = w >> 5;
+            const int q4 = qw >> 2;
+            const uint4 *r4 = (const uint4 *)row, *p4 = (const uint4 *)P;
+            for (int q = 0; q < q4 && !lost; q += 2) {
+                uint4 a = r4[q], b = p4[q];
+                unsigned acc = (a.x & b.x) | (a.y & b.y) | (a.z & b.z) | (a.w & b.w);
+                if (q + 1 < q4) {
+                    uint4 a2 = r4[q + 1], b2 = p4[q + 1];
+                    acc |= (a2.x & b2.x) | (a2.y & b2.y) | (a2.z & b2.z) | (a2.w & b2.w);
+                }
+                lost = acc != 0;
+            }
+            for (int q = q4 * 4; q < qw && !lost; q++) lost = (row[q] & P[q]) != 0;
+            if (!lost) lost = (row[qw] & P[qw] & ((1u << (w & 31)) - 1u)) != 0;
+        }
+        if (lost) sc.lose[w] = 1;
+    }
+    __syncthreads();
+}
+
+// FORB: a winner's color enters the forbidden rows of the vertices that
+// share a net with it.
+__device__ void push_color_nets(const BatchItem &it, const Scratch &sc, int w, int c)
+{
+    const long long fw = words32(it.cap);
+    const unsigned bit = 1u << (c & 31);
+    unsigned *col_word = sc.forb + (c >> 5);
+    for (int k = it.a_off[w]; k < it.a_off[w + 1]; k++) {
+        int v = it.a_idx[k];
+        for (int j = it.b_off[v]; j < it.b_off[v + 1]; j++) {
+            int y = it.b_idx[j];
+            if (y != w) atomicOr(col_word + y * fw, bit);
+        }
+    }
+}
+
+// DENSE: the round's winners' colors enter the forbidden rows of their
+// neighbours.  Pull: each vertex left uncolored tests every winner against
+// its own row (its row is written by its thread only).  Push: each winner
+// walks its row and sets its color in every neighbour's row.
+__device__ void dense_propagate(const BatchItem &it, const Scratch &sc, const int *st, const int *Wn, int nw_next,
+                                int nwin, bool pull)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const long long fw = words32(it.cap), wpr = dense_wpr(it.n_a);
+    if (pull) {
+        for (int i = tid; i < nw_next; i += nt) {
+            const int y = Wn[i];
+            const unsigned *row = sc.adj + y * wpr;
+            unsigned *frow = sc.forb + y * fw;
+            for (int j = 0; j < nwin; j++) {
+                int x = sc.win[j];
+                if (adj_bit(row, x)) {
+                    int c = st[x];
+                    frow[c >> 5] |= 1u << (c & 31);
+                }
+            }
+        }
+        return;
+    }
+    for (int j = tid; j < nwin; j += nt) {
+        const int x = sc.win[j];
+        const int c = st[x];
+        const unsigned bit = 1u << (c & 31);
+        unsigned *col_word = sc.forb + (c >> 5);
+        const unsigned *row = sc.adj + x * wpr;
+        for (int q = 0; q < wpr; q++) {
+            unsigned m = row[q];
+            while (m) {
+                int y = (q << 5) + __builtin_ctz(m);
+                m &= m - 1;
+                atomicOr(col_word + y * fw, bit);
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(BATCH_BLOCK) k_batch(BatchItem *items, const int *order, int n_items, int *next)
 {
     __shared__ int s_scan[20];
     __shared__ int s_item;
-    __shared__ int s_nw;
-    __shared__ double s_walk;
     __shared__ int s_maxc;
+    __shared__ int s_nl;
+    __shared__ int s_cmin, s_cmax, s_nslot;
     const int tid = threadIdx.x, nt = blockDim.x;
     for (;;) {
         if (tid == 0) s_item = atomicAdd(next, 1);
@@ -277,156 +446,166 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch(BatchItem *items, const i
         const int k = s_item;
         __syncthreads();
         if (k >= n_items) break;
-        BatchItem it = items[order[k]];
-        const BatchSlot sl = it.scratch ? batch_slot(it.scratch, it.n_a, it.n_b)
-                                        : batch_slot(slot_base + (long long)blockIdx.x * slot_bytes, slot_cap_a,
-                                                     slot_cap_b);
+        const BatchItem it = items[order[k]];
+        const Scratch sc = batch_scratch(it);
         int *st = it.colors;
         const int n_a = it.n_a, n_b = it.n_b;
-        // dense mode when the net walk would exceed four times the vertex pairs
-        double walk = 0.0;
-        for (int v = tid; v < n_b; v += nt) {
-            double k = (double)(it.b_off[v + 1] - it.b_off[v]);
-            walk += k * k;
-        }
-        for (int d = WAVE / 2; d > 0; d >>= 1) walk += __shfl_xor(walk, d);
-        if (tid == 0) s_walk = 0.0;
-        __syncthreads();
-        if (lane_id() == 0) atomicAdd(&s_walk, walk);
-        __syncthreads();
-        const bool dense = n_a <= sl.dense_cap && s_walk > 4.0 * (double)n_a * (double)n_a;
-        __syncthreads();
-        if (dense) {
-            for (int u = tid; u < n_a; u += nt) {
-                st[u] = -1;
-                sl.w0[u] = u;
-                sl.lose[u] = 0;
-            }
-            __syncthreads();
-            int nw_left = 0;
-            if (tid == 0) s_maxc = -1;
-            __syncthreads();
-            int rounds = batch_dense(it, sl, st, s_scan, &s_maxc, &nw_left);
-            if (tid == 0) {
-                items[order[k]].rounds = rounds;
-                items[order[k]].status = nw_left == 0 ? 0 : -6;
-                items[order[k]].dense = 1;
-            }
-            __syncthreads();
-            continue;
-        }
+        const int mode = it.mode;
         for (int u = tid; u < n_a; u += nt) {
             st[u] = -1;
-            sl.w0[u] = u;
-            sl.lose[u] = 0;
+            sc.w0[u] = u;
+            sc.lose[u] = 0;
         }
-        for (int v = tid; v < n_b; v += nt) {
-            sl.mask[2 * v] = 0;
-            sl.mask[2 * v + 1] = 0;
-            sl.done[v] = 0;
+        if (mode != MODE_DENSE)
+            for (int v = tid; v < n_b; v += nt) sc.nl0[v] = v;
+        if (mode == MODE_MASKS) {
+            for (int v = tid; v < 2 * n_b; v += nt) sc.mask[v] = 0;
+        } else {
+            const long long fwords = (long long)n_a * words32(it.cap);
+            for (long long i = tid; i < fwords; i += nt) sc.forb[i] = 0;
+            for (int u = tid; u < n_a; u += nt) sc.ff[u] = 0;
         }
-        if (tid == 0) s_nw = n_a;
+        int avg_deg2 = 0;
+        if (mode == MODE_DENSE) {
+            // conflict matrix: bit y of row x iff x != y share a net
+            const long long wpr = dense_wpr(n_a);
+            for (long long i = tid; i < (long long)n_a * wpr; i += nt) sc.adj[i] = 0;
+            __syncthreads();
+            for (int v = tid; v < n_b; v += nt) {
+                int b = it.b_off[v], e = it.b_off[v + 1];
+                for (int i = b; i < e; i++) {
+                    int x = it.b_idx[i];
+                    for (int j = b; j < e; j++) {
+                        int y = it.b_idx[j];
+                        if (y != x) atomicOr(&sc.adj[x * wpr + (y >> 5)], 1u << (y & 31));
+                    }
+                }
+            }
+            __syncthreads();
+            int pc = 0;
+            for (long long i = tid; i < (long long)n_a * wpr; i += nt) pc += __builtin_popcount(sc.adj[i]);
+            long long tot = 0;
+            {
+                // block sum in 64 bits: popcounts can exceed 2^31 in total
+                unsigned long long v = (unsigned long long)pc;
+                for (int d = WAVE / 2; d > 0; d >>= 1) v += __shfl_xor(v, d);
+                __shared__ unsigned long long s_pc;
+                if (tid == 0) s_pc = 0;
+                __syncthreads();
+                if (lane_id() == 0) atomicAdd(&s_pc, v);
+                __syncthreads();
+                tot = (long long)s_pc;
+            }
+            avg_deg2 = n_a ? (int)(tot / n_a) : 0;
+        }
+        if (tid == 0) {
+            s_maxc = -1;
+            s_cmin = 0x7fffffff;
+            s_cmax = -1;
+        }
         __syncthreads();
-        int *W = sl.w0, *Wn = sl.w1;
+        int *W = sc.w0, *Wn = sc.w1;
+        int *L = sc.nl0, *Ln = sc.nl1;
+        int nw = n_a, nl = n_b;
         int rounds = 0;
-        int nw = s_nw;
-        if (tid == 0) s_maxc = -1;
-        __syncthreads();
+        const long long fw = words32(it.cap);
         while (nw > 0 && rounds < it.max_rounds) {
-            // coloring: OR of the nets' masks, first clear bit
+            // first-fit proposals against the snapshot
+            int lo = 0x7fffffff, hi = -1;
             for (int i = tid; i < nw; i += nt) {
                 int w = W[i];
-                unsigned long long m0 = 0, m1 = 0;
-                for (int q = it.a_off[w]; q < it.a_off[w + 1]; q++) {
-                    int v = it.a_idx[q];
-                    m0 |= sl.mask[2 * v];
-                    m1 |= sl.mask[2 * v + 1];
-                }
                 int col;
-                if (~m0) col = __builtin_ctzll(~m0);
-                else if (~m1) col = 64 + __builtin_ctzll(~m1);
-                else col = batch_first_fit_above(it, st, w, 128);
+                if (mode == MODE_MASKS) {
+                    unsigned long long m0 = 0, m1 = 0;
+                    for (int q = it.a_off[w]; q < it.a_off[w + 1]; q++) {
+                        int v = it.a_idx[q];
+                        m0 |= sc.mask[2 * v];
+                        m1 |= sc.mask[2 * v + 1];
+                    }
+                    if (~m0) col = __builtin_ctzll(~m0);
+                    else if (~m1) col = 64 + __builtin_ctzll(~m1);
+                    else col = masks_first_fit_above(it, st, w, 128);
+                } else {
+                    col = first_clear(sc.forb + w * fw, sc.ff[w]);
+                    sc.ff[w] = col;
+                }
                 st[w] = TENT | col;
+                lo = min(lo, col);
+                hi = max(hi, col);
             }
-            __syncthreads();
-            // removal, net side: first proposed holder of a color (rank order) keeps
-            for (int v = tid; v < n_b; v += nt) {
-                if (sl.done[v]) continue;
-                int b = it.b_off[v], e = it.b_off[v + 1];
-                unsigned long long s0 = 0, s1 = 0;
-                bool wide = false;
-                int pending = 0;
-                for (int j = b; j < e; j++) {
-                    int x = it.b_idx[j];
-                    int s = st[x];
-                    if (s < 0) {
-                        pending++;
-                        continue;
-                    }
-                    if (!(s & TENT)) continue;
-                    pending++;
-                    int c = s & COLOR_MASK;
-                    if (c < 64) {
-                        if ((s0 >> c) & 1ull) sl.lose[x] = 1;
-                        s0 |= 1ull << c;
-                    } else if (c < 128) {
-                        if ((s1 >> (c - 64)) & 1ull) sl.lose[x] = 1;
-                        s1 |= 1ull << (c - 64);
-                    } else {
-                        wide = true;
-                    }
+            if (mode == MODE_DENSE) {
+                for (int d = WAVE / 2; d > 0; d >>= 1) {
+                    lo = min(lo, __shfl_xor(lo, d));
+                    hi = max(hi, __shfl_xor(hi, d));
                 }
-                if (wide) {
-                    for (int j = b; j < e; j++) {
-                        int x = it.b_idx[j];
-                        int s = st[x];
-                        if (s < 0 || !(s & TENT) || (s & COLOR_MASK) < 128) continue;
-                        for (int j2 = b; j2 < j; j2++) {
-                            int t = st[it.b_idx[j2]];
-                            if (t >= 0 && (t & TENT) && (t & COLOR_MASK) == (s & COLOR_MASK)) {
-                                sl.lose[x] = 1;
-                                break;
-                            }
-                        }
-                    }
+                if (lane_id() == 0 && hi >= 0) {
+                    atomicMin(&s_cmin, lo);
+                    atomicMax(&s_cmax, hi);
                 }
-                if (pending == 0) sl.done[v] = 1;
             }
+            if (tid == 0) s_nl = 0;
             __syncthreads();
-            // apply + stable compaction of the losers
+            if (mode == MODE_DENSE) {
+                dense_removal(it, sc, st, W, nw, s_cmin, s_cmax, &s_nslot);
+            } else {
+                net_removal(it, sc, st, L, nl, Ln, &s_nl);
+                __syncthreads();
+            }
+            // winners keep their colors, losers -> -1 (stable compaction);
+            // DENSE also lists the winners
             int base_out = 0;
             for (int i0 = 0; i0 < nw; i0 += nt) {
                 int i = i0 + tid;
                 int flag = 0;
+                int w = -1;
                 if (i < nw) {
-                    int w = W[i];
-                    int s = st[w];
-                    if (sl.lose[w]) {
-                        sl.lose[w] = 0;
+                    w = W[i];
+                    if (sc.lose[w]) {
+                        sc.lose[w] = 0;
                         st[w] = -1;
                         flag = 1;
                     } else {
-                        int col = s & COLOR_MASK;
+                        int col = st[w] & COLOR_MASK;
                         st[w] = col;
                         max_to(&s_maxc, col);
-                        if (col < 128) {
-                            unsigned long long bit = 1ull << (col & 63);
-                            int wsel = col >> 6;
-                            for (int q = it.a_off[w]; q < it.a_off[w + 1]; q++)
-                                atomicOr(&sl.mask[2 * it.a_idx[q] + wsel], bit);
+                        if (mode == MODE_MASKS) {
+                            if (col < 128) {
+                                unsigned long long bit = 1ull << (col & 63);
+                                int half = col >> 6;
+                                for (int q = it.a_off[w]; q < it.a_off[w + 1]; q++)
+                                    atomicOr(&sc.mask[2 * it.a_idx[q] + half], bit);
+                            }
+                        } else if (mode == MODE_FORB) {
+                            push_color_nets(it, sc, w, col);
                         }
                     }
                 }
                 int total;
-                int pos = batch_block_scan(flag, s_scan, &total);
-                if (flag) Wn[base_out + pos] = W[i];
+                int pos = block_excl_scan(flag, s_scan, &total);
+                if (flag) Wn[base_out + pos] = w;
+                else if (i < nw && mode == MODE_DENSE) sc.win[i - base_out - pos] = w;
                 base_out += total;
             }
+            if (tid == 0) {
+                s_cmin = 0x7fffffff;
+                s_cmax = -1;
+            }
             __syncthreads();
+            if (mode == MODE_DENSE) {
+                const int nwin = nw - base_out;
+                dense_propagate(it, sc, st, Wn, base_out, nwin, base_out <= avg_deg2);
+                __syncthreads();
+            }
             if (tid == 0 && it.log && rounds < it.log_cap) {
                 it.log[3 * rounds] = nw;
                 it.log[3 * rounds + 1] = base_out;
                 it.log[3 * rounds + 2] = s_maxc;
+            }
+            if (mode != MODE_DENSE) {
+                nl = s_nl;
+                int *t = L;
+                L = Ln;
+                Ln = t;
             }
             int *tmp = W;
             W = Wn;
@@ -435,10 +614,23 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch(BatchItem *items, const i
             rounds++;
             __syncthreads();
         }
+        const int status = nw == 0 ? 0 : -6;
+        if (it.host_done) {
+            // hand the graph over to the host: colors first, then (after every
+            // wave's system-scope fence, which also writes back this graph's
+            // scratch from L2) the done word
+            if (it.host_colors)
+                for (int u = tid; u < n_a; u += nt) it.host_colors[u] = st[u];
+            __threadfence_system();
+            __syncthreads();
+            if (tid == 0) {
+                __atomic_store_n(it.host_done, ((long long)rounds << 32) | (unsigned)(status + 256), __ATOMIC_RELAXED);
+                __threadfence_system();
+            }
+        }
         if (tid == 0) {
             items[order[k]].rounds = rounds;
-            items[order[k]].status = nw == 0 ? 0 : -6;
-            items[order[k]].dense = 0;
+            items[order[k]].status = status;
         }
         __syncthreads();
     }

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -13,14 +14,36 @@ using namespace bgpc;
 
 namespace {
 
-const int kZero = 0;
-
 int device_cus()
 {
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 256;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) return 256;
     return v;
+}
+
+// A second stream per device for the graphs that take the whole-device path
+// while the persistent launch runs (default priority, created once).
+hipStream_t side_stream()
+{
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        streams[dev] = nullptr;
+    }
+    return streams[dev];
+}
+
+// Graphs that one workgroup would color far slower than the whole device:
+// many nets to rescan every round and colors past the net masks, or simply
+// many memberships.  They take bgpc_color (same rounds, same colors).
+bool whole_device(const BatchItem &b)
+{
+    return b.mode != MODE_DENSE && ((b.mode == MODE_FORB && b.nnz > 50000) || b.nnz > 1000000);
 }
 
 bool item_ok(const bgpc_batch_item &it)
@@ -41,7 +64,7 @@ namespace bgpc {
 int color_one_workgroup(const Graph &g, int *colors, int max_rounds, hipStream_t s, int log_cap,
                         std::vector<int> *log, int *rounds_out)
 {
-    const long long scr = batch_slot_bytes(g.n_a, g.n_b);
+    const long long scr = batch_scratch_bytes(MODE_DENSE, g.n_a, g.n_b, g.n_a + 1);
     const size_t o_tbl = 0, o_ord = 256, o_next = 512, o_log = 768;
     const size_t o_scr = o_log + (((size_t)3 * log_cap * 4 + 255) & ~(size_t)255);
     char *base = nullptr;
@@ -49,7 +72,7 @@ int color_one_workgroup(const Graph &g, int *colors, int max_rounds, hipStream_t
         (void)hipGetLastError();
         return BGPC_E_OOM;
     }
-    BatchItem h;
+    BatchItem h = {};
     h.n_a = g.n_a;
     h.n_b = g.n_b;
     h.a_off = g.a_off;
@@ -61,9 +84,9 @@ int color_one_workgroup(const Graph &g, int *colors, int max_rounds, hipStream_t
     h.log = log_cap ? (int *)(base + o_log) : nullptr;
     h.log_cap = log_cap;
     h.max_rounds = max_rounds;
+    h.mode = MODE_DENSE;
+    h.cap = g.n_a + 1;
     h.status = -1;
-    h.rounds = 0;
-    h.dense = 0;
     int zero[2] = {0, 0};
     int rc = BGPC_OK;
     if (hipMemcpyAsync(base + o_tbl, &h, sizeof(h), hipMemcpyHostToDevice, s) != hipSuccess ||
@@ -72,7 +95,7 @@ int color_one_workgroup(const Graph &g, int *colors, int max_rounds, hipStream_t
         rc = BGPC_E_HIP;
     } else {
         k_batch<<<1, BATCH_BLOCK, 0, s>>>((BatchItem *)(base + o_tbl), (const int *)(base + o_ord), 1,
-                                          (int *)(base + o_next), nullptr, 0, 0, 0);
+                                          (int *)(base + o_next));
         if (hipGetLastError() != hipSuccess) rc = BGPC_E_HIP;
         else if (hipMemcpyAsync(&h, base + o_tbl, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
                  hipStreamSynchronize(s) != hipSuccess)
@@ -111,10 +134,10 @@ extern "C" BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items
     hipStream_t s = (hipStream_t)o.stream;
 
     std::vector<BatchItem> h(n_items);
-    int cap_a = 1, cap_b = 1;
     for (int i = 0; i < n_items; i++) {
         const bgpc_batch_item &it = items[i];
         BatchItem &b = h[i];
+        b = BatchItem{};
         b.n_a = it.csr_A.n_rows;
         b.n_b = it.csr_B.n_rows;
         b.a_off = it.csr_A.offsets;
@@ -122,15 +145,9 @@ extern "C" BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items
         b.b_off = it.csr_B.offsets;
         b.b_idx = it.csr_B.indices;
         b.colors = it.colors_out;
-        b.scratch = nullptr;
-        b.log = nullptr;
-        b.log_cap = 0;
         b.max_rounds = o.max_rounds > 0 ? o.max_rounds : b.n_a + 65;
         b.status = -1;
-        b.rounds = 0;
-        b.dense = 0;
-        cap_a = std::max(cap_a, b.n_a);
-        cap_b = std::max(cap_b, b.n_b);
+        b.nnz = (int)it.csr_A.nnz;
     }
     // largest graphs first
     std::vector<int> order(n_items);
@@ -138,34 +155,124 @@ extern "C" BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         return items[x].csr_A.nnz + items[x].csr_A.n_rows > items[y].csr_A.nnz + items[y].csr_A.n_rows;
     });
-    const int grid = std::max(1, std::min(n_items, device_cus() * 2));
-    const long long slot = batch_slot_bytes(cap_a, cap_b);
-    const size_t tbl = ((size_t)n_items * sizeof(BatchItem) + 255) & ~(size_t)255;
-    const size_t ord = ((size_t)n_items * 4 + 255) & ~(size_t)255;
-    const size_t bytes = tbl + ord + 256 + (size_t)grid * slot;
-    char *base = nullptr;
-    if (hipMallocAsync((void **)&base, bytes, s) != hipSuccess) {
+    const int cus = device_cus();
+    const size_t tbl = al256((long long)n_items * sizeof(BatchItem));
+    const size_t ord = al256(4ll * n_items);
+    char *meta = nullptr;
+    if (hipMallocAsync((void **)&meta, tbl + ord + 256 * (size_t)(n_items + 1), s) != hipSuccess) {
         (void)hipGetLastError();
         return BGPC_E_OOM;
     }
-    BatchItem *d_items = (BatchItem *)base;
-    int *d_order = (int *)(base + tbl);
-    int *d_next = (int *)(base + tbl + ord);
-    char *slots = base + tbl + ord + 256;
+    BatchItem *d_items = (BatchItem *)meta;
+    int *d_order = (int *)(meta + tbl);
+    char *d_next = meta + tbl + ord;   // one queue counter per launch, 256 bytes apart
     int rc = BGPC_OK;
-    if (hipMemcpyAsync(d_items, h.data(), sizeof(BatchItem) * n_items, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(d_order, order.data(), 4 * (size_t)n_items, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(d_next, &kZero, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess) {
+    // shape pass: the mode and scratch of each graph depend on its net sizes
+    if (hipMemcpyAsync(d_items, h.data(), sizeof(BatchItem) * n_items, hipMemcpyHostToDevice, s) != hipSuccess)
         rc = BGPC_E_HIP;
-    } else {
-        k_batch<<<grid, BATCH_BLOCK, 0, s>>>(d_items, d_order, n_items, d_next, slots, slot, cap_a, cap_b);
-        if (hipGetLastError() != hipSuccess) rc = BGPC_E_HIP;
-        else if (hipMemcpyAsync(h.data(), d_items, sizeof(BatchItem) * n_items, hipMemcpyDeviceToHost, s) !=
-                     hipSuccess ||
-                 hipStreamSynchronize(s) != hipSuccess)
+    if (rc == BGPC_OK) {
+        k_batch_shape<<<std::max(1, std::min(n_items, cus * 4)), BATCH_BLOCK, 0, s>>>(d_items, n_items);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(h.data(), d_items, sizeof(BatchItem) * n_items, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
             rc = BGPC_E_HIP;
     }
-    (void)hipFreeAsync(base, s);
+    for (int i = 0; i < n_items && rc == BGPC_OK; i++)
+        if (h[i].walk < 0) {
+            items[i].status = BGPC_E_INVALID;
+            rc = BGPC_E_INVALID;
+        }
+    std::vector<long long> need(n_items);
+    for (int i = 0; i < n_items && rc == BGPC_OK; i++) {
+        h[i].mode = batch_mode(h[i].n_a, h[i].walk, h[i].walk_max, &h[i].cap);
+        need[i] = batch_scratch_bytes(h[i].mode, h[i].n_a, h[i].n_b, h[i].cap);
+    }
+    // the persistent launch takes the graphs in `order` minus the whole-device ones
+    std::vector<int> big, queue;
+    for (int k = 0; k < n_items; k++) (whole_device(h[order[k]]) ? big : queue).push_back(order[k]);
+    const int nq = (int)queue.size();
+    // launches over consecutive runs of the (largest-first) queue whose
+    // scratch fits the budget; each launch reuses the one scratch buffer
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 8ull << 30;
+    long long budget = std::max<long long>(1ll << 28, (long long)(free_b / 2));
+    std::vector<std::pair<int, int>> runs;
+    long long biggest = 0;
+    for (int k = 0; k < nq && rc == BGPC_OK;) {
+        long long sum = 0;
+        int e = k;
+        while (e < nq && (e == k || sum + need[queue[e]] <= budget)) sum += need[queue[e++]];
+        runs.push_back({k, e});
+        biggest = std::max(biggest, sum);
+        k = e;
+    }
+    char *scr = nullptr;
+    if (rc == BGPC_OK && !runs.empty() &&
+        hipMallocAsync((void **)&scr, (size_t)std::max(biggest, 256ll), s) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = BGPC_E_OOM;
+    }
+    for (size_t r = 0; r < runs.size() && rc == BGPC_OK; r++) {
+        long long off = 0;
+        for (int k = runs[r].first; k < runs[r].second; k++) {
+            h[queue[k]].scratch = scr + off;
+            off += need[queue[k]];
+        }
+    }
+    if (rc == BGPC_OK &&
+        (hipMemcpyAsync(d_items, h.data(), sizeof(BatchItem) * n_items, hipMemcpyHostToDevice, s) != hipSuccess ||
+         (nq && hipMemcpyAsync(d_order, queue.data(), 4 * (size_t)nq, hipMemcpyHostToDevice, s) != hipSuccess)))
+        rc = BGPC_E_HIP;
+    std::vector<int> zeros(64 * (runs.size() + 1), 0);
+    if (rc == BGPC_OK && !runs.empty() &&
+        hipMemcpyAsync(d_next, zeros.data(), 256 * runs.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        rc = BGPC_E_HIP;
+    // whole-device graphs on the side stream, after the caller's prior work on s
+    hipStream_t side = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    if (rc == BGPC_OK && !big.empty()) {
+        side = side_stream();
+        if (!side || hipEventCreateWithFlags(&ev_in, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ev_out, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(ev_in, s) != hipSuccess || hipStreamWaitEvent(side, ev_in, 0) != hipSuccess)
+            rc = BGPC_E_HIP;
+    }
+    for (size_t r = 0; r < runs.size() && rc == BGPC_OK; r++) {
+        const int n = runs[r].second - runs[r].first;
+        const int grid = std::max(1, std::min(n, cus * 2));
+        k_batch<<<grid, BATCH_BLOCK, 0, s>>>(d_items, d_order + runs[r].first, n, (int *)(d_next + 256 * r));
+        if (hipGetLastError() != hipSuccess) rc = BGPC_E_HIP;
+    }
+    std::vector<std::pair<int, int>> big_res(big.size(), {BGPC_OK, 0});
+    for (size_t j = 0; j < big.size() && rc == BGPC_OK; j++) {
+        const bgpc_batch_item &it = items[big[j]];
+        bgpc_opts po = o;
+        po.stream = side;
+        po.log = nullptr;
+        po.prof = nullptr;
+        int32_t r = 0;
+        po.rounds_out = &r;
+        int st = bgpc_color(&it.csr_A, &it.csr_B, nullptr, &po, it.colors_out);
+        if (st != BGPC_OK && st != BGPC_E_NOT_CONVERGED) rc = st;
+        big_res[j] = {st, r};
+    }
+    if (ev_out) {
+        if (hipEventRecord(ev_out, side) != hipSuccess || hipStreamWaitEvent(s, ev_out, 0) != hipSuccess)
+            rc = BGPC_E_HIP;
+    }
+    if (rc == BGPC_OK &&
+        (hipMemcpyAsync(h.data(), d_items, sizeof(BatchItem) * n_items, hipMemcpyDeviceToHost, s) != hipSuccess ||
+         hipStreamSynchronize(s) != hipSuccess))
+        rc = BGPC_E_HIP;
+    for (size_t j = 0; j < big.size(); j++) {
+        h[big[j]].status = big_res[j].first;
+        h[big[j]].rounds = big_res[j].second;
+    }
+    if (side) (void)hipStreamSynchronize(side);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (scr) (void)hipFreeAsync(scr, s);
+    (void)hipFreeAsync(meta, s);
     (void)hipStreamSynchronize(s);
     if (rc != BGPC_OK) return rc;
     for (int i = 0; i < n_items; i++) {
@@ -181,20 +288,24 @@ extern "C" BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items
 //
 // A worker thread owns a device pool of `mem_budget` bytes and a pinned host
 // staging area of the same size (same offsets).  Each pass it (1) retires
-// groups whose completion event has fired, (2) admits waiting requests in
-// arrival order while a slot is free and the pool has room for the request's
-// CSR arrays, colors and scratch, and (3) launches the admitted group on the
-// next of four compute streams: uploads, one k_batch launch (one workgroup
-// per graph), downloads of colors and statuses, completion event.  Requests
-// that arrive while other groups run join the next group, whose work overlaps
-// the running ones on the device.  A request's colors depend on its graph
+// every request whose done word (pinned host memory, written by the
+// workgroup that colored it, after the colors) is set, and every group whose
+// completion event fired (its table), (2) admits waiting requests in arrival
+// order while a slot is free and the pool has room for the request's CSR
+// arrays, colors and scratch, and (3) launches the admitted group on the next
+// of four compute streams: uploads, one k_batch launch (one workgroup per
+// graph).  Requests that arrive while other groups run join the next group,
+// whose work overlaps the running ones on the device, and each request
+// completes as soon as its own graph is done.  Graphs that one workgroup
+// would color far slower than the whole device go to a second thread that
+// runs bgpc_color for them one at a time on a stream of its own (their arrays
+// are allocated outside the pool).  A request's colors depend on its graph
 // only.
 
 #include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <map>
-#include <mutex>
 #include <thread>
 
 namespace {
@@ -205,15 +316,13 @@ double now_s()
     return duration_cast<duration<double>>(steady_clock::now().time_since_epoch()).count();
 }
 
-size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
-
 // first-fit allocator over [0, cap) with coalescing; 256-byte granules
 class RangeAlloc {
 public:
     explicit RangeAlloc(size_t cap) { free_[0] = cap & ~(size_t)255; }
     bool alloc(size_t bytes, size_t *off)
     {
-        bytes = al256(bytes);
+        bytes = (size_t)al256((long long)bytes);
         for (auto it = free_.begin(); it != free_.end(); ++it) {
             if (it->second >= bytes) {
                 *off = it->first;
@@ -227,7 +336,7 @@ public:
     }
     void release(size_t off, size_t bytes)
     {
-        bytes = al256(bytes);
+        bytes = (size_t)al256((long long)bytes);
         auto it = free_.emplace(off, bytes).first;
         auto nx = std::next(it);
         if (nx != free_.end() && it->first + it->second == nx->first) {
@@ -252,32 +361,70 @@ struct Req {
     double t_submit = 0, t_admit = 0, t_done = 0;
     size_t off = 0, bytes = 0;
     int status = 0, rounds = 0;
+    int mode = MODE_MASKS, cap = 128;
+    bool device = false;                 // whole-device path
+    volatile long long *done = nullptr;  // pinned done word (batched path)
     // layout inside the request's pool block: uploaded arrays first, then
-    // colors, then scratch
-    size_t o_aoff = 0, o_aidx = 0, o_boff = 0, o_bidx = 0, o_col = 0, o_scr = 0;
+    // colors, then scratch; the done word sits at o_done in the staging area
+    size_t o_aoff = 0, o_aidx = 0, o_boff = 0, o_bidx = 0, o_col = 0, o_scr = 0, o_done = 0;
 };
+
+// mode of a request's graph from its host arrays (the shape pass of the
+// batched path, on the submitting thread); false if the arrays are malformed
+bool host_mode(Req *q)
+{
+    const bgpc_request &r = q->r;
+    const long long nnz = r.nnz;
+    if (r.a_off[0] != 0 || r.a_off[r.n_a] != nnz || r.b_off[0] != 0 || r.b_off[r.n_b] != nnz) return false;
+    double walk = 0.0;
+    for (int v = 0; v < r.n_b; v++) {
+        if (r.b_off[v + 1] < r.b_off[v] || r.b_off[v + 1] > nnz) return false;
+        double sz = (double)(r.b_off[v + 1] - r.b_off[v]);
+        walk += sz * sz;
+    }
+    for (long long j = 0; j < nnz; j++)
+        if ((unsigned)r.b_idx[j] >= (unsigned)r.n_a) return false;
+    long long wmax = 0;
+    for (int u = 0; u < r.n_a; u++) {
+        if (r.a_off[u + 1] < r.a_off[u] || r.a_off[u + 1] > nnz) return false;
+        long long sum = 0;
+        for (int k = r.a_off[u]; k < r.a_off[u + 1]; k++) {
+            unsigned v = (unsigned)r.a_idx[k];
+            if (v >= (unsigned)r.n_b) return false;
+            sum += r.b_off[v + 1] - r.b_off[v];
+        }
+        wmax = std::max(wmax, std::min(sum, 0x3fffffffll));
+    }
+    q->mode = batch_mode(r.n_a, walk, wmax, &q->cap);
+    BatchItem b = {};
+    b.mode = q->mode;
+    b.nnz = (int)nnz;
+    q->device = whole_device(b);
+    return true;
+}
 
 void layout(Req *q)
 {
     const bgpc_request &r = q->r;
     size_t o = 0;
     q->o_aoff = o;
-    o += al256(4 * ((size_t)r.n_a + 1));
+    o += al256(4 * ((long long)r.n_a + 1));
     q->o_aidx = o;
-    o += al256(4 * (size_t)r.nnz + 4);
+    o += al256(4 * (long long)r.nnz + 4);
     q->o_boff = o;
-    o += al256(4 * ((size_t)r.n_b + 1));
+    o += al256(4 * ((long long)r.n_b + 1));
     q->o_bidx = o;
-    o += al256(4 * (size_t)r.nnz + 4);
+    o += al256(4 * (long long)r.nnz + 4);
     q->o_col = o;
-    o += al256(4 * ((size_t)r.n_a + 1));
+    o += al256(4 * ((long long)r.n_a + 1));
+    q->o_done = o;
+    o += 256;
     q->o_scr = o;
-    o += (size_t)batch_slot_bytes(r.n_a, r.n_b);
+    o += (size_t)batch_scratch_bytes(q->mode, r.n_a, r.n_b, q->cap);
     q->bytes = o;
 }
 
 struct Group {
-    std::vector<Req *> reqs;
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     size_t tbl_off = 0, tbl_bytes = 0;
@@ -291,32 +438,38 @@ struct bgpc_session {
     int max_slots = 0, max_group = 0, max_rounds = 0;
     char *dpool = nullptr;
     char *hpool = nullptr;
+    char *hpool_dev = nullptr;      // device view of hpool
     RangeAlloc *alloc = nullptr;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
+    hipStream_t dev_stream = nullptr;
     int rr = 0;
     int slots_used = 0;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_done, cv_dev;
     std::deque<Req *> submitted;    // guarded by mu
     std::vector<Req *> completed;   // guarded by mu
+    std::deque<Req *> dev_queue;    // guarded by mu
     std::deque<Req *> pending;      // worker only
+    std::vector<Req *> running;     // worker only: launched, done word not yet seen
     std::vector<Group *> inflight;  // worker only
-    std::thread worker;
+    std::thread worker, dev_worker;
     bool stop = false;              // guarded by mu
+    bool dev_stop = false;          // guarded by mu: set once the worker has handed over every request
     int error = 0;
 
     bool launch(std::vector<Req *> &grp);
-    void retire(Group *g);
+    void finish(Req *q);
     void loop();
+    void dev_loop();
+    void dev_run(Req *q);
 };
 
 bool bgpc_session::launch(std::vector<Req *> &grp)
 {
     const int n = (int)grp.size();
     Group *g = new Group();
-    g->reqs = grp;
-    const size_t o_ord = al256(sizeof(BatchItem) * n), o_next = o_ord + al256(4 * (size_t)n);
+    const size_t o_ord = al256((long long)sizeof(BatchItem) * n), o_next = o_ord + al256(4ll * n);
     g->tbl_bytes = o_next + 256;
     if (!alloc->alloc(g->tbl_bytes, &g->tbl_off)) {
         delete g;
@@ -341,12 +494,26 @@ bool bgpc_session::launch(std::vector<Req *> &grp)
         Req *q = grp[i];
         const bgpc_request &r = q->r;
         char *hb = hpool + q->off, *db = dpool + q->off;
-        std::memcpy(hb + q->o_aoff, r.a_off, 4 * ((size_t)r.n_a + 1));
-        if (r.nnz) std::memcpy(hb + q->o_aidx, r.a_idx, 4 * (size_t)r.nnz);
-        std::memcpy(hb + q->o_boff, r.b_off, 4 * ((size_t)r.n_b + 1));
-        if (r.nnz) std::memcpy(hb + q->o_bidx, r.b_idx, 4 * (size_t)r.nnz);
-        ok = ok && hipMemcpyAsync(db, hb, q->o_col, hipMemcpyHostToDevice, s) == hipSuccess;
+        if (r.flags & BGPC_REQ_PINNED) {
+            ok = ok && hipMemcpyAsync(db + q->o_aoff, r.a_off, 4 * ((size_t)r.n_a + 1), hipMemcpyHostToDevice, s) ==
+                           hipSuccess;
+            ok = ok && (!r.nnz || hipMemcpyAsync(db + q->o_aidx, r.a_idx, 4 * (size_t)r.nnz, hipMemcpyHostToDevice,
+                                                 s) == hipSuccess);
+            ok = ok && hipMemcpyAsync(db + q->o_boff, r.b_off, 4 * ((size_t)r.n_b + 1), hipMemcpyHostToDevice, s) ==
+                           hipSuccess;
+            ok = ok && (!r.nnz || hipMemcpyAsync(db + q->o_bidx, r.b_idx, 4 * (size_t)r.nnz, hipMemcpyHostToDevice,
+                                                 s) == hipSuccess);
+        } else {
+            std::memcpy(hb + q->o_aoff, r.a_off, 4 * ((size_t)r.n_a + 1));
+            if (r.nnz) std::memcpy(hb + q->o_aidx, r.a_idx, 4 * (size_t)r.nnz);
+            std::memcpy(hb + q->o_boff, r.b_off, 4 * ((size_t)r.n_b + 1));
+            if (r.nnz) std::memcpy(hb + q->o_bidx, r.b_idx, 4 * (size_t)r.nnz);
+            ok = ok && hipMemcpyAsync(db, hb, q->o_col, hipMemcpyHostToDevice, s) == hipSuccess;
+        }
+        q->done = (volatile long long *)(hb + q->o_done);
+        *q->done = 0;
         BatchItem &b = h_items[i];
+        b = BatchItem{};
         b.n_a = r.n_a;
         b.n_b = r.n_b;
         b.a_off = (const int *)(db + q->o_aoff);
@@ -355,57 +522,51 @@ bool bgpc_session::launch(std::vector<Req *> &grp)
         b.b_idx = (const int *)(db + q->o_bidx);
         b.colors = (int *)(db + q->o_col);
         b.scratch = db + q->o_scr;
-        b.log = nullptr;
-        b.log_cap = 0;
         b.max_rounds = max_rounds > 0 ? max_rounds : r.n_a + 65;
+        b.mode = q->mode;
+        b.cap = q->cap;
         b.status = -1;
-        b.rounds = 0;
-        b.dense = 0;
+        b.nnz = (int)r.nnz;
+        char *hb_dev = hpool_dev + q->off;
+        void *user_dev = nullptr;
+        if ((r.flags & BGPC_REQ_PINNED) && r.n_a && hipHostGetDevicePointer(&user_dev, r.colors_out, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            ok = false;
+        }
+        b.host_colors = (r.flags & BGPC_REQ_PINNED) ? (int *)user_dev : (int *)(hb_dev + q->o_col);
+        b.host_done = (long long *)(hb_dev + q->o_done);
         h_order[i] = i;
     }
     *(int *)(ht + o_next) = 0;
     ok = ok && hipMemcpyAsync(dt, ht, g->tbl_bytes, hipMemcpyHostToDevice, s) == hipSuccess;
     if (ok) {
-        k_batch<<<n, BATCH_BLOCK, 0, s>>>((BatchItem *)dt, (const int *)(dt + o_ord), n, (int *)(dt + o_next),
-                                          nullptr, 0, 0, 0);
+        k_batch<<<n, BATCH_BLOCK, 0, s>>>((BatchItem *)dt, (const int *)(dt + o_ord), n, (int *)(dt + o_next));
         ok = hipGetLastError() == hipSuccess;
     }
-    for (int i = 0; i < n && ok; i++) {
-        Req *q = grp[i];
-        ok = hipMemcpyAsync(hpool + q->off + q->o_col, dpool + q->off + q->o_col, 4 * (size_t)q->r.n_a,
-                            hipMemcpyDeviceToHost, s) == hipSuccess;
-    }
-    ok = ok && hipMemcpyAsync(ht, dt, sizeof(BatchItem) * n, hipMemcpyDeviceToHost, s) == hipSuccess;
     ok = ok && hipEventRecord(g->done, s) == hipSuccess;
     if (!ok) {
         error = BGPC_E_HIP;
         (void)hipStreamSynchronize(s);
     }
     inflight.push_back(g);
+    running.insert(running.end(), grp.begin(), grp.end());
     return true;
 }
 
-void bgpc_session::retire(Group *g)
+// a batched request whose done word is set: colors to the caller, memory back
+void bgpc_session::finish(Req *q)
 {
-    const double t = now_s();
-    const BatchItem *h_items = (const BatchItem *)(hpool + g->tbl_off);
-    std::vector<Req *> done;
-    for (size_t i = 0; i < g->reqs.size(); i++) {
-        Req *q = g->reqs[i];
-        if (q->r.n_a) std::memcpy(q->r.colors_out, hpool + q->off + q->o_col, 4 * (size_t)q->r.n_a);
-        q->status = error ? error : h_items[i].status;
-        q->rounds = h_items[i].rounds;
-        q->t_done = t;
-        alloc->release(q->off, q->bytes);
-        done.push_back(q);
-    }
-    slots_used -= (int)g->reqs.size();
-    alloc->release(g->tbl_off, g->tbl_bytes);
-    events.push_back(g->done);
-    delete g;
+    const long long d = *q->done;
+    if (q->r.n_a && !(q->r.flags & BGPC_REQ_PINNED))
+        std::memcpy(q->r.colors_out, hpool + q->off + q->o_col, 4 * (size_t)q->r.n_a);
+    q->status = error ? error : (int)(d & 0xffffffffll) - 256;
+    q->rounds = (int)(d >> 32);
+    q->t_done = now_s();
+    alloc->release(q->off, q->bytes);
+    slots_used--;
     {
         std::lock_guard<std::mutex> lk(mu);
-        completed.insert(completed.end(), done.begin(), done.end());
+        completed.push_back(q);
     }
     cv_done.notify_all();
 }
@@ -416,27 +577,47 @@ void bgpc_session::loop()
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(mu);
-            if (submitted.empty() && pending.empty() && inflight.empty()) {
+            if (submitted.empty() && pending.empty() && inflight.empty() && running.empty()) {
                 if (stop) break;
                 cv_work.wait(lk, [&] { return stop || !submitted.empty(); });
                 if (stop && submitted.empty()) break;
             }
             while (!submitted.empty()) {
-                pending.push_back(submitted.front());
+                Req *q = submitted.front();
                 submitted.pop_front();
+                if (q->device) {
+                    dev_queue.push_back(q);
+                    cv_dev.notify_one();
+                } else {
+                    pending.push_back(q);
+                }
             }
         }
         bool progress = false;
-        // retire finished groups
-        for (size_t i = 0; i < inflight.size();) {
-            hipError_t q = hipEventQuery(inflight[i]->done);
-            if (q == hipSuccess) {
-                Group *g = inflight[i];
-                inflight.erase(inflight.begin() + i);
-                retire(g);
+        // requests whose graphs are done (any order within and across groups)
+        for (size_t i = 0; i < running.size();) {
+            if (*running[i]->done != 0 || error) {
+                Req *q = running[i];
+                running[i] = running.back();
+                running.pop_back();
+                finish(q);
                 progress = true;
             } else {
-                if (q != hipErrorNotReady) error = BGPC_E_HIP;
+                i++;
+            }
+        }
+        // groups whose launch finished: their tables
+        for (size_t i = 0; i < inflight.size();) {
+            hipError_t st = hipEventQuery(inflight[i]->done);
+            if (st == hipSuccess) {
+                Group *g = inflight[i];
+                inflight.erase(inflight.begin() + i);
+                alloc->release(g->tbl_off, g->tbl_bytes);
+                events.push_back(g->done);
+                delete g;
+                progress = true;
+            } else {
+                if (st != hipErrorNotReady) error = BGPC_E_HIP;
                 i++;
             }
         }
@@ -464,6 +645,73 @@ void bgpc_session::loop()
     }
 }
 
+// one whole-device request: arrays in stream-ordered allocations, bgpc_color
+void bgpc_session::dev_run(Req *q)
+{
+    const bgpc_request &r = q->r;
+    hipStream_t s = dev_stream;
+    const size_t b_aoff = 4 * ((size_t)r.n_a + 1), b_boff = 4 * ((size_t)r.n_b + 1), b_idx = 4 * (size_t)r.nnz + 4;
+    const size_t b_col = 4 * ((size_t)r.n_a + 1);
+    const size_t o1 = al256(b_aoff), o2 = o1 + al256(b_idx), o3 = o2 + al256(b_boff), o4 = o3 + al256(b_idx);
+    char *d = nullptr;
+    int st = BGPC_OK;
+    int32_t rounds = 0;
+    if (hipMallocAsync((void **)&d, o4 + al256(b_col), s) != hipSuccess) {
+        (void)hipGetLastError();
+        st = BGPC_E_OOM;
+    }
+    if (st == BGPC_OK) {
+        bool ok = hipMemcpyAsync(d, r.a_off, b_aoff, hipMemcpyHostToDevice, s) == hipSuccess &&
+                  (!r.nnz || hipMemcpyAsync(d + o1, r.a_idx, 4 * (size_t)r.nnz, hipMemcpyHostToDevice, s) ==
+                                 hipSuccess) &&
+                  hipMemcpyAsync(d + o2, r.b_off, b_boff, hipMemcpyHostToDevice, s) == hipSuccess &&
+                  (!r.nnz || hipMemcpyAsync(d + o3, r.b_idx, 4 * (size_t)r.nnz, hipMemcpyHostToDevice, s) ==
+                                 hipSuccess);
+        if (!ok) st = BGPC_E_HIP;
+    }
+    if (st == BGPC_OK) {
+        bgpc_csr A = {r.n_a, r.n_b, r.nnz, (const int32_t *)d, (const int32_t *)(d + o1)};
+        bgpc_csr B = {r.n_b, r.n_a, r.nnz, (const int32_t *)(d + o2), (const int32_t *)(d + o3)};
+        bgpc_opts o;
+        bgpc_opts_default(&o);
+        o.stream = s;
+        o.max_rounds = max_rounds;
+        o.rounds_out = &rounds;
+        st = bgpc_color(&A, &B, nullptr, &o, (int32_t *)(d + o4));
+        if ((st == BGPC_OK || st == BGPC_E_NOT_CONVERGED) && r.n_a &&
+            (hipMemcpyAsync(r.colors_out, d + o4, 4 * (size_t)r.n_a, hipMemcpyDeviceToHost, s) != hipSuccess ||
+             hipStreamSynchronize(s) != hipSuccess))
+            st = BGPC_E_HIP;
+    }
+    if (d) (void)hipFreeAsync(d, s);
+    (void)hipStreamSynchronize(s);
+    q->status = st;
+    q->rounds = rounds;
+    q->t_done = now_s();
+}
+
+void bgpc_session::dev_loop()
+{
+    (void)hipSetDevice(device);
+    for (;;) {
+        Req *q = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_dev.wait(lk, [&] { return dev_stop || !dev_queue.empty(); });
+            if (dev_queue.empty()) break;   // dev_stop and nothing left
+            q = dev_queue.front();
+            dev_queue.pop_front();
+        }
+        q->t_admit = now_s();
+        dev_run(q);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            completed.push_back(q);
+        }
+        cv_done.notify_all();
+    }
+}
+
 extern "C" {
 
 BGPC_API bgpc_session *bgpc_session_create(size_t mem_budget, int32_t max_slots, int32_t max_group,
@@ -477,15 +725,18 @@ BGPC_API bgpc_session *bgpc_session_create(size_t mem_budget, int32_t max_slots,
     S->max_rounds = max_rounds;
     bool ok = hipGetDevice(&S->device) == hipSuccess;
     ok = ok && hipMalloc((void **)&S->dpool, S->budget) == hipSuccess;
-    ok = ok && hipHostMalloc((void **)&S->hpool, S->budget, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&S->hpool, S->budget, hipHostMallocMapped) == hipSuccess;
+    ok = ok && hipHostGetDevicePointer((void **)&S->hpool_dev, S->hpool, 0) == hipSuccess;
     for (int i = 0; i < 4 && ok; i++) {
         hipStream_t st;
         ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
         if (ok) S->streams.push_back(st);
     }
+    ok = ok && hipStreamCreateWithFlags(&S->dev_stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         for (auto st : S->streams) (void)hipStreamDestroy(st);
+        if (S->dev_stream) (void)hipStreamDestroy(S->dev_stream);
         if (S->dpool) (void)hipFree(S->dpool);
         if (S->hpool) (void)hipHostFree(S->hpool);
         delete S;
@@ -493,6 +744,7 @@ BGPC_API bgpc_session *bgpc_session_create(size_t mem_budget, int32_t max_slots,
     }
     S->alloc = new RangeAlloc(S->budget);
     S->worker = std::thread([S] { S->loop(); });
+    S->dev_worker = std::thread([S] { S->dev_loop(); });
     return S;
 }
 
@@ -503,8 +755,12 @@ BGPC_API int bgpc_session_submit(bgpc_session *S, const bgpc_request *r)
         return BGPC_E_INVALID;
     Req *q = new Req();
     q->r = *r;
+    if (!host_mode(q)) {
+        delete q;
+        return BGPC_E_INVALID;
+    }
     layout(q);
-    if (q->bytes + 4096 > S->budget) {
+    if (!q->device && q->bytes + 4096 > S->budget) {
         delete q;
         return BGPC_E_OOM;   // could never be admitted
     }
@@ -549,10 +805,18 @@ BGPC_API void bgpc_session_destroy(bgpc_session *S)
     }
     S->cv_work.notify_all();
     if (S->worker.joinable()) S->worker.join();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->dev_stop = true;
+    }
+    S->cv_dev.notify_all();
+    if (S->dev_worker.joinable()) S->dev_worker.join();
     for (auto st : S->streams) {
         (void)hipStreamSynchronize(st);
         (void)hipStreamDestroy(st);
     }
+    (void)hipStreamSynchronize(S->dev_stream);
+    (void)hipStreamDestroy(S->dev_stream);
     for (auto e : S->events) (void)hipEventDestroy(e);
     for (Req *q : S->completed) delete q;
     for (Req *q : S->pending) delete q;

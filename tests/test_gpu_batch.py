@@ -32,6 +32,69 @@ def test_batch_matches_oracle(cuda):
         assert np.array_equal(c, ref.colors) and r == ref.rounds
 
 
+def _shape(g):
+    """(walk, walk_max): sum of squared net sizes, largest summed net size of a vertex."""
+    sizes = np.diff(np.asarray(g.b_off, dtype=np.int64))
+    per_member = np.repeat(np.arange(g.n_a), np.diff(np.asarray(g.a_off, dtype=np.int64)))
+    wsum = np.bincount(per_member, weights=sizes[np.asarray(g.a_idx)], minlength=g.n_a) if g.n_a else np.zeros(0)
+    return float((sizes ** 2).sum()), int(wsum.max()) if wsum.size else 0
+
+
+def _route(g):
+    """The per-graph route of bgpc_color_batch restated from its rule:
+    'dense' (conflict matrix), 'forb' (forbidden bitmaps), 'masks', or
+    'device' (the whole-device path of bgpc_color)."""
+    walk, wmax = _shape(g)
+    heavy = walk > 128.0 * g.n_a or walk > 4.0 * g.n_a ** 2
+    if g.n_a > 0 and heavy and g.n_a <= 16384:
+        return "dense"
+    cap = min(wmax + 2, g.n_a + 1)
+    mode = "forb" if g.n_a > 0 and heavy and g.n_a * ((cap + 31) // 32) * 4 <= (64 << 20) else "masks"
+    if (mode == "forb" and g.nnz > 50000) or g.nnz > 1000000:
+        return "device"
+    return mode
+
+
+def test_batch_every_mode_matches_oracle(cuda):
+    """Graphs on every route of the per-graph rule: few vertices with heavily
+    overlapping nets and many colors (conflict matrix; buckets both below and
+    above the list size), colors past 127 on more vertices than the matrix
+    takes (forbidden-color bitmaps, or the whole-device path when large),
+    sparse (net masks); every one equals the oracle."""
+    shapes = [(300, 20000, 3, 30, 31), (200, 9000, 3, 30, 32), (6000, 6000, 20, 40, 34),
+              (4097, 9000, 3, 30, 39), (9000, 3000, 30, 60, 37), (1004, 1992, 3, 30, 40),
+              (17000, 380, 100, 150, 44), (20000, 8000, 10, 30, 35), (3000, 3000, 3, 6, 38)]
+    graphs = [synth.random_uniform(*sh) for sh in shapes]
+    routes = [_route(g) for g in graphs]
+    assert routes == ["dense"] * 6 + ["forb", "device", "masks"]
+    st, statuses, rounds, colors = _batch(cuda, graphs)
+    assert st == 0 and all(s == 0 for s in statuses)
+    for g, c, r in zip(graphs, colors, rounds):
+        ref = oracle.bgpc(g)
+        assert r == ref.rounds and np.array_equal(c, ref.colors)
+    assert all(colors[i].max() >= 128 for i in (0, 1, 2, 3, 4, 6))   # colors past the net masks
+
+
+def test_batch_rejects_malformed(cuda):
+    """An index out of range or offsets that decrease: BGPC_E_INVALID for the
+    batch (nothing launched over the bad arrays) and for a session request."""
+    import torch
+    good = synth.random_uniform(500, 400, 2, 6, 41)
+    bad = synth.random_uniform(500, 400, 2, 6, 42)
+    b_idx = bad.b_idx.copy()
+    b_idx[len(b_idx) // 2] = bad.n_a + 5
+    bad_idx = synth.Bipartite(bad.n_a, bad.n_b, bad.b_off, b_idx, bad.a_off, bad.a_idx, "bad_idx")
+    a_off = bad.a_off.copy()
+    a_off[3] = a_off[4] + 1
+    bad_off = synth.Bipartite(bad.n_a, bad.n_b, bad.b_off, bad.b_idx, a_off, bad.a_idx, "bad_off")
+    for b in (bad_idx, bad_off):
+        st, statuses, rounds, colors = _batch(cuda, [good, b])
+        assert st == bgpc.E_INVALID and statuses[1] == bgpc.E_INVALID
+        s = bgpc.Session(64 << 20, max_slots=4, max_group=4)
+        assert s.submit(0, b.n_a, b.n_b, b.a_off, b.a_idx, b.b_off, b.b_idx) == bgpc.E_INVALID
+        s.close()
+
+
 def test_batch_isolation_and_order(cuda):
     import torch
     graphs = [synth.batch_graph(i) for i in range(12)]
@@ -139,6 +202,7 @@ def test_serving_batched_workload_graphs(cuda):
 
 def test_serving_rejects_oversized(cuda):
     s = bgpc.Session(1 << 20, max_slots=4, max_group=4)
-    g = synth.batch_graph(3)
+    g = synth.random_uniform(300000, 100000, 2, 4, 43)   # sparse (batched route), ~4 MB of arrays
+    assert _route(g) == "masks"
     assert s.submit(0, g.n_a, g.n_b, g.a_off, g.a_idx, g.b_off, g.b_idx) == bgpc.E_OOM
     s.close()
