@@ -194,7 +194,7 @@ int run(const RunArgs &a)
     bool any_net_round = false;
     for (int r = 0; r < max_rounds && start_round + r < 64; r++)
         if (start_round + r >= 0 && ((o.net_color_mask >> (start_round + r)) & 1ull)) any_net_round = true;
-    size_t bytes = aligned(n_a + 1, 4) * 3            // W[0], W[1], heavy
+    size_t bytes = aligned(n_a + 1, 4) * 4            // W[0], W[1], heavy, first-fit cursors
                    + aligned(n_a + 1, 1)              // lose
                    + aligned(n_b + 1, 8)              // mask0
                    + aligned(n_b + 1, 4)              // big net list
@@ -216,6 +216,7 @@ int run(const RunArgs &a)
     int *W0 = ar.take<int>(n_a + 1);
     int *W1 = ar.take<int>(n_a + 1);
     int *heavy = ar.take<int>(n_a + 1);
+    int *ffc = ar.take<int>(n_a + 1);
     uint8_t *lose = ar.take<uint8_t>(n_a + 1);
     uint64_t *mask0 = ar.take<uint64_t>(n_b + 1);
     int *big = ar.take<int>(n_b + 1);
@@ -246,6 +247,35 @@ int run(const RunArgs &a)
     const int nthr = 256;
     const int g_a = grid_for(n_a, nthr, di.cus * 8);
     const int g_b = grid_for(n_b, nthr, di.cus * 8);
+    // higher color words (colors >= 64), net-major, grown as the largest
+    // possible color grows; at most half of the free device memory
+    uint64_t *hw = nullptr;
+    int PH = 0;
+    long mc_ub = -1;   // upper bound of every color present before the next round
+    const bool planes_ok = !(o.flags & BGPC_INCREMENTAL);
+    long max_PH = 0;
+    {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) max_PH = (long)(fr / 2 / (8 * ((size_t)n_b + 1)));
+        else (void)hipGetLastError();
+        max_PH = std::min<long>(max_PH, (long)n_a / 64 + 2);
+    }
+    auto ensure_planes = [&](long bound) {
+        const long need = bound < 64 ? 0 : (bound >> 6);
+        if (need <= PH || PH >= max_PH) return;
+        long np = std::min<long>(std::max<long>(need + 2, 2L * PH), max_PH);
+        if (np <= PH) return;
+        uint64_t *nh = nullptr;
+        if (hipMallocAsync((void **)&nh, (size_t)np * ((size_t)n_b + 1) * 8, s) != hipSuccess) {
+            (void)hipGetLastError();
+            max_PH = PH;   // no room: colors past the words take the neighbourhood walk
+            return;
+        }
+        k_grow_planes<<<grid_for((long)np * n_b, nthr, di.cus * 16), nthr, 0, s>>>(hw, PH, nh, (int)np, n_b);
+        if (hw) (void)hipFreeAsync(hw, s);
+        hw = nh;
+        PH = (int)np;
+    };
     // pinned counters live for the thread's lifetime (never freed: freeing at
     // thread exit could run after the HIP runtime has shut down)
     static thread_local HostProgress *prog_p = new HostProgress();
@@ -343,6 +373,7 @@ int run(const RunArgs &a)
 
         // ---- initial state
         k_fill_u8<<<g_a, nthr, 0, s>>>(lose, 0, n_a + 1);
+        k_fill_i32<<<g_a, nthr, 0, s>>>(ffc, 0, n_a + 1);
         k_fill_u8<<<g_b, nthr, 0, s>>>(done_net, 0, n_b + 1);
         k_fill_i32<<<g_a, nthr, 0, s>>>((int *)dirty_bits, 0, n_a / 32 + 2);
         k_fill_i32<<<g_a, nthr, 0, s>>>((int *)aff_bits, 0, n_a / 32 + 2);
@@ -366,7 +397,17 @@ int run(const RunArgs &a)
                 goto finish;
             }
             k_max_color<<<g_a, nthr, 0, s>>>(st, n_a, ctrl);
-            k_mask_rebuild<D2><<<g_b, nthr, 0, s>>>(g, st, mask0);
+            {
+                // colors present: size the higher color words before the rebuild
+                if (hipMemcpyAsync(&h_ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess) {
+                    st_code = BGPC_E_HIP;
+                    goto finish;
+                }
+                mc_ub = h_ctrl.max_color;
+                if (planes_ok) ensure_planes(mc_ub + 1);
+            }
+            k_mask_rebuild<D2><<<g_b, nthr, 0, s>>>(g, st, mask0, hw, PH);
             const int gt = grid_for(max_tiles, 1, di.cus * 4);
             k_count_uncolored<<<gt, TILE_BLOCK, 0, s>>>(st, n_a, tile_count);
             // identity compaction: the uncolored vertices in id order become W0
@@ -456,6 +497,16 @@ int run(const RunArgs &a)
             const bool net_mode = rid >= 0 && rid < 64 && ((o.net_color_mask >> rid) & 1ull);
             int *Wc = Wb[par], *Wn = Wb[par ^ 1];
             int *host = use_prog ? prog.d : nullptr;
+            if (planes_ok) {
+                // a vertex-based round raises the largest color by at most one;
+                // a net-based round colors below the largest net
+                if (use_prog) {
+                    int seen = prog.h[0], mc = prog.h[3];
+                    if (seen >= 0 && net_round_issued <= seen) mc_ub = std::min(mc_ub, (long)mc + (r - 1 - seen));
+                }
+                mc_ub = net_mode ? std::max<long>(mc_ub, max_net - 1) : mc_ub + 1;
+                ensure_planes(mc_ub);
+            }
             if (net_mode) {
                 k_ncolor_small<D2><<<g_b, nthr, 0, s>>>(g, st, owner, ctrl);
                 if (n_big) k_ncolor_big<D2><<<g_big, 256, ncolor_words * 4, s>>>(g, st, owner, big, &shape[1], ctrl,
@@ -467,16 +518,18 @@ int run(const RunArgs &a)
                 const bool full = r > 0 || resume;
                 if (full) {
                     k_set_max_final<<<1, 64, 0, s>>>(ctrl, -1);
-                    k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, nullptr, ctrl, par, st, lose, mask0, tile_count, rec, rr, 0);
+                    k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, nullptr, ctrl, par, st, lose, mask0, tile_count, rec, rr, 0,
+                                                          hw, PH);
                     k_compact<<<gt, TILE_BLOCK, 0, s>>>(nullptr, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 1, 1, host);
-                    k_mask_rebuild<D2><<<g_b, nthr, 0, s>>>(g, st, mask0);
+                    k_mask_rebuild<D2><<<g_b, nthr, 0, s>>>(g, st, mask0, hw, PH);
+                    k_fill_i32<<<g_a, nthr, 0, s>>>(ffc, 0, n_a + 1);
                     k_fill_u8<<<g_b, nthr, 0, s>>>(done_net, 0, n_b + 1);
         k_fill_i32<<<g_a, nthr, 0, s>>>((int *)dirty_bits, 0, n_a / 32 + 2);
         k_fill_i32<<<g_a, nthr, 0, s>>>((int *)aff_bits, 0, n_a / 32 + 2);
         k_fill_i32<<<g_b, nthr, 0, s>>>((int *)tchg_bits, 0, n_b / 32 + 2);
         k_fill_i32<<<g_b, nthr, 0, s>>>((int *)cn_bits, 0, n_b / 32 + 2);
                 } else {
-                    k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1);
+                    k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1, hw, PH);
                     k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 1, 1, host);
                 }
                 net_round_issued = r;
@@ -491,10 +544,11 @@ int run(const RunArgs &a)
                 if (r == inc_start) {
                     // full round whose losers keep their proposals
                     k_inc_reset<<<1, 64, 0, s>>>(ic);
-                    LAUNCH_PROF(BGPC_PROF_COLOR, (k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy, PCNT(r))));
+                    LAUNCH_PROF(BGPC_PROF_COLOR, (k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy, PCNT(r), hw, PH, ffc)));
                     if (need_wide)
                         k_vcolor_wide<D2><<<di.cus * 2, 256, wide_bytes, s>>>(g, heavy, ctrl, st, lds_bits, nullptr,
-                                                                               nullptr, nullptr, nullptr, nullptr);
+                                                                               nullptr, nullptr, nullptr, nullptr,
+                                                                               hw, PH, ffc);
                     LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r))));
                     k_inc_apply_full<D2><<<g_inc, nthr, 0, s>>>(g, ic, ctrl, par, Wc, st, lose, mask0, cn_bits, CNl);
                 } else {
@@ -502,7 +556,8 @@ int run(const RunArgs &a)
                                                            tchg_bits, TCNl, heavy, ctrl);
                     if (need_wide)
                         k_vcolor_wide<D2><<<di.cus * 2, 256, wide_bytes, s>>>(g, heavy, ctrl, st, lds_bits, ic,
-                                                                               aff_bits, Al, tchg_bits, TCNl);
+                                                                               aff_bits, Al, tchg_bits, TCNl,
+                                                                               nullptr, 0, nullptr);
                     k_expand<D2><<<g_inc, nthr, 0, s>>>(g, TCNl, &ic->n_tcn, tchg_bits, st, aff_bits, Al, &ic->n_a);
                     k_inc_conflict<D2><<<g_inc, nthr, 0, s>>>(g, ic, par, Al, aff_bits, st, WINl, ctrl);
                     k_inc_apply<D2><<<g_inc, nthr, 0, s>>>(g, ic, WINl, st, mask0, cn_bits, CNl, ctrl);
@@ -513,7 +568,7 @@ int run(const RunArgs &a)
                 inc_used = true;
             } else {
                 if (policy == BGPC_FIRST_FIT) {
-                    LAUNCH_PROF(BGPC_PROF_COLOR, (k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy, PCNT(r))));
+                    LAUNCH_PROF(BGPC_PROF_COLOR, (k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy, PCNT(r), hw, PH, ffc)));
                     // the wide path can only be needed once colors 0..63 all exist:
                     // a vertex-based first-fit round raises the largest color by at
                     // most one, a net-based round keeps it below the largest net
@@ -529,15 +584,16 @@ int run(const RunArgs &a)
                     }
                     if (need_wide)
                         k_vcolor_wide<D2><<<di.cus * 2, 256, wide_bytes, s>>>(g, heavy, ctrl, st, lds_bits, nullptr,
-                                                                               nullptr, nullptr, nullptr, nullptr);
+                                                                               nullptr, nullptr, nullptr, nullptr,
+                                                                               hw, PH, ffc);
                 } else {
                     k_vcolor_chunked<D2><<<g_chunk, 64, wide_bytes, s>>>(g, Wc, ctrl, par, st, mask0, policy, chunk,
-                                                                          lds_bits);
+                                                                          lds_bits, hw, PH);
                 }
                 LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r))));
                 if (n_big)
                     k_conflict_big<D2><<<g_big, 256, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 1);
-                k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1);
+                k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1, hw, PH);
                 k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 0, 1, host);
             }
             LAUNCH_CHECK();
@@ -613,6 +669,7 @@ finish:
             }
         }
     }
+    if (hw) (void)hipFreeAsync(hw, s);
     ar.release();
     if (!ar.async) (void)hipGetLastError();
     hipStreamSynchronize(s);

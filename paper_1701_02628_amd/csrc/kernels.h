@@ -237,18 +237,53 @@ __global__ void k_check_colors(const int *st, int n, int cap, int *err)
 // ---------------------------------------------------------------------------
 // masks of colors 0..63 held by the colored members of each net
 
+// Per-net color words.  mask0[v] holds the colors 0..63 of the colored
+// members of net v; colors 64 and up, when the driver has allocated them,
+// sit net-major in hw: word p of net v (colors 64(p+1) .. 64(p+1)+63) at
+// hw[v * PH + p].  Both hold snapshot colors only and are updated by the
+// winners of each vertex-based round.
 template <bool D2>
-__global__ void k_mask_rebuild(Graph g, const int *st, uint64_t *mask0)
+__global__ void k_mask_rebuild(Graph g, const int *st, uint64_t *mask0, uint64_t *hw, int PH)
 {
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n_b; v += gridDim.x * blockDim.x) {
         uint64_t m = 0;
         int sz = Acc<D2>::size(g, v);
+        uint64_t *row = hw ? hw + (long)v * PH : nullptr;
+        for (int p = 0; row && p < PH; p++) row[p] = 0;
         for (int k = 0; k < sz; k++) {
             int c = snap_color(st[Acc<D2>::member(g, v, k)]);
             if (c >= 0 && c < 64) m |= 1ull << c;
+            else if (c >= 64 && row && (c >> 6) - 1 < PH) row[(c >> 6) - 1] |= 1ull << (c & 63);
         }
         mask0[v] = m;
     }
+}
+
+// hw rows of PHo words -> rows of PHn >= PHo words (the new words zero)
+__global__ void k_grow_planes(const uint64_t *old, int PHo, uint64_t *neu, int PHn, int n_b)
+{
+    const long total = (long)n_b * PHn;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+        long v = i / PHn;
+        int p = (int)(i - v * PHn);
+        neu[i] = (p < PHo && old) ? old[v * PHo + p] : 0ull;
+    }
+}
+
+// Smallest color >= from (from >= 64) that no net of w holds, searched one
+// 64-color word at a time by one thread; -1 when the search passes the
+// allocated words.
+template <bool D2>
+__device__ int hw_first_free(const Graph &g, int w, const uint64_t *hw, int PH, int from)
+{
+    const int nn = Acc<D2>::nets_count(g, w);
+    for (int p = (from >> 6) - 1; p < PH; p++) {
+        uint64_t m = 0;
+        for (int k = 0; k < nn; k++) m |= hw[(long)Acc<D2>::net_at(g, w, k) * PH + p];
+        if (p == (from >> 6) - 1) m |= (1ull << (from & 63)) - 1ull;
+        if (~m) return 64 * (p + 1) + __builtin_ctzll(~m);
+    }
+    return -1;
 }
 
 __global__ void k_max_color(const int *st, int n, Ctrl *ctrl)
@@ -366,7 +401,8 @@ __device__ int block_find_free_down(const uint32_t *bits, int cap_bits, int from
 // colors are all forbidden are queued for k_vcolor_wide.
 template <bool D2>
 __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *ctrl, int par, int *st,
-                                                  const uint64_t *mask0, int *heavy, unsigned long long *prof)
+                                                  const uint64_t *mask0, int *heavy, unsigned long long *prof,
+                                                  const uint64_t *hw, int PH, int *ffc)
 {
     unsigned long long rows = 0;
     __shared__ int s_pre[65], s_beg[64];
@@ -430,8 +466,16 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
             }
         }
         if (w >= 0) {
+            int col = -1;
             if (~m) {
-                int col = __builtin_ctzll(~m);
+                col = __builtin_ctzll(~m);
+            } else if (PH > 0 && d <= 64) {
+                // colors 0..63 all forbidden: the higher words, from the
+                // vertex's last first-fit answer (F only grows in these rounds)
+                col = hw_first_free<D2>(g, w, hw, PH, max(64, ffc[w]));
+                if (col >= 0) ffc[w] = col;
+            }
+            if (col >= 0) {
                 st[w] = TENT | col;
                 local_max = max(local_max, col);
             } else {
@@ -445,28 +489,69 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
     if (prof && lane == 0 && rows) atomicAdd(&prof[3 * (blockIdx.x & 63) + 2], rows);
 }
 
-// Block per queued vertex: full forbidden bitmap in LDS, first clear bit.
+// Block per queued vertex.  With the higher color words allocated, the block
+// ORs the words of all nets of w, eight words per pass from the vertex's last
+// first-fit answer; past the allocated words (or without them) it builds the
+// full forbidden bitmap in LDS from the distance-2 neighbourhood.  First
+// clear bit either way.
 template <bool D2>
 __global__ void k_vcolor_wide(Graph g, const int *heavy, Ctrl *ctrl, int *st, int lds_bits, IncCtrl *ic,
-                              unsigned *aff_bits, int *A, unsigned *tchg_bits, int *tcn)
+                              unsigned *aff_bits, int *A, unsigned *tchg_bits, int *tcn, const uint64_t *hw, int PH,
+                              int *ffc)
 {
     extern __shared__ uint32_t dyn[];
     __shared__ int s_net[1025], s_pre[1025], s_scan[20], s_res;
+    __shared__ unsigned long long s_or[8];
     const int nh = ctrl->n_heavy;
     if (nh == 0) return;
-    int cap = ctrl->max_color + 2;
-    if (cap > lds_bits) {
-        if (threadIdx.x == 0 && blockIdx.x == 0) atomicOr(&ctrl->error, ERR_COLOR_CAP);
-        return;
-    }
-    int nwords = (cap + 31) >> 5;
+    const int tid = threadIdx.x, nt = blockDim.x;
     for (int h = blockIdx.x; h < nh; h += gridDim.x) {
         int w = heavy[h];
-        for (int i = threadIdx.x; i < nwords; i += blockDim.x) dyn[i] = 0;
-        __syncthreads();
-        build_forbidden<D2>(g, st, w, dyn, cap, s_net, s_pre, s_scan);
-        int col = block_find_free_up(dyn, cap, 0, &s_res);
-        if (threadIdx.x == 0) {
+        int col = -1;
+        if (PH > 0) {
+            const int nn = Acc<D2>::nets_count(g, w);
+            const int from = max(64, ffc ? ffc[w] : 0);
+            for (int p0 = (from >> 6) - 1; p0 < PH && col < 0; p0 += 8) {
+                unsigned long long acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                for (int k = tid; k < nn; k += nt) {
+                    const uint64_t *row = hw + (long)Acc<D2>::net_at(g, w, k) * PH;
+#pragma unroll
+                    for (int q = 0; q < 8; q++)
+                        if (p0 + q < PH) acc[q] |= row[p0 + q];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    for (int dd = WAVE / 2; dd > 0; dd >>= 1) acc[q] |= shfl64(acc[q], lane_id() ^ dd);
+                }
+                if (tid < 8) s_or[tid] = 0;
+                __syncthreads();
+                if (lane_id() == 0)
+                    for (int q = 0; q < 8; q++) atomicOr(&s_or[q], acc[q]);
+                __syncthreads();
+                for (int q = 0; q < 8 && p0 + q < PH; q++) {
+                    unsigned long long m = s_or[q];
+                    if (q == 0 && p0 == (from >> 6) - 1) m |= (1ull << (from & 63)) - 1ull;
+                    if (~m) {
+                        col = 64 * (p0 + q + 1) + __builtin_ctzll(~m);
+                        break;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (col < 0) {
+            int cap = ctrl->max_color + 2;
+            if (cap > lds_bits) {
+                if (tid == 0) atomicOr(&ctrl->error, ERR_COLOR_CAP);
+                return;
+            }
+            int nwords = (cap + 31) >> 5;
+            for (int i = tid; i < nwords; i += nt) dyn[i] = 0;
+            __syncthreads();
+            build_forbidden<D2>(g, st, w, dyn, cap, s_net, s_pre, s_scan);
+            col = block_find_free_up(dyn, cap, 0, &s_res);
+        }
+        if (tid == 0) {
             int nw = TENT | col;
             if (ic) {   // incremental rounds: note a changed proposal, join A
                 if (st[w] != nw) {
@@ -477,6 +562,7 @@ __global__ void k_vcolor_wide(Graph g, const int *heavy, Ctrl *ctrl, int *st, in
             } else {
                 st[w] = nw;
             }
+            if (ffc) ffc[w] = col;
             max_to(&ctrl->max_color, col);
         }
         __syncthreads();
@@ -551,13 +637,80 @@ __device__ __forceinline__ void policy_update(int policy, int col, PolicyState &
     if (policy == 2) s.col_next = min(col + 1, s.col_max / 3 + 1);
 }
 
+// OR over the nets of w of color word p (p = 0: mask0; p >= 1: hw word
+// p - 1), lanes of the wave splitting the nets; every lane gets the result.
+template <bool D2>
+__device__ uint64_t wave_word_or(const Graph &g, int w, const uint64_t *mask0, const uint64_t *hw, int PH, int p)
+{
+    const int nn = Acc<D2>::nets_count(g, w);
+    uint64_t m = 0;
+    for (int k = lane_id(); k < nn; k += WAVE) {
+        int v = Acc<D2>::net_at(g, w, k);
+        m |= p == 0 ? mask0[v] : hw[(long)v * PH + p - 1];
+    }
+    for (int d = WAVE / 2; d > 0; d >>= 1) m |= shfl64(m, lane_id() ^ d);
+    return m;
+}
+
+// The policies' searches over the color words of w (m0: word 0, already
+// gathered).  up: smallest free color >= from; down: largest free color
+// <= from, or -1 when there is none.  -2: the search needs words beyond the
+// allocated ones.
+template <bool D2>
+__device__ int words_free_up(const Graph &g, int w, uint64_t m0, const uint64_t *mask0, const uint64_t *hw, int PH,
+                             int from)
+{
+    for (int p = from >> 6; p <= PH; p++) {
+        uint64_t m = p == 0 ? m0 : wave_word_or<D2>(g, w, mask0, hw, PH, p);
+        if (p == (from >> 6)) m |= (1ull << (from & 63)) - 1ull;
+        if (~m) return 64 * p + __builtin_ctzll(~m);
+    }
+    return -2;
+}
+
+template <bool D2>
+__device__ int words_free_down(const Graph &g, int w, uint64_t m0, const uint64_t *mask0, const uint64_t *hw, int PH,
+                               int from)
+{
+    if (from < 0) return -1;
+    if ((from >> 6) > PH) return -2;
+    for (int p = from >> 6; p >= 0; p--) {
+        uint64_t m = p == 0 ? m0 : wave_word_or<D2>(g, w, mask0, hw, PH, p);
+        uint64_t fr = ~m;
+        if (p == (from >> 6)) fr &= bits_upto(from & 63);
+        if (fr) return 64 * p + 63 - __builtin_clzll(fr);
+    }
+    return -1;
+}
+
+// One policy pick from the color words; -2 when they do not reach far enough.
+template <bool D2>
+__device__ int pick_words(const Graph &g, int w, uint64_t m0, const uint64_t *mask0, const uint64_t *hw, int PH,
+                          int policy, const PolicyState &s)
+{
+    if (policy == 1 && (w & 1) == 0) {   // B1, even rank
+        int c = words_free_down<D2>(g, w, m0, mask0, hw, PH, s.col_max);
+        if (c == -1) c = words_free_up<D2>(g, w, m0, mask0, hw, PH, s.col_max + 1);
+        return c;
+    }
+    if (policy == 2) {
+        int c = words_free_up<D2>(g, w, m0, mask0, hw, PH, s.col_next);
+        if (c == -2) return -2;
+        if (c > s.col_max) c = words_free_up<D2>(g, w, m0, mask0, hw, PH, 0);
+        return c;
+    }
+    return words_free_up<D2>(g, w, m0, mask0, hw, PH, 0);
+}
+
 // One wave (block of 64) per chunk of `chunk` consecutive worklist entries;
 // the policy state runs through the chunk in worklist order.  Lanes compute
 // the low masks of 64 entries at a time; an entry whose pick needs colors
-// >= 64 builds its full forbidden bitmap with the whole wave.
+// >= 64 searches the higher color words with the whole wave, or, past the
+// allocated words, builds its full forbidden bitmap with the whole wave.
 template <bool D2>
 __global__ void __launch_bounds__(64) k_vcolor_chunked(Graph g, const int *W, Ctrl *ctrl, int par, int *st,
-                                                        const uint64_t *mask0, int policy, int chunk, int lds_bits)
+                                                        const uint64_t *mask0, int policy, int chunk, int lds_bits,
+                                                        const uint64_t *hw, int PH)
 {
     extern __shared__ uint32_t dyn[];
     __shared__ int s_net[65], s_pre[65], s_scan[4], s_res;
@@ -583,16 +736,19 @@ __global__ void __launch_bounds__(64) k_vcolor_chunked(Graph g, const int *W, Ct
                 uint64_t mj = shfl64(m, j);
                 int col;
                 if (!pick_low(policy, mj, wj, s, &col)) {
-                    if (cap < 0) cap = ctrl->max_color + 2;
-                    if (cap > lds_bits) {
-                        if (lane == 0) atomicOr(&ctrl->error, ERR_COLOR_CAP);
-                        return;
+                    col = PH > 0 ? pick_words<D2>(g, wj, mj, mask0, hw, PH, policy, s) : -2;
+                    if (col == -2) {
+                        if (cap < 0) cap = ctrl->max_color + 2;
+                        if (cap > lds_bits) {
+                            if (lane == 0) atomicOr(&ctrl->error, ERR_COLOR_CAP);
+                            return;
+                        }
+                        int nwords = (cap + 31) >> 5;
+                        for (int q = lane; q < nwords; q += WAVE) dyn[q] = 0;
+                        __syncthreads();
+                        build_forbidden<D2>(g, st, wj, dyn, cap, s_net, s_pre, s_scan);
+                        col = pick_bitmap(policy, dyn, cap, wj, s, &s_res);
                     }
-                    int nwords = (cap + 31) >> 5;
-                    for (int q = lane; q < nwords; q += WAVE) dyn[q] = 0;
-                    __syncthreads();
-                    build_forbidden<D2>(g, st, wj, dyn, cap, s_net, s_pre, s_scan);
-                    col = pick_bitmap(policy, dyn, cap, wj, s, &s_res);
                 }
                 policy_update(policy, col, s);
                 if (lane == 0) {
@@ -1022,7 +1178,8 @@ __global__ void k_conflict_big(Graph g, const int *st, uint8_t *lose, uint8_t *d
 template <bool D2>
 __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, Ctrl *ctrl, int par, int *st,
                                                       uint8_t *lose, uint64_t *mask0, int *tile_count,
-                                                      RoundRec *rec, int round, int update_masks)
+                                                      RoundRec *rec, int round, int update_masks, uint64_t *hw,
+                                                      int PH)
 {
     constexpr int NWV = TILE_BLOCK / WAVE;
     __shared__ int s_scan[8];
@@ -1073,6 +1230,13 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
                             beg = g.a_off[u];
                             d = g.a_off[u + 1] - beg;
                             if (D2) atomicOr((unsigned long long *)&mask0[u], bit);
+                        } else if (update_masks && (col >> 6) - 1 < PH) {
+                            // higher color word of every net of u
+                            const int p = (col >> 6) - 1;
+                            const unsigned long long b = 1ull << (col & 63);
+                            const int nn = Acc<D2>::nets_count(g, u);
+                            for (int q = 0; q < nn; q++)
+                                atomicOr((unsigned long long *)&hw[(long)Acc<D2>::net_at(g, u, q) * PH + p], b);
                         }
                     }
                     mx = max(mx, col);
