@@ -80,51 +80,55 @@ def main():
     # dominant kernel: the one with the larger summed event time over a call
     kernel_ms = {}
     for kid, name in ((bgpc.PROF_COLOR, "k_vcolor_ff"), (bgpc.PROF_CONFLICT, "k_conflict_small")):
-        pr = bgpc.Profile(kid, 0, 0.0, 0.0)
+        pr = bgpc.Profile(kid, 0, 0.0, 0.0, 0.0)
         step(pr)
         kernel_ms[name] = (kid, pr.ms)
     dom_name = max(kernel_ms, key=lambda k: kernel_ms[k][1])
     dom_kid = kernel_ms[dom_name][0]
     torch.cuda.synchronize()
 
-    # timed region: K calls; the dominant kernel's launches are bracketed by
-    # HIP event pairs on the call's stream inside the library
-    prof_tot = {"launches": 0, "ms": 0.0, "bytes": 0.0}
+    # timed region: K calls, inputs resident, nothing else on the stream
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     rounds = 0
     for _ in range(args.steps):
-        pr = bgpc.Profile(dom_kid, 0, 0.0, 0.0)
-        rounds = step(pr).rounds
-        prof_tot["launches"] += pr.launches
-        prof_tot["ms"] += pr.ms
-        prof_tot["bytes"] += pr.bytes
+        rounds = step().rounds
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1) / args.steps
 
-    # the same number of calls without event pairs, for the event overhead
-    torch.cuda.synchronize()
+    # K more calls with the dominant kernel's launches bracketed by HIP event
+    # pairs on the call's stream inside the library (roofline)
+    prof_tot = {"launches": 0, "ms": 0.0, "bytes": 0.0, "bytes_scanned": 0.0}
     ev2, ev3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev2.record(stream)
     for _ in range(args.steps):
-        step()
+        pr = bgpc.Profile(dom_kid, 0, 0.0, 0.0, 0.0)
+        step(pr)
+        prof_tot["launches"] += pr.launches
+        prof_tot["ms"] += pr.ms
+        prof_tot["bytes"] += pr.bytes
+        prof_tot["bytes_scanned"] += pr.bytes_scanned
     ev3.record(stream)
     torch.cuda.synchronize()
-    ms_plain = ev2.elapsed_time(ev3) / args.steps
+    ms_events = ev2.elapsed_time(ev3) / args.steps
 
     stats = bgpc.color_stats(out)
     value = g.nnz / (ms / 1e3)
     avg_us = 1e3 * prof_tot["ms"] / max(1, prof_tot["launches"])
     bytes_per_launch = prof_tot["bytes"] / max(1, prof_tot["launches"])
+    scanned_per_launch = prof_tot["bytes_scanned"] / max(1, prof_tot["launches"])
     achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                 "frac": achieved / 8000.0, "traffic": measured_traffic(args.workload, dom_name),
                 "launches_per_step": prof_tot["launches"] / args.steps,
                 "avg_launch_us": avg_us, "algorithmic_bytes_per_launch": bytes_per_launch,
-                "share_of_step": prof_tot["ms"] / args.steps / ms}
+                "scanned_bytes_per_launch": scanned_per_launch,
+                "scanned_GBps": scanned_per_launch / (avg_us * 1e-6) / 1e9,
+                "share_of_step": prof_tot["ms"] / args.steps / ms_events}
 
     line = {
         "metric": "BGPC nnz/s at 1 GPU & colors vs seq greedy; batched graphs/s + p99 latency",
@@ -134,7 +138,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
-        "ms_per_step_without_events": ms_plain,
+        "ms_per_step_with_kernel_events": ms_events,
         "wall_s_timed": wall,
         "higher_is_better": True,
         "scaling": "weak",

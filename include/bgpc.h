@@ -129,6 +129,9 @@ typedef struct {
     int32_t launches;         /* out */
     double ms;                /* out: summed event time of those launches */
     double bytes;             /* out: summed algorithmic bytes of those launches */
+    double bytes_scanned;     /* out: the same figure over the nets the removal scan actually read
+                                 (vertex-based rounds re-scan only nets whose members changed their
+                                 proposals; equal to bytes for the coloring kernel) */
 } bgpc_profile;
 
 typedef struct {

@@ -35,7 +35,7 @@ class RoundLog(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("launches", ctypes.c_int32), ("ms", ctypes.c_double),
-                ("bytes", ctypes.c_double)]
+                ("bytes", ctypes.c_double), ("bytes_scanned", ctypes.c_double)]
 
 
 PROF_CONFLICT, PROF_COLOR = 0, 1

@@ -162,6 +162,7 @@ struct EventPool {
 
 struct RunArgs {
     Graph g;
+    long nnz;
     bool d2;
     const bgpc_opts *o;
     int *st;
@@ -194,6 +195,7 @@ int run(const RunArgs &a)
     bool any_net_round = false;
     for (int r = 0; r < max_rounds && start_round + r < 64; r++)
         if (start_round + r >= 0 && ((o.net_color_mask >> (start_round + r)) & 1ull)) any_net_round = true;
+    const size_t sp_words = (size_t)((a.nnz + (D2 ? n_b : 0)) / 64 + 4);
     size_t bytes = aligned(n_a + 1, 4) * 4            // W[0], W[1], heavy, first-fit cursors
                    + aligned(n_a + 1, 1)              // lose
                    + aligned(n_b + 1, 8)              // mask0
@@ -203,13 +205,16 @@ int run(const RunArgs &a)
                    + aligned(1, sizeof(Ctrl))         //
                    + aligned(8, 4)                    // shape figures
                    + aligned(rec_cap, sizeof(RoundRec))
-                   + aligned((size_t)prof_rounds * PROF_SLOTS * 3 + 1, 8)
+                   + aligned((size_t)prof_rounds * PROF_SLOTS * 4 + 1, 8)
                    + (any_net_round ? aligned(n_a + 1, 4) : 0)
                    + aligned(1, sizeof(IncCtrl))
                    + aligned(n_a + 1, 4) * 4          // incremental lists D0, D1, A, winners
                    + aligned(n_b + 1, 4) * 2          // nets with a changed proposal / a winner
                    + aligned(n_a / 32 + 2, 4) * 2     // dirty, affected bit sets
-                   + aligned(n_b / 32 + 2, 4) * 2;    // net bit sets
+                   + aligned(n_b / 32 + 2, 4) * 2     // net bit sets
+                   + aligned(sp_words, 8)             // standing proposals: verdict bits
+                   + aligned(n_a + 1, 4)              //   loss counts
+                   + aligned(n_b + 1, 1);             //   dirty nets
     Arena ar;
     int rc = ar.reserve(bytes, s);
     if (rc != BGPC_OK) return rc;
@@ -225,7 +230,7 @@ int run(const RunArgs &a)
     Ctrl *ctrl = ar.take<Ctrl>(1);
     int *shape = ar.take<int>(8);
     RoundRec *rec = ar.take<RoundRec>(rec_cap);
-    unsigned long long *pcnt = ar.take<unsigned long long>((size_t)prof_rounds * PROF_SLOTS * 3 + 1);
+    unsigned long long *pcnt = ar.take<unsigned long long>((size_t)prof_rounds * PROF_SLOTS * 4 + 1);
     int *owner = any_net_round ? ar.take<int>(n_a + 1) : nullptr;
     IncCtrl *ic = ar.take<IncCtrl>(1);
     int *Dl[2] = {ar.take<int>(n_a + 1), ar.take<int>(n_a + 1)};
@@ -237,6 +242,9 @@ int run(const RunArgs &a)
     unsigned *aff_bits = ar.take<unsigned>(n_a / 32 + 2);
     unsigned *tchg_bits = ar.take<unsigned>(n_b / 32 + 2);
     unsigned *cn_bits = ar.take<unsigned>(n_b / 32 + 2);
+    unsigned long long *sp_bits = ar.take<unsigned long long>(sp_words);
+    int *sp_cnt = ar.take<int>(n_a + 1);
+    uint8_t *sp_dirty = ar.take<uint8_t>(n_b + 1);
     int *Wb[2] = {W0, W1};
 
     int st_code = BGPC_OK;
@@ -260,6 +268,12 @@ int run(const RunArgs &a)
         else (void)hipGetLastError();
         max_PH = std::min<long>(max_PH, (long)n_a / 64 + 2);
     }
+    // standing proposals in vertex-based rounds (not with the opt-in
+    // incremental rounds); their state is reset after every net-based round
+    const bool sp_on = !(o.flags & BGPC_INCREMENTAL);
+    bool sp_reset = true, sp_used = false;
+    const SPState sp_none = {nullptr, nullptr, nullptr};
+    const SPState sp_state = {sp_bits, sp_cnt, sp_dirty};
     auto ensure_planes = [&](long bound) {
         const long need = bound < 64 ? 0 : (bound >> 6);
         if (need <= PH || PH >= max_PH) return;
@@ -288,11 +302,12 @@ int run(const RunArgs &a)
         o.prof->launches = 0;
         o.prof->ms = 0.0;
         o.prof->bytes = 0.0;
+        o.prof->bytes_scanned = 0.0;
     }
-#define PCNT(r) ((r) < prof_rounds ? pcnt + (size_t)(r) * PROF_SLOTS * 3 : nullptr)
+#define PCNT(r) ((r) < prof_rounds ? pcnt + (size_t)(r) * PROF_SLOTS * 4 : nullptr)
     if (prof_rounds)
-        k_fill_i32<<<grid_for((long)prof_rounds * PROF_SLOTS * 6, nthr, di.cus * 4), nthr, 0, s>>>(
-            (int *)pcnt, 0, (long)prof_rounds * PROF_SLOTS * 6);
+        k_fill_i32<<<grid_for((long)prof_rounds * PROF_SLOTS * 8, nthr, di.cus * 4), nthr, 0, s>>>(
+            (int *)pcnt, 0, (long)prof_rounds * PROF_SLOTS * 8);
 #define LAUNCH_PROF(kid, launch)                                  \
     do {                                                          \
         hipEvent_t e0_ = nullptr, e1_ = nullptr;                  \
@@ -507,19 +522,35 @@ int run(const RunArgs &a)
                 mc_ub = net_mode ? std::max<long>(mc_ub, max_net - 1) : mc_ub + 1;
                 ensure_planes(mc_ub);
             }
+            if (net_mode && sp_used && !sp_reset) {
+                // losers of the previous vertex-based round hold their
+                // proposals: a net-based round starts from them uncolored
+                k_drop_proposals<<<g_a, nthr, 0, s>>>(st, n_a);
+                sp_reset = true;
+            }
+            if (!net_mode && r < inc_start && sp_on && sp_reset) {
+                k_fill_i32<<<grid_for((long)sp_words * 2, nthr, di.cus * 8), nthr, 0, s>>>((int *)sp_bits, 0,
+                                                                                           (long)sp_words * 2);
+                k_fill_i32<<<g_a, nthr, 0, s>>>(sp_cnt, 0, n_a + 1);
+                k_fill_u8<<<g_b, nthr, 0, s>>>(sp_dirty, 1, n_b + 1);
+                sp_reset = false;
+            }
+            const bool spr = !net_mode && r < inc_start && sp_on;   // this round keeps standing proposals
+            if (spr) sp_used = true;
             if (net_mode) {
                 k_ncolor_small<D2><<<g_b, nthr, 0, s>>>(g, st, owner, ctrl);
                 if (n_big) k_ncolor_big<D2><<<g_big, 256, ncolor_words * 4, s>>>(g, st, owner, big, &shape[1], ctrl,
                                                                                  ncolor_words);
                 if (!D2) k_ncolor_isolated<<<g_a, nthr, 0, s>>>(g, Wc, ctrl, par, st);
-                LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 0, PCNT(r))));
+                LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 0, PCNT(r), sp_none)));
                 if (n_big)
-                    k_conflict_big<D2><<<g_big, 256, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 0);
+                    k_conflict_big<D2><<<g_big, 256, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 0,
+                                                                           sp_none);
                 const bool full = r > 0 || resume;
                 if (full) {
                     k_set_max_final<<<1, 64, 0, s>>>(ctrl, -1);
                     k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, nullptr, ctrl, par, st, lose, mask0, tile_count, rec, rr, 0,
-                                                          hw, PH);
+                                                          hw, PH, nullptr);
                     k_compact<<<gt, TILE_BLOCK, 0, s>>>(nullptr, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 1, 1, host);
                     k_mask_rebuild<D2><<<g_b, nthr, 0, s>>>(g, st, mask0, hw, PH);
                     k_fill_i32<<<g_a, nthr, 0, s>>>(ffc, 0, n_a + 1);
@@ -529,7 +560,8 @@ int run(const RunArgs &a)
         k_fill_i32<<<g_b, nthr, 0, s>>>((int *)tchg_bits, 0, n_b / 32 + 2);
         k_fill_i32<<<g_b, nthr, 0, s>>>((int *)cn_bits, 0, n_b / 32 + 2);
                 } else {
-                    k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1, hw, PH);
+                    k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1, hw, PH,
+                                                          nullptr);
                     k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 1, 1, host);
                 }
                 net_round_issued = r;
@@ -544,12 +576,12 @@ int run(const RunArgs &a)
                 if (r == inc_start) {
                     // full round whose losers keep their proposals
                     k_inc_reset<<<1, 64, 0, s>>>(ic);
-                    LAUNCH_PROF(BGPC_PROF_COLOR, (k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy, PCNT(r), hw, PH, ffc)));
+                    LAUNCH_PROF(BGPC_PROF_COLOR, (k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy, PCNT(r), hw, PH, ffc, nullptr)));
                     if (need_wide)
                         k_vcolor_wide<D2><<<di.cus * 2, 256, wide_bytes, s>>>(g, heavy, ctrl, st, lds_bits, nullptr,
                                                                                nullptr, nullptr, nullptr, nullptr,
-                                                                               hw, PH, ffc);
-                    LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r))));
+                                                                               hw, PH, ffc, nullptr);
+                    LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), sp_none)));
                     k_inc_apply_full<D2><<<g_inc, nthr, 0, s>>>(g, ic, ctrl, par, Wc, st, lose, mask0, cn_bits, CNl);
                 } else {
                     k_inc_color<D2><<<g_inc, nthr, 0, s>>>(g, ic, par, Dl[par], dirty_bits, st, mask0, aff_bits, Al,
@@ -557,7 +589,7 @@ int run(const RunArgs &a)
                     if (need_wide)
                         k_vcolor_wide<D2><<<di.cus * 2, 256, wide_bytes, s>>>(g, heavy, ctrl, st, lds_bits, ic,
                                                                                aff_bits, Al, tchg_bits, TCNl,
-                                                                               nullptr, 0, nullptr);
+                                                                               nullptr, 0, nullptr, nullptr);
                     k_expand<D2><<<g_inc, nthr, 0, s>>>(g, TCNl, &ic->n_tcn, tchg_bits, st, aff_bits, Al, &ic->n_a);
                     k_inc_conflict<D2><<<g_inc, nthr, 0, s>>>(g, ic, par, Al, aff_bits, st, WINl, ctrl);
                     k_inc_apply<D2><<<g_inc, nthr, 0, s>>>(g, ic, WINl, st, mask0, cn_bits, CNl, ctrl);
@@ -567,8 +599,10 @@ int run(const RunArgs &a)
                 k_inc_close<<<1, 64, 0, s>>>(ic, ctrl, par, rec, rr, host);
                 inc_used = true;
             } else {
+                uint8_t *dty = spr ? sp_dirty : nullptr;
+                const SPState &spx = spr ? sp_state : sp_none;
                 if (policy == BGPC_FIRST_FIT) {
-                    LAUNCH_PROF(BGPC_PROF_COLOR, (k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy, PCNT(r), hw, PH, ffc)));
+                    LAUNCH_PROF(BGPC_PROF_COLOR, (k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy, PCNT(r), hw, PH, ffc, dty)));
                     // the wide path can only be needed once colors 0..63 all exist:
                     // a vertex-based first-fit round raises the largest color by at
                     // most one, a net-based round keeps it below the largest net
@@ -585,21 +619,25 @@ int run(const RunArgs &a)
                     if (need_wide)
                         k_vcolor_wide<D2><<<di.cus * 2, 256, wide_bytes, s>>>(g, heavy, ctrl, st, lds_bits, nullptr,
                                                                                nullptr, nullptr, nullptr, nullptr,
-                                                                               hw, PH, ffc);
+                                                                               hw, PH, ffc, dty);
                 } else {
                     k_vcolor_chunked<D2><<<g_chunk, 64, wide_bytes, s>>>(g, Wc, ctrl, par, st, mask0, policy, chunk,
-                                                                          lds_bits, hw, PH);
+                                                                          lds_bits, hw, PH, dty);
                 }
-                LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r))));
+                LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), spx)));
+                if (spr && prof_kernel == BGPC_PROF_CONFLICT && PCNT(r))
+                    k_census<D2><<<g_b, nthr, 0, s>>>(g, st, PCNT(r));
                 if (n_big)
-                    k_conflict_big<D2><<<g_big, 256, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 1);
-                k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1, hw, PH);
+                    k_conflict_big<D2><<<g_big, 256, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 1,
+                                                                           spx);
+                k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1, hw, PH,
+                                                      spr ? sp_cnt : nullptr);
                 k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 0, 1, host);
             }
             LAUNCH_CHECK();
             issued++;
         }
-        if (inc_used) k_drop_proposals<<<g_a, nthr, 0, s>>>(st, n_a);
+        if (inc_used || sp_used) k_drop_proposals<<<g_a, nthr, 0, s>>>(st, n_a);
         LAUNCH_CHECK();
     }
 
@@ -624,28 +662,37 @@ finish:
         // algorithmic bytes from the per-round counters
         int k = std::min(std::min(h_ctrl.rounds, rec_cap - 2), prof_rounds);
         std::vector<RoundRec> rr_h(std::max(k, 1));
-        std::vector<unsigned long long> pc_h((size_t)std::max(k, 1) * PROF_SLOTS * 3);
+        std::vector<unsigned long long> pc_h((size_t)std::max(k, 1) * PROF_SLOTS * 4);
         if (k > 0 && hipMemcpy(rr_h.data(), rec, sizeof(RoundRec) * k, hipMemcpyDeviceToHost) == hipSuccess &&
-            hipMemcpy(pc_h.data(), pcnt, sizeof(unsigned long long) * k * PROF_SLOTS * 3,
+            hipMemcpy(pc_h.data(), pcnt, sizeof(unsigned long long) * k * PROF_SLOTS * 4,
                       hipMemcpyDeviceToHost) == hipSuccess) {
-            double bytes = 0.0;
+            double bytes = 0.0, scanned = 0.0;
             for (int i = 0; i < k; i++) {
-                double nets = 0, mem = 0, rows = 0;
+                double nets = 0, mem = 0, rows = 0, smem = 0;
                 for (int q = 0; q < PROF_SLOTS; q++) {
-                    nets += (double)pc_h[((size_t)i * PROF_SLOTS + q) * 3 + 0];
-                    mem += (double)pc_h[((size_t)i * PROF_SLOTS + q) * 3 + 1];
-                    rows += (double)pc_h[((size_t)i * PROF_SLOTS + q) * 3 + 2];
+                    nets += (double)pc_h[((size_t)i * PROF_SLOTS + q) * 4 + 0];
+                    mem += (double)pc_h[((size_t)i * PROF_SLOTS + q) * 4 + 1];
+                    rows += (double)pc_h[((size_t)i * PROF_SLOTS + q) * 4 + 2];
+                    smem += (double)pc_h[((size_t)i * PROF_SLOTS + q) * 4 + 3];
                 }
                 if (prof_kernel == BGPC_PROF_CONFLICT) {
-                    // per walked net: its end offset + member ids; every member
+                    // per net of the round (a net with a member in the
+                    // worklist): its end offset + member ids; every member
                     // state once (at most n_a distinct)
                     bytes += 4.0 * nets + 4.0 * mem + 4.0 * std::min(mem, (double)n_a);
+                    // the same over the nets actually read (their count is
+                    // not kept: offsets counted per member / average size)
+                    const double snets = mem > 0 ? nets * smem / mem : 0.0;
+                    scanned += 4.0 * snets + 4.0 * smem + 4.0 * std::min(smem, (double)n_a);
                 } else if (prof_kernel == BGPC_PROF_COLOR && rr_h[i].mode == 0) {
                     // per entry: id, two row offsets, proposal; per incidence: net
                     // id; every net mask once (at most n_b distinct)
-                    bytes += 16.0 * rr_h[i].w + 4.0 * rows + 8.0 * std::min(rows, (double)n_b);
+                    const double b = 16.0 * rr_h[i].w + 4.0 * rows + 8.0 * std::min(rows, (double)n_b);
+                    bytes += b;
+                    scanned += b;
                 }
             }
+            o.prof->bytes_scanned = scanned;
             o.prof->bytes = bytes;
         }
     }
@@ -775,6 +822,7 @@ BGPC_API int bgpc_color(const bgpc_csr *csr_A, const bgpc_csr *csr_B, const int3
     }
     RunArgs a;
     a.g = Graph{csr_A->n_rows, csr_B->n_rows, csr_A->offsets, csr_A->indices, csr_B->offsets, csr_B->indices};
+    a.nnz = csr_B->nnz;
     a.d2 = false;
     a.o = &o;
     a.st = colors_out;
@@ -796,6 +844,7 @@ BGPC_API int d2gc_color(const bgpc_csr *adj, const int32_t *order, const bgpc_op
     }
     RunArgs a;
     a.g = Graph{adj->n_rows, adj->n_rows, adj->offsets, adj->indices, adj->offsets, adj->indices};
+    a.nnz = adj->nnz;
     a.d2 = true;
     a.o = &o;
     a.st = colors_out;

@@ -270,6 +270,14 @@ __global__ void k_grow_planes(const uint64_t *old, int PHo, uint64_t *neu, int P
     }
 }
 
+// Nets of w, marked for a new scan (standing proposals): w's proposal changed.
+template <bool D2>
+__device__ __forceinline__ void mark_nets_dirty(const Graph &g, int w, uint8_t *dirty, int first, int step)
+{
+    const int nn = Acc<D2>::nets_count(g, w);
+    for (int k = first; k < nn; k += step) dirty[Acc<D2>::net_at(g, w, k)] = 1;
+}
+
 // Smallest color >= from (from >= 64) that no net of w holds, searched one
 // 64-color word at a time by one thread; -1 when the search passes the
 // allocated words.
@@ -402,24 +410,33 @@ __device__ int block_find_free_down(const uint32_t *bits, int cap_bits, int from
 template <bool D2>
 __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *ctrl, int par, int *st,
                                                   const uint64_t *mask0, int *heavy, unsigned long long *prof,
-                                                  const uint64_t *hw, int PH, int *ffc)
+                                                  const uint64_t *hw, int PH, int *ffc, uint8_t *dirty)
 {
     unsigned long long rows = 0;
     __shared__ int s_pre[65], s_beg[64];
     __shared__ int s_idx[STAGE];
     const int n = ctrl->n_w[par];
     const int lane = threadIdx.x, nb = gridDim.x, lb = xcd_remap(blockIdx.x, nb);
+    const int stride = nb * 64;
     int local_max = -1;
-    for (int base = lb * 64; base < n; base += nb * 64) {
-        int i = base + lane;
-        int w = i < n ? W[i] : -1;
-        int beg = 0, d = 0;
-        uint64_t m = 0;
-        if (w >= 0) {
-            beg = g.a_off[w];
-            d = g.a_off[w + 1] - beg;
-            if (D2) m = mask0[w];
+    // the next 64 entries and their row offsets are loaded while the current
+    // ones are colored
+    int nw_ = -1, nbeg = 0, nend = 0;
+    auto fetch = [&](int bs) {
+        int i = bs + lane;
+        nw_ = i < n ? W[i] : -1;
+        if (nw_ >= 0) {
+            nbeg = g.a_off[nw_];
+            nend = g.a_off[nw_ + 1];
         }
+    };
+    fetch(lb * 64);
+    for (int base = lb * 64; base < n; base += stride) {
+        const int w = nw_;
+        const int beg = w >= 0 ? nbeg : 0, d = w >= 0 ? nend - nbeg : 0;
+        fetch(base + stride);
+        uint64_t m = 0;
+        if (D2 && w >= 0) m = mask0[w];
         int incl = wave_incl_scan(d);
         int total = __shfl(incl, 63);
         int pre = incl - d;
@@ -446,12 +463,12 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
                 }
             }
             __syncthreads();
-            for (int k0 = 0; k0 < d; k0 += 8) {
-                uint64_t mm[8];
+            for (int k0 = 0; k0 < d; k0 += 16) {
+                uint64_t mm[16];
 #pragma unroll
-                for (int q = 0; q < 8; q++) mm[q] = (k0 + q < d) ? mask0[s_idx[pre + k0 + q]] : 0ull;
+                for (int q = 0; q < 16; q++) mm[q] = (k0 + q < d) ? mask0[s_idx[pre + k0 + q]] : 0ull;
 #pragma unroll
-                for (int q = 0; q < 8; q++) m |= mm[q];
+                for (int q = 0; q < 16; q++) m |= mm[q];
             }
         } else {
             for (int k0 = 0; k0 < d; k0 += 8) {
@@ -476,7 +493,19 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
                 if (col >= 0) ffc[w] = col;
             }
             if (col >= 0) {
-                st[w] = TENT | col;
+                const int nv = TENT | col;
+                if (!dirty) {
+                    st[w] = nv;
+                } else if (st[w] != nv) {
+                    // standing proposals: a changed proposal re-opens w's nets
+                    st[w] = nv;
+                    if (total <= STAGE) {
+                        if (D2) dirty[w] = 1;
+                        for (int k = 0; k < d; k++) dirty[s_idx[pre + k]] = 1;
+                    } else {
+                        mark_nets_dirty<D2>(g, w, dirty, 0, 1);
+                    }
+                }
                 local_max = max(local_max, col);
             } else {
                 heavy[atomicAdd(&ctrl->n_heavy, 1)] = w;
@@ -486,7 +515,7 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
     }
     local_max = wave_max(local_max);
     if (lane == 0 && local_max >= 0) max_to(&ctrl->max_color, local_max);
-    if (prof && lane == 0 && rows) atomicAdd(&prof[3 * (blockIdx.x & 63) + 2], rows);
+    if (prof && lane == 0 && rows) atomicAdd(&prof[4 * (blockIdx.x & 63) + 2], rows);
 }
 
 // Block per queued vertex.  With the higher color words allocated, the block
@@ -497,7 +526,7 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
 template <bool D2>
 __global__ void k_vcolor_wide(Graph g, const int *heavy, Ctrl *ctrl, int *st, int lds_bits, IncCtrl *ic,
                               unsigned *aff_bits, int *A, unsigned *tchg_bits, int *tcn, const uint64_t *hw, int PH,
-                              int *ffc)
+                              int *ffc, uint8_t *dirty)
 {
     extern __shared__ uint32_t dyn[];
     __shared__ int s_net[1025], s_pre[1025], s_scan[20], s_res;
@@ -550,6 +579,12 @@ __global__ void k_vcolor_wide(Graph g, const int *heavy, Ctrl *ctrl, int *st, in
             __syncthreads();
             build_forbidden<D2>(g, st, w, dyn, cap, s_net, s_pre, s_scan);
             col = block_find_free_up(dyn, cap, 0, &s_res);
+        }
+        if (dirty) {
+            // standing proposals: a changed proposal re-opens w's nets
+            const bool changed = st[w] != (TENT | col);
+            __syncthreads();
+            if (changed) mark_nets_dirty<D2>(g, w, dirty, tid, nt);
         }
         if (tid == 0) {
             int nw = TENT | col;
@@ -710,7 +745,7 @@ __device__ int pick_words(const Graph &g, int w, uint64_t m0, const uint64_t *ma
 template <bool D2>
 __global__ void __launch_bounds__(64) k_vcolor_chunked(Graph g, const int *W, Ctrl *ctrl, int par, int *st,
                                                         const uint64_t *mask0, int policy, int chunk, int lds_bits,
-                                                        const uint64_t *hw, int PH)
+                                                        const uint64_t *hw, int PH, uint8_t *dirty)
 {
     extern __shared__ uint32_t dyn[];
     __shared__ int s_net[65], s_pre[65], s_scan[4], s_res;
@@ -751,6 +786,11 @@ __global__ void __launch_bounds__(64) k_vcolor_chunked(Graph g, const int *W, Ct
                     }
                 }
                 policy_update(policy, col, s);
+                if (dirty) {
+                    // standing proposals: a changed proposal re-opens wj's nets
+                    const bool changed = st[wj] != (TENT | col);
+                    if (changed) mark_nets_dirty<D2>(g, wj, dirty, lane, WAVE);
+                }
                 if (lane == 0) {
                     st[wj] = TENT | col;
                     max_to(&ctrl->max_color, col);
@@ -941,12 +981,47 @@ struct RankIter {
 // Scan of one net of at most SMALL_NET members in rank order (distance-2:
 // the center merged in at its rank); src[k - rel] is entry k of the net
 // lists.  The first holder of a color keeps it.  Colors below 64 use a bit
-// set; larger colors are compared pairwise against earlier members.  Colors
-// are gathered eight members at a time.  Returns the number of members still
+// set; larger colors are compared pairwise against earlier members.  States
+// are gathered SCAN_BATCH members at a time.  Returns the number of members still
 // uncolored or proposed (0: the net is finished).
+//
+// Standing proposals (vertex-based rounds): a loser keeps its proposal into
+// the next round, and a net is scanned again only when one of its members'
+// proposals changed (the net is "dirty").  Every other net's verdict carries
+// over: lbits holds one bit per (net, member position), set when that member
+// loses in that net, and lcnt[u] counts the nets in which u loses; a scan
+// updates both for the positions whose verdict changed.  u loses the round
+// iff lcnt[u] > 0 -- the same verdict as a full scan, since a net's verdict
+// depends only on its members' proposals.
+struct SPState {
+    unsigned long long *lbits;   // bit of position p of net v at lpos(v) + p
+    int *lcnt;
+    uint8_t *dirty;
+};
+
+// first position of net v in lbits (distance-2 nets hold one more member)
+template <bool D2>
+__device__ __forceinline__ long sp_lpos(const Graph &g, int v)
+{
+    return (long)g.b_off[v] + (D2 ? v : 0);
+}
+
+// verdict of one position; only the calling thread changes this bit
+__device__ __forceinline__ void sp_set(const SPState &sp, long pos, int x, bool lost)
+{
+    unsigned long long *wd = sp.lbits + (pos >> 6);
+    const unsigned long long bit = 1ull << (pos & 63);
+    const bool old = (__atomic_load_n(wd, __ATOMIC_RELAXED) & bit) != 0;
+    if (old != lost) {
+        atomicXor(wd, bit);
+        atomicAdd(&sp.lcnt[x], lost ? 1 : -1);
+    }
+}
+
+constexpr int SCAN_BATCH = 16;   // member states gathered per batch (all in flight)
 template <bool D2, class Src>
 __device__ __forceinline__ int scan_net(int v, int b, int e, Src src, int rel, const int *st, uint8_t *lose,
-                                        int tent_only)
+                                        int tent_only, const SPState *sp, long lpos)
 {
     const int size = e - b + (D2 ? 1 : 0);
     int cpos = size;   // rank position of the center (distance-2)
@@ -965,17 +1040,17 @@ __device__ __forceinline__ int scan_net(int v, int b, int e, Src src, int rel, c
         if (p == cpos) return v;
         return (int)src[b + p - 1 - rel];
     };
-    uint64_t seen = 0;
+    uint64_t seen = 0, lm = 0;   // lm: positions that lose (standing proposals)
     bool wide = false;
     int pending = 0;
-    for (int p0 = 0; p0 < size; p0 += 8) {
-        int xs[8], ss[8];
+    for (int p0 = 0; p0 < size; p0 += SCAN_BATCH) {
+        int xs[SCAN_BATCH], ss[SCAN_BATCH];
 #pragma unroll
-        for (int q = 0; q < 8; q++) xs[q] = (p0 + q < size) ? member(p0 + q) : -1;
+        for (int q = 0; q < SCAN_BATCH; q++) xs[q] = (p0 + q < size) ? member(p0 + q) : -1;
 #pragma unroll
-        for (int q = 0; q < 8; q++) ss[q] = xs[q] >= 0 ? st[xs[q]] : 0;
+        for (int q = 0; q < SCAN_BATCH; q++) ss[q] = xs[q] >= 0 ? st[xs[q]] : 0;
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
+        for (int q = 0; q < SCAN_BATCH; q++) {
             int x = xs[q], s = ss[q];
             if (x < 0) continue;
             if (s < 0) {
@@ -987,27 +1062,51 @@ __device__ __forceinline__ int scan_net(int v, int b, int e, Src src, int rel, c
             if (tent_only && !tent) continue;
             int c = s & COLOR_MASK;
             if (c < 64) {
-                if ((seen >> c) & 1ull) lose[x] = 1;
+                if ((seen >> c) & 1ull) {
+                    if (sp) lm |= 1ull << (p0 + q);
+                    else lose[x] = 1;
+                }
                 seen |= 1ull << c;
             } else {
                 wide = true;
             }
         }
     }
-    if (!wide) return pending;
-    // pairwise for colors >= 64, in rank order
-    for (int p = 0; p < size; p++) {
-        int x = member(p);
-        int s = st[x];
-        if (s < 0 || (tent_only && !(s & TENT))) continue;
-        int c = s & COLOR_MASK;
-        if (c < 64) continue;
-        for (int p2 = 0; p2 < p; p2++) {
-            int t = st[member(p2)];
-            if (t < 0 || (tent_only && !(t & TENT))) continue;
-            if ((t & COLOR_MASK) == c) {
-                lose[x] = 1;
-                break;
+    if (wide) {
+        // pairwise for colors >= 64, in rank order
+        for (int p = 0; p < size; p++) {
+            int x = member(p);
+            int s = st[x];
+            if (s < 0 || (tent_only && !(s & TENT))) continue;
+            int c = s & COLOR_MASK;
+            if (c < 64) continue;
+            for (int p2 = 0; p2 < p; p2++) {
+                int t = st[member(p2)];
+                if (t < 0 || (tent_only && !(t & TENT))) continue;
+                if ((t & COLOR_MASK) == c) {
+                    if (sp) lm |= 1ull << p;
+                    else lose[x] = 1;
+                    break;
+                }
+            }
+        }
+    }
+    if (sp) {
+        // changed verdicts against the stored bits of this net's positions
+        // (size <= 64: at most two words; only this thread changes them)
+        const long w0 = lpos >> 6;
+        const int sh = (int)(lpos & 63);
+        unsigned long long a0 = __atomic_load_n(&sp->lbits[w0], __ATOMIC_RELAXED);
+        unsigned long long a1 = sh + size > 64 ? __atomic_load_n(&sp->lbits[w0 + 1], __ATOMIC_RELAXED) : 0ull;
+        unsigned long long old = (a0 >> sh) | (sh ? (a1 << (64 - sh)) : 0ull);
+        if (size < 64) old &= (1ull << size) - 1ull;
+        unsigned long long chg = old ^ lm;
+        if (chg) {
+            atomicXor(&sp->lbits[w0], chg << sh);
+            if (sh + size > 64) atomicXor(&sp->lbits[w0 + 1], chg >> (64 - sh));
+            for (unsigned long long m = chg; m; m &= m - 1) {
+                int p = __builtin_ctzll(m);
+                atomicAdd(&sp->lcnt[member(p)], ((lm >> p) & 1ull) ? 1 : -1);
             }
         }
     }
@@ -1021,27 +1120,95 @@ __device__ __forceinline__ int scan_net(int v, int b, int e, Src src, int rel, c
 // until a net-based round evicts (the driver then clears the marks).  With
 // tent_only, only proposed colors take part (after a vertex-based round no
 // colored vertex can clash).
+// Standing proposals: only dirty nets are scanned.  The wave sweeps its
+// stretches' flags, queues the dirty nets in LDS and scans them 64 at a
+// time, one net per lane, members read straight from the net lists.
+template <bool D2>
+__device__ void conflict_dirty(const Graph &g, const int *st, uint8_t *done, const SPState &sp, int lb, int nb,
+                               int *q, int &walked_nets, int &walked_members, int &scanned_members, bool prof)
+{
+    const int lane = threadIdx.x, stride = nb * 64;
+    int qn = 0;
+    auto drain = [&](int cnt) {
+        int v = lane < cnt ? q[lane] : -1;
+        if (v >= 0) {
+            const int b = g.b_off[v], e = g.b_off[v + 1];
+            const int sz = e - b + (D2 ? 1 : 0);
+            if (sz >= 2 && sz <= SMALL_NET) {
+                int pending = scan_net<D2>(v, b, e, g.b_idx, 0, st, nullptr, 1, &sp, (long)b + (D2 ? v : 0));
+                if (pending == 0) done[v] = 1;
+                scanned_members += sz;
+                walked_nets++;
+            }
+            if (sz <= SMALL_NET) sp.dirty[v] = 0;   // larger nets: k_conflict_big
+        }
+        __syncthreads();
+        // move the rest of the queue to its front
+        int rest = qn - cnt;
+        int keep = lane < rest ? q[cnt + lane] : 0;
+        __syncthreads();
+        if (lane < rest) q[lane] = keep;
+        qn = rest;
+        __syncthreads();
+    };
+    for (int base = lb * 64; base < g.n_b; base += stride) {
+        const int v = base + lane;
+        const bool d = v < g.n_b && sp.dirty[v] && !done[v];
+        const uint64_t bal = __ballot(d);
+        if (d) q[qn + __builtin_popcountll(bal & ((1ull << lane) - 1ull))] = v;
+        qn += __builtin_popcountll(bal);
+        __syncthreads();
+        if (qn >= 64) drain(64);
+    }
+    if (qn > 0) drain(qn);
+}
+
 template <bool D2>
 __global__ void __launch_bounds__(64) k_conflict_small(Graph g, const int *st, uint8_t *lose, uint8_t *done,
-                                                       int tent_only, unsigned long long *prof)
+                                                       int tent_only, unsigned long long *prof, SPState sp)
 {
     int walked_nets = 0, walked_members = 0;
     __shared__ int s_idx[STAGE];
     const int lane = threadIdx.x, nb = gridDim.x, lb = xcd_remap(blockIdx.x, nb);
-    for (int base = lb * 64; base < g.n_b; base += nb * 64) {
-        int v = base + lane;
-        bool act = false;
-        int b = 0, e = 0;
+    const int stride = nb * 64;
+    const bool spm = sp.lbits != nullptr;
+    if (spm) {
+        // the round's nets are counted by k_census (profiling only)
+        int scanned = 0;
+        conflict_dirty<D2>(g, st, done, sp, lb, nb, s_idx, walked_nets, walked_members, scanned, prof != nullptr);
+        if (prof) {
+            int ws = wave_sum(scanned);
+            if (lane == 0 && ws) atomicAdd(&prof[4 * (blockIdx.x & 63) + 3], (unsigned long long)ws);
+        }
+        return;
+    }
+    // the next stretch's offsets and flags are loaded while the current one
+    // is scanned
+    int nb_ = 0, ne_ = 0, noff0 = 0, noffe = 0;
+    uint8_t nskip = 1;
+    auto fetch = [&](int bs) {
+        if (bs >= g.n_b) return;
+        int v = bs + lane;
         if (v < g.n_b) {
-            b = g.b_off[v];
-            e = g.b_off[v + 1];
+            nb_ = g.b_off[v];
+            ne_ = g.b_off[v + 1];
+            nskip = done[v] | (spm ? (uint8_t)!sp.dirty[v] : (uint8_t)0);
+        }
+        noff0 = g.b_off[bs];
+        noffe = g.b_off[min(bs + 64, g.n_b)];
+    };
+    fetch(lb * 64);
+    for (int base = lb * 64; base < g.n_b; base += stride) {
+        const int v = base + lane;
+        const int b = nb_, e = ne_, off0 = noff0, seg = noffe - noff0;
+        const uint8_t skip = nskip;
+        fetch(base + stride);
+        bool act = false;
+        if (v < g.n_b) {
             int sz = e - b + (D2 ? 1 : 0);
-            act = sz >= 2 && sz <= SMALL_NET && !done[v];
+            act = sz >= 2 && sz <= SMALL_NET && !skip;
         }
         if (!__ballot(act)) continue;
-        int vend = min(base + 64, g.n_b);
-        int off0 = g.b_off[base];
-        int seg = g.b_off[vend] - off0;
         bool staged = seg <= STAGE;
         if (staged) {
             // every load of the stretch in flight before the first LDS store
@@ -1059,9 +1226,12 @@ __global__ void __launch_bounds__(64) k_conflict_small(Graph g, const int *st, u
         }
         __syncthreads();
         if (act) {
-            int pending = staged ? scan_net<D2>(v, b, e, (const int *)s_idx, off0, st, lose, tent_only)
-                                 : scan_net<D2>(v, b, e, g.b_idx, 0, st, lose, tent_only);
+            const SPState *spp = spm ? &sp : nullptr;
+            const long lpos = (long)b + (D2 ? v : 0);
+            int pending = staged ? scan_net<D2>(v, b, e, (const int *)s_idx, off0, st, lose, tent_only, spp, lpos)
+                                 : scan_net<D2>(v, b, e, g.b_idx, 0, st, lose, tent_only, spp, lpos);
             if (pending == 0) done[v] = 1;
+            if (spm) sp.dirty[v] = 0;
         }
         walked_nets += act ? 1 : 0;
         walked_members += act ? e - b + (D2 ? 1 : 0) : 0;
@@ -1070,9 +1240,40 @@ __global__ void __launch_bounds__(64) k_conflict_small(Graph g, const int *st, u
     if (prof) {
         int wn = wave_sum(walked_nets), wm = wave_sum(walked_members);
         if (lane == 0 && wn) {
-            atomicAdd(&prof[3 * (blockIdx.x & 63) + 0], (unsigned long long)wn);
-            atomicAdd(&prof[3 * (blockIdx.x & 63) + 1], (unsigned long long)wm);
+            atomicAdd(&prof[4 * (blockIdx.x & 63) + 0], (unsigned long long)wn);
+            atomicAdd(&prof[4 * (blockIdx.x & 63) + 1], (unsigned long long)wm);
+            atomicAdd(&prof[4 * (blockIdx.x & 63) + 3], (unsigned long long)wm);
         }
+    }
+}
+
+// Profiling only (launched after the timed removal launch): the round's nets
+// of at most SMALL_NET members -- those with a member still uncolored or
+// proposed -- and their sizes, the units the removal step is responsible for.
+template <bool D2>
+__global__ void k_census(Graph g, const int *st, unsigned long long *prof)
+{
+    int nets = 0, mem = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n_b; v += gridDim.x * blockDim.x) {
+        const int sz = Acc<D2>::size(g, v);
+        if (sz < 2 || sz > SMALL_NET) continue;
+        bool open = false;
+        for (int k0 = 0; k0 < sz && !open; k0 += SCAN_BATCH) {
+            int ss[SCAN_BATCH];
+#pragma unroll
+            for (int j = 0; j < SCAN_BATCH; j++) ss[j] = k0 + j < sz ? st[Acc<D2>::member(g, v, k0 + j)] : 0;
+#pragma unroll
+            for (int j = 0; j < SCAN_BATCH; j++) open = open || ss[j] < 0 || (ss[j] & TENT);
+        }
+        if (open) {
+            nets++;
+            mem += sz;
+        }
+    }
+    int wn = wave_sum(nets), wm = wave_sum(mem);
+    if (lane_id() == 0 && wn) {
+        atomicAdd(&prof[4 * (blockIdx.x & 63) + 0], (unsigned long long)wn);
+        atomicAdd(&prof[4 * (blockIdx.x & 63) + 1], (unsigned long long)wm);
     }
 }
 
@@ -1083,7 +1284,7 @@ __device__ __forceinline__ unsigned hash_color(int c) { return (unsigned)c * 265
 // windows of WIN_COLORS with a direct-mapped table.
 template <bool D2>
 __global__ void k_conflict_big(Graph g, const int *st, uint8_t *lose, uint8_t *done, const int *big,
-                               const int *n_big_p, Ctrl *ctrl, int tent_only)
+                               const int *n_big_p, Ctrl *ctrl, int tent_only, SPState sp)
 {
     extern __shared__ int sh[];
     __shared__ int s_scan[20];
@@ -1091,7 +1292,8 @@ __global__ void k_conflict_big(Graph g, const int *st, uint8_t *lose, uint8_t *d
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int bi = blockIdx.x; bi < n_big; bi += gridDim.x) {
         int v = big[bi];
-        if (done[v]) continue;
+        if (done[v] || (sp.lbits && !sp.dirty[v])) continue;
+        const long lpos = sp.lbits ? sp_lpos<D2>(g, v) : 0;
         int sz = Acc<D2>::size(g, v);
         int pending = 0;
         for (int k = tid; k < sz; k += nt) {
@@ -1099,6 +1301,7 @@ __global__ void k_conflict_big(Graph g, const int *st, uint8_t *lose, uint8_t *d
             pending += (s < 0 || (s & TENT)) ? 1 : 0;
         }
         pending = block_sum(pending, s_scan);
+        if (sp.lbits && tid == 0) sp.dirty[v] = 0;
         if (pending == 0) {
             if (tid == 0) done[v] = 1;
             continue;
@@ -1137,7 +1340,8 @@ __global__ void k_conflict_big(Graph g, const int *st, uint8_t *lose, uint8_t *d
                 if (c < 0) continue;
                 unsigned h = hash_color(c) & (cap - 1);
                 while (keys[h] != c) h = (h + 1) & (cap - 1);
-                if (minr[h] != x) lose[x] = 1;
+                if (sp.lbits) sp_set(sp, lpos + k, x, minr[h] != x);
+                else if (minr[h] != x) lose[x] = 1;
             }
             __syncthreads();
         } else {
@@ -1158,7 +1362,10 @@ __global__ void k_conflict_big(Graph g, const int *st, uint8_t *lose, uint8_t *d
                     int s = st[x];
                     if (tent_only && !(s >= 0 && (s & TENT))) continue;
                     int c = cur_color(s) - base;
-                    if (c >= 0 && c < WIN_COLORS && sh[c] != x) lose[x] = 1;
+                    if (c >= 0 && c < WIN_COLORS) {
+                        if (sp.lbits) sp_set(sp, lpos + k, x, sh[c] != x);
+                        else if (sh[c] != x) lose[x] = 1;
+                    }
                 }
                 __syncthreads();
             }
@@ -1179,7 +1386,7 @@ template <bool D2>
 __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, Ctrl *ctrl, int par, int *st,
                                                       uint8_t *lose, uint64_t *mask0, int *tile_count,
                                                       RoundRec *rec, int round, int update_masks, uint64_t *hw,
-                                                      int PH)
+                                                      int PH, const int *lcnt)
 {
     constexpr int NWV = TILE_BLOCK / WAVE;
     __shared__ int s_scan[8];
@@ -1206,7 +1413,7 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
 #pragma unroll
         for (int k = 0; k < KS; k++) {
             ss[k] = us[k] >= 0 ? st[us[k]] : -1;
-            ls[k] = us[k] >= 0 ? lose[us[k]] : 0;
+            ls[k] = us[k] >= 0 ? (lcnt ? (uint8_t)(lcnt[us[k]] > 0) : lose[us[k]]) : 0;
         }
         for (int k = 0; k < KS; k++) {
             int beg = 0, d = 0;
@@ -1215,9 +1422,11 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
                 int u = us[k];
                 int s = ss[k];
                 if (ls[k]) {
-                    lose[u] = 0;
-                    if (s >= 0 && !(s & TENT)) evicted++;
-                    st[u] = -1;
+                    if (!lcnt) {   // standing proposals: the loser keeps its proposal
+                        lose[u] = 0;
+                        if (s >= 0 && !(s & TENT)) evicted++;
+                        st[u] = -1;
+                    }
                     cnt++;
                 } else if (s < 0) {
                     cnt++;
@@ -1311,7 +1520,7 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_compact(const int *list, int n_s
             bool f = false;
             if (i < n) {
                 u = list ? list[i] : i;
-                f = st[u] < 0;
+                f = st[u] < 0 || (st[u] & TENT);   // uncolored, or a standing proposal
             }
             u_k[k] = u;
             bal[k] = __ballot(f);

@@ -41,7 +41,7 @@ def test_binding_struct_layouts_match_header(tmp_path):
 int main(void) {
   printf("csr %zu %zu %zu\n", sizeof(bgpc_csr), offsetof(bgpc_csr, nnz), offsetof(bgpc_csr, indices));
   printf("log %zu %zu\n", sizeof(bgpc_round_log), offsetof(bgpc_round_log, max_color));
-  printf("prof %zu %zu\n", sizeof(bgpc_profile), offsetof(bgpc_profile, bytes));
+  printf("prof %zu %zu %zu\n", sizeof(bgpc_profile), offsetof(bgpc_profile, bytes), offsetof(bgpc_profile, bytes_scanned));
   printf("opts %zu %zu %zu %zu\n", sizeof(bgpc_opts), offsetof(bgpc_opts, stream), offsetof(bgpc_opts, log),
          offsetof(bgpc_opts, prof));
   printf("stats %zu %zu\n", sizeof(bgpc_stats), offsetof(bgpc_stats, card_std));
@@ -56,7 +56,7 @@ int main(void) {
         got[k] = [int(v) for v in vals]
     assert got["csr"] == [ctypes.sizeof(bgpc.Csr), bgpc.Csr.nnz.offset, bgpc.Csr.indices.offset]
     assert got["log"] == [ctypes.sizeof(bgpc.RoundLog), bgpc.RoundLog.max_color.offset]
-    assert got["prof"] == [ctypes.sizeof(bgpc.Profile), bgpc.Profile.bytes.offset]
+    assert got["prof"] == [ctypes.sizeof(bgpc.Profile), bgpc.Profile.bytes.offset, bgpc.Profile.bytes_scanned.offset]
     assert got["opts"] == [ctypes.sizeof(bgpc.Opts), bgpc.Opts.stream.offset, bgpc.Opts.log.offset,
                            bgpc.Opts.prof.offset]
     assert got["stats"] == [ctypes.sizeof(bgpc.Stats), bgpc.Stats.card_std.offset]

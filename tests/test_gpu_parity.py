@@ -308,11 +308,13 @@ def test_profile_counters(cuda):
     A, B = bgpc.upload_bipartite(g)
     out = torch.empty(g.n_a, dtype=torch.int32, device=cuda)
     for kid in (bgpc.PROF_CONFLICT, bgpc.PROF_COLOR):
-        pr = bgpc.Profile(kid, 0, 0.0, 0.0)
+        pr = bgpc.Profile(kid, 0, 0.0, 0.0, 0.0)
         r = bgpc.bgpc_color(A, B, None, out, prof=pr)
         assert r.status == 0
         # the lookahead may queue a few empty rounds after the last one
         assert r.rounds <= pr.launches <= r.rounds + 8 and pr.ms > 0 and pr.bytes > 0
+        # the removal scan reads no more than the round's nets
+        assert 0 < pr.bytes_scanned <= pr.bytes * (1 + 1e-9)
 
 
 @pytest.mark.parametrize("shape", [(300, 20000, 3, 30, 5), (1200, 60000, 3, 30, 6), (64, 5000, 2, 9, 7)],
