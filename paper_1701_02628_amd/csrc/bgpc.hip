@@ -326,8 +326,7 @@ int run(const RunArgs &a)
     k_fill_i32<<<1, 64, 0, s>>>(shape, 0, 8);
     k_fill_i32<<<grid_for(rec_cap * (long)sizeof(RoundRec) / 4, nthr, di.cus * 4), nthr, 0, s>>>(
         (int *)rec, 0, rec_cap * (long)sizeof(RoundRec) / 4);
-    k_net_shape<D2><<<g_b, nthr, 0, s>>>(g, &shape[0], big, &shape[1], (unsigned long long *)&shape[4]);
-    k_two_hop_bound<D2><<<g_a, nthr, 0, s>>>(g, &shape[2]);
+    k_net_shape<D2><<<g_b, nthr, 0, s>>>(g, &shape[0], big, &shape[1], (unsigned long long *)&shape[4], &shape[2]);
     LAUNCH_CHECK();
     if (hipMemcpyAsync(h_shape, shape, sizeof(h_shape), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
@@ -337,7 +336,8 @@ int run(const RunArgs &a)
     {
         const int max_net = h_shape[0];
         const int n_big = h_shape[1];
-        const long two_hop = h_shape[2];
+        // distance-2 degree bound: most nets of a vertex x largest net
+        const long two_hop = std::min<long>((long)h_shape[2] * (long)max_net, 1L << 30);
         unsigned long long walk;
         std::memcpy(&walk, &h_shape[4], sizeof(walk));
         // small dense graphs under plain first-fit vertex rounds: one workgroup

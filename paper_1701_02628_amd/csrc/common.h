@@ -140,6 +140,14 @@ __device__ __forceinline__ int wave_min(int v)
 // block-wide exclusive scan for blockDim.x <= 1024 (multiple of 64);
 // `scratch` holds at least blockDim.x / 64 + 1 ints.  Returns the exclusive
 // prefix; *total receives the block sum.
+// orders one wave's LDS writes before its later LDS reads (no block barrier)
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ int block_excl_scan(int v, int *scratch, int *total)
 {
     int lane = lane_id();

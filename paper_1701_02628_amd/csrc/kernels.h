@@ -130,9 +130,10 @@ __global__ void k_init_ctrl(Ctrl *c, int n_w, int max_color)
 // Per-graph shape figures: largest net, and a bound on every vertex's
 // distance-2 neighbourhood (sum of the sizes of its nets); big-net list.
 template <bool D2>
-__global__ void k_net_shape(Graph g, int *max_net, int *big_list, int *n_big, unsigned long long *walk)
+__global__ void k_net_shape(Graph g, int *max_net, int *big_list, int *n_big, unsigned long long *walk,
+                            int *max_deg)
 {
-    int local = 0;
+    int local = 0, deg = 0;
     unsigned long long w = 0;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n_b; v += gridDim.x * blockDim.x) {
         int sz = Acc<D2>::size(g, v);
@@ -140,24 +141,15 @@ __global__ void k_net_shape(Graph g, int *max_net, int *big_list, int *n_big, un
         w += (unsigned long long)sz * (unsigned long long)sz;
         if (sz > SMALL_NET) big_list[atomicAdd(n_big, 1)] = v;
     }
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < g.n_a; u += gridDim.x * blockDim.x)
+        deg = max(deg, Acc<D2>::nets_count(g, u));
     local = wave_max(local);
-    if (lane_id() == 0) max_to(max_net, local);
-    if (w) atomicAdd(walk, w);
-}
-
-template <bool D2>
-__global__ void k_two_hop_bound(Graph g, int *bound)
-{
-    long local = 0;
-    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < g.n_a; u += gridDim.x * blockDim.x) {
-        long s = 0;
-        int k = Acc<D2>::nets_count(g, u);
-        for (int j = 0; j < k; j++) s += Acc<D2>::size(g, Acc<D2>::net_at(g, u, j));
-        local = max(local, s);
+    deg = wave_max(deg);
+    if (lane_id() == 0) {
+        max_to(max_net, local);
+        max_to(max_deg, deg);
     }
-    int l32 = (int)min(local, (long)0x3fffffff);
-    l32 = wave_max(l32);
-    if (lane_id() == 0) max_to(bound, l32);
+    if (w) atomicAdd(walk, w);
 }
 
 // owner(u): the largest net containing u, ties to the lowest net id
@@ -1451,13 +1443,16 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
                     mx = max(mx, col);
                 }
             }
-            if (update_masks) {   // uniform: every wave runs every k
+            if (update_masks) {
+                // each wave walks its own winners' rows (its own LDS slice:
+                // wave-level ordering suffices; waves without winners skip)
                 int incl = wave_incl_scan(d);
                 int total = __shfl(incl, 63);
+                if (total == 0) continue;
                 s_pre[wid][lane] = incl - d;
                 s_beg[wid][lane] = beg;
                 s_bit[wid][lane] = bit;
-                __syncthreads();
+                wave_sync();
                 for (int f0 = 0; f0 < total; f0 += 256) {
                     int tgt[4];
                     unsigned long long bt[4];
@@ -1476,7 +1471,7 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
                     for (int q = 0; q < 4; q++)
                         if (tgt[q] >= 0) atomicOr((unsigned long long *)&mask0[tgt[q]], bt[q]);
                 }
-                __syncthreads();
+                wave_sync();
             }
         }
         cnt = block_sum(cnt, s_scan);
