@@ -433,10 +433,31 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
         int total = __shfl(incl, 63);
         int pre = incl - d;
         rows += total;
-        s_pre[lane] = pre;
-        s_beg[lane] = beg;
-        __syncthreads();
-        if (total <= STAGE) {
+        // the worklist is ascending, so the 64 rows lie in one stretch of the
+        // row ids; when that stretch fits, it is copied flat (rows of
+        // vertices between worklist entries included), else row by row
+        const int beg0 = __shfl(beg, 0);
+        const int span = wave_max(w >= 0 ? beg + d : 0) - beg0;
+        const bool flat = span <= STAGE;
+        const int sofs = flat ? beg - beg0 : pre;   // lane's row in s_idx
+        if (flat) {
+            for (int f0 = 0; f0 < span; f0 += 1024) {
+                int v[16];
+#pragma unroll
+                for (int q = 0; q < 16; q++) {
+                    int f = f0 + q * 64 + lane;
+                    v[q] = f < span ? g.a_idx[beg0 + f] : 0;
+                }
+#pragma unroll
+                for (int q = 0; q < 16; q++) {
+                    int f = f0 + q * 64 + lane;
+                    if (f < span) s_idx[f] = v[q];
+                }
+            }
+        } else if (total <= STAGE) {
+            s_pre[lane] = pre;
+            s_beg[lane] = beg;
+            __syncthreads();
             for (int f0 = 0; f0 < total; f0 += 1024) {
                 int v[16];
 #pragma unroll
@@ -454,11 +475,14 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
                     if (f < total) s_idx[f] = v[q];
                 }
             }
-            __syncthreads();
+        }
+        __syncthreads();
+        const bool staged = flat || total <= STAGE;
+        if (staged) {
             for (int k0 = 0; k0 < d; k0 += 16) {
                 uint64_t mm[16];
 #pragma unroll
-                for (int q = 0; q < 16; q++) mm[q] = (k0 + q < d) ? mask0[s_idx[pre + k0 + q]] : 0ull;
+                for (int q = 0; q < 16; q++) mm[q] = (k0 + q < d) ? mask0[s_idx[sofs + k0 + q]] : 0ull;
 #pragma unroll
                 for (int q = 0; q < 16; q++) m |= mm[q];
             }
@@ -491,9 +515,9 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
                 } else if (st[w] != nv) {
                     // standing proposals: a changed proposal re-opens w's nets
                     st[w] = nv;
-                    if (total <= STAGE) {
+                    if (staged) {
                         if (D2) dirty[w] = 1;
-                        for (int k = 0; k < d; k++) dirty[s_idx[pre + k]] = 1;
+                        for (int k = 0; k < d; k++) dirty[s_idx[sofs + k]] = 1;
                     } else {
                         mark_nets_dirty<D2>(g, w, dirty, 0, 1);
                     }
