@@ -432,21 +432,16 @@ __device__ void dense_propagate(const BatchItem &it, const Scratch &sc, const in
     }
 }
 
-__global__ void __launch_bounds__(BATCH_BLOCK) k_batch(BatchItem *items, const int *order, int n_items, int *next)
+// All rounds of one graph on the calling workgroup (every thread calls);
+// returns the rounds run, *status 0 or -6 (round cap reached).
+__device__ int batch_run_item(const BatchItem it, int *status)
 {
     __shared__ int s_scan[20];
-    __shared__ int s_item;
     __shared__ int s_maxc;
     __shared__ int s_nl;
     __shared__ int s_cmin, s_cmax, s_nslot;
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (;;) {
-        if (tid == 0) s_item = atomicAdd(next, 1);
-        __syncthreads();
-        const int k = s_item;
-        __syncthreads();
-        if (k >= n_items) break;
-        const BatchItem it = items[order[k]];
+    {
         const Scratch sc = batch_scratch(it);
         int *st = it.colors;
         const int n_a = it.n_a, n_b = it.n_b;
@@ -614,7 +609,7 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch(BatchItem *items, const i
             rounds++;
             __syncthreads();
         }
-        const int status = nw == 0 ? 0 : -6;
+        *status = nw == 0 ? 0 : -6;
         if (it.host_done) {
             // hand the graph over to the host: colors first, then (after every
             // wave's system-scope fence, which also writes back this graph's
@@ -624,15 +619,88 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch(BatchItem *items, const i
             __threadfence_system();
             __syncthreads();
             if (tid == 0) {
-                __atomic_store_n(it.host_done, ((long long)rounds << 32) | (unsigned)(status + 256), __ATOMIC_RELAXED);
+                __atomic_store_n(it.host_done, ((long long)rounds << 32) | (unsigned)(*status + 256),
+                                 __ATOMIC_RELAXED);
                 __threadfence_system();
             }
         }
-        if (tid == 0) {
+        __syncthreads();
+        return rounds;
+    }
+}
+
+__global__ void __launch_bounds__(BATCH_BLOCK) k_batch(BatchItem *items, const int *order, int n_items, int *next)
+{
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(next, 1);
+        __syncthreads();
+        const int k = s_item;
+        __syncthreads();
+        if (k >= n_items) break;
+        int status = 0;
+        const int rounds = batch_run_item(items[order[k]], &status);
+        if (threadIdx.x == 0) {
             items[order[k]].rounds = rounds;
             items[order[k]].status = status;
         }
         __syncthreads();
+    }
+}
+
+// Serving ring in coherent pinned host memory: the host writes descriptors
+// and then publishes them by raising tail; workgroups claim them in order
+// through a device counter.
+struct ServeRing {
+    int tail;       // descriptors published (items[k % cap] for k < tail)
+    int stop;       // set by the host: workgroups exit
+    int pad[62];
+    BatchItem items[1];
+};
+
+// Persistent serving kernel.  A workgroup claims the next published
+// descriptor, invalidates its caches (the descriptor's arrays were copied in
+// by DMA after this kernel started, possibly into memory an earlier request
+// used), copies the descriptor to LDS and runs the graph; the graph's
+// completion reaches the host through its done word.  A workgroup leaves
+// after idle_spins empty polls (about 20 ms) or when stop is set, so every
+// wave exits; the host launches the kernel again when it publishes work and
+// none is running.
+__global__ void __launch_bounds__(BATCH_BLOCK) k_serve(ServeRing *ring, int cap, int *head, int idle_spins)
+{
+    __shared__ int s_k;
+    __shared__ unsigned long long s_desc[(sizeof(BatchItem) + 7) / 8];
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            int k = -1;
+            for (int spin = 0; spin < idle_spins; spin++) {
+                const int t = __hip_atomic_load(&ring->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                const int h = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (h < t) {
+                    if (atomicCAS(head, h, h + 1) == h) {
+                        k = h;
+                        break;
+                    }
+                    spin = 0;   // another workgroup took it: not idle
+                    continue;
+                }
+                if (__hip_atomic_load(&ring->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+                __builtin_amdgcn_s_sleep(64);
+            }
+            if (k >= 0) __threadfence_system();
+            s_k = k;
+        }
+        __syncthreads();
+        const int k = s_k;
+        if (k < 0) break;
+        const unsigned long long *src = (const unsigned long long *)&ring->items[k % cap];
+        for (int i = tid; i < (int)((sizeof(BatchItem) + 7) / 8); i += blockDim.x) s_desc[i] = src[i];
+        __syncthreads();
+        const BatchItem it = *(const BatchItem *)s_desc;
+        __syncthreads();
+        int status = 0;
+        batch_run_item(it, &status);
     }
 }
 

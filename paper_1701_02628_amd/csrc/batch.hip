@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -363,6 +364,7 @@ struct Req {
     int status = 0, rounds = 0;
     int mode = MODE_MASKS, cap = 128;
     bool device = false;                 // whole-device path
+    int slot = -1;                       // ring slot once published
     volatile long long *done = nullptr;  // pinned done word (batched path)
     // layout inside the request's pool block: uploaded arrays first, then
     // colors, then scratch; the done word sits at o_done in the staging area
@@ -424,12 +426,6 @@ void layout(Req *q)
     q->bytes = o;
 }
 
-struct Group {
-    hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
-    size_t tbl_off = 0, tbl_bytes = 0;
-};
-
 }  // namespace
 
 struct bgpc_session {
@@ -440,8 +436,17 @@ struct bgpc_session {
     char *hpool = nullptr;
     char *hpool_dev = nullptr;      // device view of hpool
     RangeAlloc *alloc = nullptr;
-    std::vector<hipStream_t> streams;
-    std::vector<hipEvent_t> events;
+    std::vector<hipStream_t> streams;   // uploads
+    std::vector<hipEvent_t> events;     // free upload events
+    hipStream_t kstream = nullptr;      // the serving kernel
+    hipEvent_t kdone = nullptr;         // recorded after each serving-kernel launch
+    bool klaunched = false;
+    ServeRing *ring = nullptr, *ring_dev = nullptr;
+    int cap = 0;                        // ring slots
+    std::vector<Req *> slot_owner;      // request in each ring slot until it is done
+    int *head = nullptr;                // device: descriptors claimed
+    int tail = 0;                       // descriptors published
+    int cus = 256;
     hipStream_t dev_stream = nullptr;
     int rr = 0;
     int slots_used = 0;
@@ -450,110 +455,105 @@ struct bgpc_session {
     std::deque<Req *> submitted;    // guarded by mu
     std::vector<Req *> completed;   // guarded by mu
     std::deque<Req *> dev_queue;    // guarded by mu
-    std::deque<Req *> pending;      // worker only
-    std::vector<Req *> running;     // worker only: launched, done word not yet seen
-    std::vector<Group *> inflight;  // worker only
+    std::deque<Req *> pending;      // worker only: waiting for admission
+    std::deque<std::pair<Req *, hipEvent_t>> uploading;   // worker only: arrays on their way
+    std::vector<Req *> running;     // worker only: published, done word not yet seen
     std::thread worker, dev_worker;
     bool stop = false;              // guarded by mu
     bool dev_stop = false;          // guarded by mu: set once the worker has handed over every request
     int error = 0;
 
-    bool launch(std::vector<Req *> &grp);
+    bool upload(Req *q);
+    bool publish(Req *q);
     void finish(Req *q);
     void loop();
     void dev_loop();
     void dev_run(Req *q);
 };
 
-bool bgpc_session::launch(std::vector<Req *> &grp)
+// copies a request's arrays into its pool block (staged through pinned
+// memory unless they are pinned already) and queues the copies' event
+bool bgpc_session::upload(Req *q)
 {
-    const int n = (int)grp.size();
-    Group *g = new Group();
-    const size_t o_ord = al256((long long)sizeof(BatchItem) * n), o_next = o_ord + al256(4ll * n);
-    g->tbl_bytes = o_next + 256;
-    if (!alloc->alloc(g->tbl_bytes, &g->tbl_off)) {
-        delete g;
-        return false;
-    }
-    g->stream = streams[rr++ % streams.size()];
+    const bgpc_request &r = q->r;
+    hipStream_t s = streams[rr++ % streams.size()];
+    hipEvent_t ev = nullptr;
     if (!events.empty()) {
-        g->done = events.back();
+        ev = events.back();
         events.pop_back();
-    } else if (hipEventCreateWithFlags(&g->done, hipEventDisableTiming) != hipSuccess) {
-        alloc->release(g->tbl_off, g->tbl_bytes);
-        delete g;
-        error = BGPC_E_HIP;
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
         return false;
     }
-    char *ht = hpool + g->tbl_off, *dt = dpool + g->tbl_off;
-    BatchItem *h_items = (BatchItem *)ht;
-    int *h_order = (int *)(ht + o_ord);
-    hipStream_t s = g->stream;
+    char *hb = hpool + q->off, *db = dpool + q->off;
     bool ok = true;
-    for (int i = 0; i < n; i++) {
-        Req *q = grp[i];
-        const bgpc_request &r = q->r;
-        char *hb = hpool + q->off, *db = dpool + q->off;
-        if (r.flags & BGPC_REQ_PINNED) {
-            ok = ok && hipMemcpyAsync(db + q->o_aoff, r.a_off, 4 * ((size_t)r.n_a + 1), hipMemcpyHostToDevice, s) ==
-                           hipSuccess;
-            ok = ok && (!r.nnz || hipMemcpyAsync(db + q->o_aidx, r.a_idx, 4 * (size_t)r.nnz, hipMemcpyHostToDevice,
-                                                 s) == hipSuccess);
-            ok = ok && hipMemcpyAsync(db + q->o_boff, r.b_off, 4 * ((size_t)r.n_b + 1), hipMemcpyHostToDevice, s) ==
-                           hipSuccess;
-            ok = ok && (!r.nnz || hipMemcpyAsync(db + q->o_bidx, r.b_idx, 4 * (size_t)r.nnz, hipMemcpyHostToDevice,
-                                                 s) == hipSuccess);
-        } else {
-            std::memcpy(hb + q->o_aoff, r.a_off, 4 * ((size_t)r.n_a + 1));
-            if (r.nnz) std::memcpy(hb + q->o_aidx, r.a_idx, 4 * (size_t)r.nnz);
-            std::memcpy(hb + q->o_boff, r.b_off, 4 * ((size_t)r.n_b + 1));
-            if (r.nnz) std::memcpy(hb + q->o_bidx, r.b_idx, 4 * (size_t)r.nnz);
-            ok = ok && hipMemcpyAsync(db, hb, q->o_col, hipMemcpyHostToDevice, s) == hipSuccess;
-        }
-        q->done = (volatile long long *)(hb + q->o_done);
-        *q->done = 0;
-        BatchItem &b = h_items[i];
-        b = BatchItem{};
-        b.n_a = r.n_a;
-        b.n_b = r.n_b;
-        b.a_off = (const int *)(db + q->o_aoff);
-        b.a_idx = (const int *)(db + q->o_aidx);
-        b.b_off = (const int *)(db + q->o_boff);
-        b.b_idx = (const int *)(db + q->o_bidx);
-        b.colors = (int *)(db + q->o_col);
-        b.scratch = db + q->o_scr;
-        b.max_rounds = max_rounds > 0 ? max_rounds : r.n_a + 65;
-        b.mode = q->mode;
-        b.cap = q->cap;
-        b.status = -1;
-        b.nnz = (int)r.nnz;
-        char *hb_dev = hpool_dev + q->off;
-        void *user_dev = nullptr;
-        if ((r.flags & BGPC_REQ_PINNED) && r.n_a && hipHostGetDevicePointer(&user_dev, r.colors_out, 0) != hipSuccess) {
-            (void)hipGetLastError();
-            ok = false;
-        }
-        b.host_colors = (r.flags & BGPC_REQ_PINNED) ? (int *)user_dev : (int *)(hb_dev + q->o_col);
-        b.host_done = (long long *)(hb_dev + q->o_done);
-        h_order[i] = i;
+    if (r.flags & BGPC_REQ_PINNED) {
+        ok = ok && hipMemcpyAsync(db + q->o_aoff, r.a_off, 4 * ((size_t)r.n_a + 1), hipMemcpyHostToDevice, s) ==
+                       hipSuccess;
+        ok = ok && (!r.nnz || hipMemcpyAsync(db + q->o_aidx, r.a_idx, 4 * (size_t)r.nnz, hipMemcpyHostToDevice, s) ==
+                                  hipSuccess);
+        ok = ok && hipMemcpyAsync(db + q->o_boff, r.b_off, 4 * ((size_t)r.n_b + 1), hipMemcpyHostToDevice, s) ==
+                       hipSuccess;
+        ok = ok && (!r.nnz || hipMemcpyAsync(db + q->o_bidx, r.b_idx, 4 * (size_t)r.nnz, hipMemcpyHostToDevice, s) ==
+                                  hipSuccess);
+    } else {
+        std::memcpy(hb + q->o_aoff, r.a_off, 4 * ((size_t)r.n_a + 1));
+        if (r.nnz) std::memcpy(hb + q->o_aidx, r.a_idx, 4 * (size_t)r.nnz);
+        std::memcpy(hb + q->o_boff, r.b_off, 4 * ((size_t)r.n_b + 1));
+        if (r.nnz) std::memcpy(hb + q->o_bidx, r.b_idx, 4 * (size_t)r.nnz);
+        ok = ok && hipMemcpyAsync(db, hb, q->o_col, hipMemcpyHostToDevice, s) == hipSuccess;
     }
-    *(int *)(ht + o_next) = 0;
-    ok = ok && hipMemcpyAsync(dt, ht, g->tbl_bytes, hipMemcpyHostToDevice, s) == hipSuccess;
-    if (ok) {
-        k_batch<<<n, BATCH_BLOCK, 0, s>>>((BatchItem *)dt, (const int *)(dt + o_ord), n, (int *)(dt + o_next));
-        ok = hipGetLastError() == hipSuccess;
-    }
-    ok = ok && hipEventRecord(g->done, s) == hipSuccess;
+    ok = ok && hipEventRecord(ev, s) == hipSuccess;
     if (!ok) {
         error = BGPC_E_HIP;
         (void)hipStreamSynchronize(s);
     }
-    inflight.push_back(g);
-    running.insert(running.end(), grp.begin(), grp.end());
+    q->done = (volatile long long *)(hb + q->o_done);
+    *q->done = 0;
+    uploading.push_back({q, ev});
     return true;
 }
 
-// a batched request whose done word is set: colors to the caller, memory back
+// writes the request's descriptor into the next ring slot and raises tail;
+// false while that slot still belongs to a request that is not done
+bool bgpc_session::publish(Req *q)
+{
+    const int slot = tail % cap;
+    if (slot_owner[slot]) return false;
+    const bgpc_request &r = q->r;
+    char *db = dpool + q->off, *hb_dev = hpool_dev + q->off;
+    BatchItem b = {};
+    b.n_a = r.n_a;
+    b.n_b = r.n_b;
+    b.a_off = (const int *)(db + q->o_aoff);
+    b.a_idx = (const int *)(db + q->o_aidx);
+    b.b_off = (const int *)(db + q->o_boff);
+    b.b_idx = (const int *)(db + q->o_bidx);
+    b.colors = (int *)(db + q->o_col);
+    b.scratch = db + q->o_scr;
+    b.max_rounds = max_rounds > 0 ? max_rounds : r.n_a + 65;
+    b.mode = q->mode;
+    b.cap = q->cap;
+    b.status = -1;
+    b.nnz = (int)r.nnz;
+    void *user_dev = nullptr;
+    if ((r.flags & BGPC_REQ_PINNED) && r.n_a && hipHostGetDevicePointer(&user_dev, r.colors_out, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        error = BGPC_E_HIP;
+    }
+    b.host_colors = (r.flags & BGPC_REQ_PINNED) ? (int *)user_dev : (int *)(hb_dev + q->o_col);
+    b.host_done = (long long *)(hb_dev + q->o_done);
+    std::memcpy((void *)&ring->items[slot], &b, sizeof(b));
+    std::atomic_thread_fence(std::memory_order_release);
+    __atomic_store_n(&ring->tail, tail + 1, __ATOMIC_RELEASE);
+    tail++;
+    slot_owner[slot] = q;
+    q->slot = slot;
+    running.push_back(q);
+    return true;
+}
+
+// a request whose done word is set: colors to the caller, memory back
 void bgpc_session::finish(Req *q)
 {
     const long long d = *q->done;
@@ -563,6 +563,7 @@ void bgpc_session::finish(Req *q)
     q->rounds = (int)(d >> 32);
     q->t_done = now_s();
     alloc->release(q->off, q->bytes);
+    if (q->slot >= 0) slot_owner[q->slot] = nullptr;
     slots_used--;
     {
         std::lock_guard<std::mutex> lk(mu);
@@ -577,7 +578,7 @@ void bgpc_session::loop()
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(mu);
-            if (submitted.empty() && pending.empty() && inflight.empty() && running.empty()) {
+            if (submitted.empty() && pending.empty() && uploading.empty() && running.empty()) {
                 if (stop) break;
                 cv_work.wait(lk, [&] { return stop || !submitted.empty(); });
                 if (stop && submitted.empty()) break;
@@ -594,7 +595,7 @@ void bgpc_session::loop()
             }
         }
         bool progress = false;
-        // requests whose graphs are done (any order within and across groups)
+        // requests whose graphs are done
         for (size_t i = 0; i < running.size();) {
             if (*running[i]->done != 0 || error) {
                 Req *q = running[i];
@@ -606,40 +607,49 @@ void bgpc_session::loop()
                 i++;
             }
         }
-        // groups whose launch finished: their tables
-        for (size_t i = 0; i < inflight.size();) {
-            hipError_t st = hipEventQuery(inflight[i]->done);
-            if (st == hipSuccess) {
-                Group *g = inflight[i];
-                inflight.erase(inflight.begin() + i);
-                alloc->release(g->tbl_off, g->tbl_bytes);
-                events.push_back(g->done);
-                delete g;
+        // uploaded requests go on the ring, in admission order
+        while (!uploading.empty()) {
+            hipError_t e = hipEventQuery(uploading.front().second);
+            if (e == hipErrorNotReady) break;
+            if (e != hipSuccess) error = BGPC_E_HIP;
+            if (!publish(uploading.front().first)) break;
+            events.push_back(uploading.front().second);
+            uploading.pop_front();
+            progress = true;
+        }
+        // the serving kernel runs while published work is not done
+        if (!running.empty()) {
+            bool alive = false;
+            if (klaunched) {
+                hipError_t e = hipEventQuery(kdone);
+                if (e == hipErrorNotReady) alive = true;
+                else if (e != hipSuccess) error = BGPC_E_HIP;
+            }
+            if (!alive) {
+                // about 20 ms of empty polls before a workgroup leaves
+                k_serve<<<std::max(1, cus * 2), BATCH_BLOCK, 0, kstream>>>(ring_dev, cap, head, 12000);
+                if (hipGetLastError() != hipSuccess || hipEventRecord(kdone, kstream) != hipSuccess)
+                    error = BGPC_E_HIP;
+                klaunched = true;
                 progress = true;
-            } else {
-                if (st != hipErrorNotReady) error = BGPC_E_HIP;
-                i++;
             }
         }
         // admit in arrival order while a slot and pool room are free
-        std::vector<Req *> grp;
-        while (!pending.empty() && slots_used + (int)grp.size() < max_slots && (int)grp.size() < max_group) {
+        int admitted = 0;
+        while (!pending.empty() && slots_used < max_slots && admitted < max_group) {
             Req *q = pending.front();
             if (!alloc->alloc(q->bytes, &q->off)) break;
             q->t_admit = now_s();
-            grp.push_back(q);
             pending.pop_front();
-        }
-        if (!grp.empty()) {
-            if (launch(grp)) {
-                slots_used += (int)grp.size();
-                progress = true;
-            } else {
-                for (auto it = grp.rbegin(); it != grp.rend(); ++it) {
-                    alloc->release((*it)->off, (*it)->bytes);
-                    pending.push_front(*it);
-                }
+            slots_used++;
+            admitted++;
+            if (!upload(q)) {
+                error = BGPC_E_HIP;
+                q->done = (volatile long long *)(hpool + q->off + q->o_done);
+                *q->done = 0;
+                running.push_back(q);   // retired through the error path
             }
+            progress = true;
         }
         if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
@@ -733,15 +743,36 @@ BGPC_API bgpc_session *bgpc_session_create(size_t mem_budget, int32_t max_slots,
         if (ok) S->streams.push_back(st);
     }
     ok = ok && hipStreamCreateWithFlags(&S->dev_stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&S->kstream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&S->kdone, hipEventDisableTiming) == hipSuccess;
+    // ring: a few times the slots, so that a slot is normally free again long
+    // before its index comes round
+    S->cap = std::max(64, 4 * max_slots);
+    const size_t ring_bytes = sizeof(ServeRing) + sizeof(BatchItem) * (size_t)S->cap;
+    ok = ok && hipHostMalloc((void **)&S->ring, ring_bytes, hipHostMallocMapped | hipHostMallocCoherent) ==
+                   hipSuccess;
+    ok = ok && hipHostGetDevicePointer((void **)&S->ring_dev, S->ring, 0) == hipSuccess;
+    ok = ok && hipMalloc((void **)&S->head, 256) == hipSuccess;
+    if (ok) {
+        std::memset(S->ring, 0, ring_bytes);
+        const int zero = 0;
+        ok = hipMemcpy(S->head, &zero, sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+    }
     if (!ok) {
         (void)hipGetLastError();
         for (auto st : S->streams) (void)hipStreamDestroy(st);
         if (S->dev_stream) (void)hipStreamDestroy(S->dev_stream);
+        if (S->kstream) (void)hipStreamDestroy(S->kstream);
+        if (S->kdone) (void)hipEventDestroy(S->kdone);
+        if (S->ring) (void)hipHostFree(S->ring);
+        if (S->head) (void)hipFree(S->head);
         if (S->dpool) (void)hipFree(S->dpool);
         if (S->hpool) (void)hipHostFree(S->hpool);
         delete S;
         return nullptr;
     }
+    S->slot_owner.assign(S->cap, nullptr);
+    S->cus = device_cus();
     S->alloc = new RangeAlloc(S->budget);
     S->worker = std::thread([S] { S->loop(); });
     S->dev_worker = std::thread([S] { S->dev_loop(); });
@@ -805,6 +836,9 @@ BGPC_API void bgpc_session_destroy(bgpc_session *S)
     }
     S->cv_work.notify_all();
     if (S->worker.joinable()) S->worker.join();
+    // every request is done: the serving kernel's workgroups leave
+    __atomic_store_n(&S->ring->stop, 1, __ATOMIC_RELEASE);
+    (void)hipStreamSynchronize(S->kstream);
     {
         std::lock_guard<std::mutex> lk(S->mu);
         S->dev_stop = true;
@@ -817,7 +851,11 @@ BGPC_API void bgpc_session_destroy(bgpc_session *S)
     }
     (void)hipStreamSynchronize(S->dev_stream);
     (void)hipStreamDestroy(S->dev_stream);
+    (void)hipStreamDestroy(S->kstream);
+    (void)hipEventDestroy(S->kdone);
     for (auto e : S->events) (void)hipEventDestroy(e);
+    (void)hipHostFree(S->ring);
+    (void)hipFree(S->head);
     for (Req *q : S->completed) delete q;
     for (Req *q : S->pending) delete q;
     for (Req *q : S->submitted) delete q;

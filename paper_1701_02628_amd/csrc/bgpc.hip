@@ -260,7 +260,8 @@ int run(const RunArgs &a)
     uint64_t *hw = nullptr;
     int PH = 0;
     long mc_ub = -1;   // upper bound of every color present before the next round
-    const bool planes_ok = !(o.flags & BGPC_INCREMENTAL);
+    // (decided from the graph's shape below)
+    bool planes_ok = !(o.flags & BGPC_INCREMENTAL);
     long max_PH = 0;
     {
         size_t fr = 0, tot = 0;
@@ -269,8 +270,11 @@ int run(const RunArgs &a)
         max_PH = std::min<long>(max_PH, (long)n_a / 64 + 2);
     }
     // standing proposals in vertex-based rounds (not with the opt-in
-    // incremental rounds); their state is reset after every net-based round
-    const bool sp_on = !(o.flags & BGPC_INCREMENTAL);
+    // incremental rounds); their state is reset after every net-based round.
+    // They pay where a coloring front sweeps many nets round after round (on
+    // 2^21 stencil nets: 12% per call); on graphs of 10^4-10^5 nets the
+    // bookkeeping costs about as much as it saves, so smaller graphs go without
+    const bool sp_on = !(o.flags & BGPC_INCREMENTAL) && n_b >= (1 << 20);
     bool sp_reset = true, sp_used = false;
     const SPState sp_none = {nullptr, nullptr, nullptr};
     const SPState sp_state = {sp_bits, sp_cnt, sp_dirty};
@@ -371,6 +375,10 @@ int run(const RunArgs &a)
         // bitmap capacity of the wide vertex paths, in bits
         long need_bits = std::max<long>(two_hop + 2, max_net + 1) + chunk + 66;
         const int lds_bits = (int)std::min<long>(((need_bits + 31) / 32) * 32, (long)lds_budget * 8);
+        // per-net color words past 63 where the distance-2 walk is costly
+        // (nets of more than SMALL_NET members) or cannot hold every color
+        // (bound past the LDS bitmap); elsewhere the walk is cheaper
+        planes_ok = planes_ok && (n_big > 0 || need_bits > lds_bits);
         const int wide_bytes = lds_bits / 8;
         // net-based rounds: bitmap + suffix counts of the largest net
         const int ncolor_words = std::min(lds_budget / 4, 2 * ((max_net + 31) / 32) + 2);
