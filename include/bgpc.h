@@ -232,16 +232,20 @@ BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items, const bgp
  * Serving: a session colors requests as they arrive (continuous batching).
  * A worker thread admits waiting requests in arrival order while one of
  * `max_slots` slots is free and its device pool of `mem_budget` bytes has room
- * for the request (CSR arrays, colors, scratch); each admission pass launches
- * its group (at most `max_group` requests, one workgroup each, the rounds and
- * per-graph modes of bgpc_color_batch) on the next of four streams, so
- * groups admitted while others run overlap on the device.  A request
- * completes as soon as its own graph is done: its workgroup copies the colors
- * to host memory and then sets a done word that the worker polls.  Requests
- * that bgpc_color_batch would give to the whole device are colored by
- * bgpc_color on a second thread and stream, one at a time; their arrays are
- * allocated outside the pool.  A request's colors equal what bgpc_color
- * returns for its graph alone.
+ * for the request (CSR arrays, colors, scratch; at most `max_group` admissions
+ * per pass), copies the request's arrays in, and once they have arrived
+ * publishes its descriptor on a ring that a persistent kernel drains: each
+ * workgroup claims the next descriptor and runs all of its graph's rounds
+ * (the rounds and per-graph modes of bgpc_color_batch), so requests admitted
+ * while others run overlap on the device.  A request completes as soon as
+ * its own graph is done: its workgroup copies the colors to host memory and
+ * then sets a done word that the worker polls.  The kernel's workgroups leave
+ * after about 20 ms without work (the worker launches it again when work is
+ * published) and when the session is destroyed.  Requests that
+ * bgpc_color_batch would give to the whole device are colored by bgpc_color
+ * on a second thread and stream, one at a time; their arrays are allocated
+ * outside the pool.  A request's colors equal what bgpc_color returns for
+ * its graph alone.  Calls on one session may come from any thread.
  *
  * bgpc_request: host arrays (csr_A offsets / indices = a_off / a_idx, csr_B =
  * b_off / b_idx), read at submit (shape and checks, as in bgpc_color_batch)
