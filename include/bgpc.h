@@ -205,8 +205,8 @@ BGPC_API int color_stats(const int32_t *colors, int64_t n, void *stream, bgpc_st
  * overlapping more than the vertex pairs), or per-vertex forbidden-color
  * bitmaps.  Graphs that one workgroup would color far slower than the whole
  * device (more than 10^6 memberships, or colors past 127 on more than 16384
- * vertices with more than 5 * 10^4 memberships) are colored by bgpc_color on a
- * second stream while the launch runs.
+ * vertices with more than 5 * 10^4 memberships) are colored by bgpc_color on
+ * three more streams (one host thread each) while the launch runs.
  *   items    host array; csr_A / csr_B / colors_out device pointers as in
  *            bgpc_color; status and rounds are written per item
  *   opts     NULL or: stream, max_rounds (per graph), flags 0 or BGPC_STRICT
@@ -243,8 +243,8 @@ BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items, const bgp
  * after about 20 ms without work (the worker launches it again when work is
  * published) and when the session is destroyed.  Requests that
  * bgpc_color_batch would give to the whole device are colored by bgpc_color
- * on a second thread and stream, one at a time; their arrays are allocated
- * outside the pool.  A request's colors equal what bgpc_color returns for
+ * on three more threads, each with a stream of its own; their arrays are
+ * allocated outside the pool.  A request's colors equal what bgpc_color returns for
  * its graph alone.  Calls on one session may come from any thread.
  *
  * bgpc_request: host arrays (csr_A offsets / indices = a_off / a_idx, csr_B =

@@ -6,12 +6,18 @@
 #include <cstring>
 #include <mutex>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "batch.h"
 #include "bgpc.h"
 
 using namespace bgpc;
+
+namespace bgpc {
+// frees the calling thread's round-driver state (bgpc.hip)
+void release_thread_state();
+}  // namespace bgpc
 
 namespace {
 
@@ -23,20 +29,22 @@ int device_cus()
     return v;
 }
 
-// A second stream per device for the graphs that take the whole-device path
-// while the persistent launch runs (default priority, created once).
-hipStream_t side_stream()
+// Streams per device for the graphs that take the whole-device path while
+// the persistent launch runs (default priority, created once): each is driven
+// by a host thread of its own, since a bgpc_color call waits for its rounds.
+constexpr int SIDE_STREAMS = 3;
+hipStream_t side_stream(int i)
 {
     static std::mutex mu;
-    static hipStream_t streams[64] = {};
+    static hipStream_t streams[64][SIDE_STREAMS] = {};
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || i < 0 || i >= SIDE_STREAMS) return nullptr;
     std::lock_guard<std::mutex> lk(mu);
-    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) {
+    if (!streams[dev][i] && hipStreamCreateWithFlags(&streams[dev][i], hipStreamNonBlocking) != hipSuccess) {
         (void)hipGetLastError();
-        streams[dev] = nullptr;
+        streams[dev][i] = nullptr;
     }
-    return streams[dev];
+    return streams[dev][i];
 }
 
 // Graphs that one workgroup would color far slower than the whole device:
@@ -228,15 +236,19 @@ extern "C" BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items
     if (rc == BGPC_OK && !runs.empty() &&
         hipMemcpyAsync(d_next, zeros.data(), 256 * runs.size(), hipMemcpyHostToDevice, s) != hipSuccess)
         rc = BGPC_E_HIP;
-    // whole-device graphs on the side stream, after the caller's prior work on s
-    hipStream_t side = nullptr;
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    if (rc == BGPC_OK && !big.empty()) {
-        side = side_stream();
-        if (!side || hipEventCreateWithFlags(&ev_in, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&ev_out, hipEventDisableTiming) != hipSuccess ||
-            hipEventRecord(ev_in, s) != hipSuccess || hipStreamWaitEvent(side, ev_in, 0) != hipSuccess)
+    // whole-device graphs on the side streams, after the caller's prior work on s
+    const int nside = (int)std::min<size_t>(SIDE_STREAMS, big.size());
+    hipStream_t side[SIDE_STREAMS] = {};
+    hipEvent_t ev_in = nullptr, ev_out[SIDE_STREAMS] = {};
+    if (rc == BGPC_OK && nside > 0) {
+        if (hipEventCreateWithFlags(&ev_in, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev_in, s) != hipSuccess)
             rc = BGPC_E_HIP;
+        for (int t = 0; t < nside && rc == BGPC_OK; t++) {
+            side[t] = side_stream(t);
+            if (!side[t] || hipStreamWaitEvent(side[t], ev_in, 0) != hipSuccess ||
+                hipEventCreateWithFlags(&ev_out[t], hipEventDisableTiming) != hipSuccess)
+                rc = BGPC_E_HIP;
+        }
     }
     for (size_t r = 0; r < runs.size() && rc == BGPC_OK; r++) {
         const int n = runs[r].second - runs[r].first;
@@ -245,21 +257,39 @@ extern "C" BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items
         if (hipGetLastError() != hipSuccess) rc = BGPC_E_HIP;
     }
     std::vector<std::pair<int, int>> big_res(big.size(), {BGPC_OK, 0});
-    for (size_t j = 0; j < big.size() && rc == BGPC_OK; j++) {
-        const bgpc_batch_item &it = items[big[j]];
-        bgpc_opts po = o;
-        po.stream = side;
-        po.log = nullptr;
-        po.prof = nullptr;
-        int32_t r = 0;
-        po.rounds_out = &r;
-        int st = bgpc_color(&it.csr_A, &it.csr_B, nullptr, &po, it.colors_out);
-        if (st != BGPC_OK && st != BGPC_E_NOT_CONVERGED) rc = st;
-        big_res[j] = {st, r};
-    }
-    if (ev_out) {
-        if (hipEventRecord(ev_out, side) != hipSuccess || hipStreamWaitEvent(s, ev_out, 0) != hipSuccess)
-            rc = BGPC_E_HIP;
+    if (rc == BGPC_OK && nside > 0) {
+        // largest first (the order of `big`), taken by the threads as they free up
+        std::atomic<size_t> next_big(0);
+        std::atomic<int> side_rc(BGPC_OK);
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        auto worker = [&](int t) {
+            (void)hipSetDevice(dev);
+            for (size_t j = next_big++; j < big.size(); j = next_big++) {
+                const bgpc_batch_item &it = items[big[j]];
+                bgpc_opts po = o;
+                po.stream = side[t];
+                po.log = nullptr;
+                po.prof = nullptr;
+                int32_t rr = 0;
+                po.rounds_out = &rr;
+                int st = bgpc_color(&it.csr_A, &it.csr_B, nullptr, &po, it.colors_out);
+                if (st != BGPC_OK && st != BGPC_E_NOT_CONVERGED) side_rc = st;
+                big_res[j] = {st, rr};
+            }
+        };
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nside; t++)
+            pool.emplace_back([&worker, t] {
+                worker(t);
+                release_thread_state();
+            });
+        worker(0);
+        for (auto &th : pool) th.join();
+        if (side_rc != BGPC_OK) rc = side_rc;
+        for (int t = 0; t < nside; t++)
+            if (hipEventRecord(ev_out[t], side[t]) != hipSuccess || hipStreamWaitEvent(s, ev_out[t], 0) != hipSuccess)
+                rc = BGPC_E_HIP;
     }
     if (rc == BGPC_OK &&
         (hipMemcpyAsync(h.data(), d_items, sizeof(BatchItem) * n_items, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -269,9 +299,11 @@ extern "C" BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items
         h[big[j]].status = big_res[j].first;
         h[big[j]].rounds = big_res[j].second;
     }
-    if (side) (void)hipStreamSynchronize(side);
+    for (int t = 0; t < nside; t++) {
+        if (side[t]) (void)hipStreamSynchronize(side[t]);
+        if (ev_out[t]) (void)hipEventDestroy(ev_out[t]);
+    }
     if (ev_in) (void)hipEventDestroy(ev_in);
-    if (ev_out) (void)hipEventDestroy(ev_out);
     if (scr) (void)hipFreeAsync(scr, s);
     (void)hipFreeAsync(meta, s);
     (void)hipStreamSynchronize(s);
@@ -298,9 +330,9 @@ extern "C" BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items
 // graph).  Requests that arrive while other groups run join the next group,
 // whose work overlaps the running ones on the device, and each request
 // completes as soon as its own graph is done.  Graphs that one workgroup
-// would color far slower than the whole device go to a second thread that
-// runs bgpc_color for them one at a time on a stream of its own (their arrays
-// are allocated outside the pool).  A request's colors depend on its graph
+// would color far slower than the whole device go to three more threads that
+// run bgpc_color for them, each on a stream of its own (their arrays are
+// allocated outside the pool).  A request's colors depend on its graph
 // only.
 
 #include <chrono>
@@ -447,7 +479,7 @@ struct bgpc_session {
     int *head = nullptr;                // device: descriptors claimed
     int tail = 0;                       // descriptors published
     int cus = 256;
-    hipStream_t dev_stream = nullptr;
+    std::vector<hipStream_t> dev_streams;   // one per whole-device thread
     int rr = 0;
     int slots_used = 0;
     std::mutex mu;
@@ -458,7 +490,8 @@ struct bgpc_session {
     std::deque<Req *> pending;      // worker only: waiting for admission
     std::deque<std::pair<Req *, hipEvent_t>> uploading;   // worker only: arrays on their way
     std::vector<Req *> running;     // worker only: published, done word not yet seen
-    std::thread worker, dev_worker;
+    std::thread worker;
+    std::vector<std::thread> dev_workers;
     bool stop = false;              // guarded by mu
     bool dev_stop = false;          // guarded by mu: set once the worker has handed over every request
     int error = 0;
@@ -467,8 +500,8 @@ struct bgpc_session {
     bool publish(Req *q);
     void finish(Req *q);
     void loop();
-    void dev_loop();
-    void dev_run(Req *q);
+    void dev_loop(int t);
+    void dev_run(Req *q, hipStream_t s);
 };
 
 // copies a request's arrays into its pool block (staged through pinned
@@ -656,10 +689,9 @@ void bgpc_session::loop()
 }
 
 // one whole-device request: arrays in stream-ordered allocations, bgpc_color
-void bgpc_session::dev_run(Req *q)
+void bgpc_session::dev_run(Req *q, hipStream_t s)
 {
     const bgpc_request &r = q->r;
-    hipStream_t s = dev_stream;
     const size_t b_aoff = 4 * ((size_t)r.n_a + 1), b_boff = 4 * ((size_t)r.n_b + 1), b_idx = 4 * (size_t)r.nnz + 4;
     const size_t b_col = 4 * ((size_t)r.n_a + 1);
     const size_t o1 = al256(b_aoff), o2 = o1 + al256(b_idx), o3 = o2 + al256(b_boff), o4 = o3 + al256(b_idx);
@@ -700,7 +732,7 @@ void bgpc_session::dev_run(Req *q)
     q->t_done = now_s();
 }
 
-void bgpc_session::dev_loop()
+void bgpc_session::dev_loop(int t)
 {
     (void)hipSetDevice(device);
     for (;;) {
@@ -708,12 +740,16 @@ void bgpc_session::dev_loop()
         {
             std::unique_lock<std::mutex> lk(mu);
             cv_dev.wait(lk, [&] { return dev_stop || !dev_queue.empty(); });
-            if (dev_queue.empty()) break;   // dev_stop and nothing left
+            if (dev_queue.empty()) {   // dev_stop and nothing left
+                lk.unlock();
+                release_thread_state();
+                break;
+            }
             q = dev_queue.front();
             dev_queue.pop_front();
         }
         q->t_admit = now_s();
-        dev_run(q);
+        dev_run(q, dev_streams[t]);
         {
             std::lock_guard<std::mutex> lk(mu);
             completed.push_back(q);
@@ -742,7 +778,11 @@ BGPC_API bgpc_session *bgpc_session_create(size_t mem_budget, int32_t max_slots,
         ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
         if (ok) S->streams.push_back(st);
     }
-    ok = ok && hipStreamCreateWithFlags(&S->dev_stream, hipStreamNonBlocking) == hipSuccess;
+    for (int i = 0; i < SIDE_STREAMS && ok; i++) {
+        hipStream_t st;
+        ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+        if (ok) S->dev_streams.push_back(st);
+    }
     ok = ok && hipStreamCreateWithFlags(&S->kstream, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&S->kdone, hipEventDisableTiming) == hipSuccess;
     // ring: a few times the slots, so that a slot is normally free again long
@@ -761,7 +801,7 @@ BGPC_API bgpc_session *bgpc_session_create(size_t mem_budget, int32_t max_slots,
     if (!ok) {
         (void)hipGetLastError();
         for (auto st : S->streams) (void)hipStreamDestroy(st);
-        if (S->dev_stream) (void)hipStreamDestroy(S->dev_stream);
+        for (auto st : S->dev_streams) (void)hipStreamDestroy(st);
         if (S->kstream) (void)hipStreamDestroy(S->kstream);
         if (S->kdone) (void)hipEventDestroy(S->kdone);
         if (S->ring) (void)hipHostFree(S->ring);
@@ -775,7 +815,7 @@ BGPC_API bgpc_session *bgpc_session_create(size_t mem_budget, int32_t max_slots,
     S->cus = device_cus();
     S->alloc = new RangeAlloc(S->budget);
     S->worker = std::thread([S] { S->loop(); });
-    S->dev_worker = std::thread([S] { S->dev_loop(); });
+    for (int t = 0; t < (int)S->dev_streams.size(); t++) S->dev_workers.emplace_back([S, t] { S->dev_loop(t); });
     return S;
 }
 
@@ -844,13 +884,16 @@ BGPC_API void bgpc_session_destroy(bgpc_session *S)
         S->dev_stop = true;
     }
     S->cv_dev.notify_all();
-    if (S->dev_worker.joinable()) S->dev_worker.join();
+    for (auto &th : S->dev_workers)
+        if (th.joinable()) th.join();
     for (auto st : S->streams) {
         (void)hipStreamSynchronize(st);
         (void)hipStreamDestroy(st);
     }
-    (void)hipStreamSynchronize(S->dev_stream);
-    (void)hipStreamDestroy(S->dev_stream);
+    for (auto st : S->dev_streams) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
     (void)hipStreamDestroy(S->kstream);
     (void)hipEventDestroy(S->kdone);
     for (auto e : S->events) (void)hipEventDestroy(e);

@@ -160,6 +160,13 @@ struct EventPool {
     }
 };
 
+// per-thread state of the round driver (pinned progress mirror, event pool);
+// created on a thread's first call and kept: freeing it at thread exit could
+// run after the HIP runtime has shut down.  Worker threads that end while the
+// runtime is up give it back with release_thread_state().
+thread_local HostProgress *t_prog = nullptr;
+thread_local EventPool *t_evpool = nullptr;
+
 struct RunArgs {
     Graph g;
     long nnz;
@@ -296,9 +303,11 @@ int run(const RunArgs &a)
     };
     // pinned counters live for the thread's lifetime (never freed: freeing at
     // thread exit could run after the HIP runtime has shut down)
-    static thread_local HostProgress *prog_p = new HostProgress();
+    if (!t_prog) t_prog = new HostProgress();
+    HostProgress *prog_p = t_prog;
     HostProgress &prog = *prog_p;
-    static thread_local EventPool *evpool_p = new EventPool();
+    if (!t_evpool) t_evpool = new EventPool();
+    EventPool *evpool_p = t_evpool;
     EventPool &evpool = *evpool_p;
     evpool.used = 0;
     const int prof_kernel = o.prof ? o.prof->kernel : -1;
@@ -802,6 +811,24 @@ bool opts_ok(const bgpc_opts &o)
 }
 
 }  // namespace
+
+namespace bgpc {
+
+void release_thread_state()
+{
+    if (t_prog) {
+        if (t_prog->h) (void)hipHostFree((void *)t_prog->h);
+        delete t_prog;
+        t_prog = nullptr;
+    }
+    if (t_evpool) {
+        for (hipEvent_t e : t_evpool->ev) (void)hipEventDestroy(e);
+        delete t_evpool;
+        t_evpool = nullptr;
+    }
+}
+
+}  // namespace bgpc
 
 extern "C" {
 
