@@ -157,8 +157,14 @@ BGPC_API void bgpc_opts_default(bgpc_opts *opts);
  *   csr_B    nets -> vertices: n_rows = |V_B|, n_cols = |V_A| (vtxs(v)),
  *            the transpose of csr_A
  *   order    NULL for the natural order, else a device int32[|V_A|]
- *            permutation: order[k] is the vertex of rank k
- *   colors_out  device int32[|V_A|]; with BGPC_RESUME it is read first
+ *            permutation: order[k] is the vertex of rank k (Section II:
+ *            the order in which vertices are visited).  The library copies
+ *            the graph relabelled to ranks into its own workspace (about
+ *            4 |V_A| + 3 nnz int32 more) and maps the colors back; the
+ *            caller's arrays are not modified.  BGPC_E_INVALID when it is
+ *            not a permutation of [0, |V_A|)
+ *   colors_out  device int32[|V_A|], indexed by vertex id; with
+ *            BGPC_RESUME it is read first
  * Limits: |V_A|, |V_B| < 2^30; nnz < 2^31; when net-based rounds run, no
  * net above 220,000 vertices; colors below 440,000 (BGPC_E_UNSUPPORTED).
  */
@@ -170,6 +176,7 @@ BGPC_API int bgpc_color(const bgpc_csr *csr_A, const bgpc_csr *csr_B, const int3
  * adj is its CSR (n_rows = n_cols = n).  Nets are the closed neighbourhoods;
  * in net-based rounds the center of N[v] is queued before nbor(v)
  * (Algorithm 9) and colors start at |nbor(v)|.
+ * `order` as for bgpc_color (a permutation of the n vertices).
  */
 BGPC_API int d2gc_color(const bgpc_csr *adj, const int32_t *order, const bgpc_opts *opts,
                         int32_t *colors_out);

@@ -7,6 +7,8 @@
 // keeps at most LOOKAHEAD rounds queued beyond what it has seen completed and
 // stops queueing as soon as it sees an empty worklist.
 #include <hip/hip_runtime.h>
+#include <rocprim/device/device_scan.hpp>
+#include <rocprim/device/device_segmented_radix_sort.hpp>
 
 #include <algorithm>
 #include <atomic>
@@ -812,6 +814,158 @@ bool opts_ok(const bgpc_opts &o)
 
 }  // namespace
 
+namespace {
+
+// ---- caller orders (ranks = positions in `order`): the graph is relabelled
+// to ranks on the device, colored in natural order, and the colors mapped back
+
+// inv[order[k]] = k; err set when order is not a permutation of [0, n)
+__global__ void k_order_inverse(const int *order, int n, int *mark, int *inv, int *err)
+{
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        unsigned v = (unsigned)order[k];
+        if (v >= (unsigned)n || atomicAdd(&mark[v], 1) != 0) {
+            atomicOr(err, 1);
+            continue;
+        }
+        inv[v] = k;
+    }
+}
+
+// size of rank k's row (the row of vertex order[k])
+__global__ void k_rank_degree(const int *off, const int *order, int n, int *deg)
+{
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+        deg[k] = off[order[k] + 1] - off[order[k]];
+}
+
+// rows copied in rank order, one wave per row; entries mapped through map (if given)
+__global__ void k_rank_rows(const int *off, const int *idx, const int *order, int n, const int *noff,
+                            const int *map, int *nidx)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, nwv = gridDim.x * blockDim.x / WAVE;
+    for (int k = wid; k < n; k += nwv) {
+        const int src = off[order[k]], len = off[order[k] + 1] - src, dst = noff[k];
+        for (int j = lane; j < len; j += WAVE) {
+            int x = idx[src + j];
+            nidx[dst + j] = map ? map[x] : x;
+        }
+    }
+}
+
+__global__ void k_map_ids(const int *idx, long n, const int *map, int *out)
+{
+    for (long j = blockIdx.x * (long)blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x)
+        out[j] = map[idx[j]];
+}
+
+// out[i] = in[perm[i]]
+__global__ void k_gather_i32(const int *in, const int *perm, int n, int *out)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = in[perm[i]];
+}
+
+}  // namespace
+
+namespace bgpc {
+
+// Relabels the graph to ranks, runs the rounds there and maps the colors back.
+// BGPC: vertex rows are reordered (net ids unchanged) and every net's members
+// become ranks, sorted again; distance-2: rows reordered, entries mapped,
+// each row sorted again.  The caller's arrays are not modified.
+int run_ordered(const RunArgs &a, const int32_t *order)
+{
+    if (a.g.n_a == 0) return a.d2 ? run<true>(a) : run<false>(a);
+    const Graph g = a.g;
+    hipStream_t s = a.s;
+    const int n_a = g.n_a, n_b = g.n_b;
+    const long nnz = a.nnz;
+    const DevInfo di = dev_info();
+    const int nthr = 256;
+    const int ga = grid_for(n_a, nthr, di.cus * 8);
+    size_t sort_bytes = 0, scan_bytes = 0;
+    const int nseg = a.d2 ? n_a : n_b;
+    if (rocprim::segmented_radix_sort_keys(nullptr, sort_bytes, (const int *)nullptr, (int *)nullptr, (unsigned)nnz,
+                                           (unsigned)nseg, (const int *)nullptr, (const int *)nullptr, 0u, 32u,
+                                           s) != hipSuccess ||
+        rocprim::inclusive_scan(nullptr, scan_bytes, (const int *)nullptr, (int *)nullptr, (size_t)n_a,
+                                rocprim::plus<int>(), s) != hipSuccess) {
+        (void)hipGetLastError();
+        return BGPC_E_HIP;
+    }
+    const size_t bytes = aligned(n_a + 1, 4) * 4 + aligned(nnz + 1, 4) * 3 + aligned(4, 4) + aligned(sort_bytes, 1) +
+                         aligned(scan_bytes, 1);
+    Arena ar;
+    int rc = ar.reserve(bytes, s);
+    if (rc != BGPC_OK) return rc;
+    int *inv = ar.take<int>(n_a + 1);
+    int *mark = ar.take<int>(n_a + 1);
+    int *noff = ar.take<int>(n_a + 1);
+    int *ncol = ar.take<int>(n_a + 1);
+    int *nidx = ar.take<int>(nnz + 1);
+    int *tmp = ar.take<int>(nnz + 1);
+    int *nidx2 = ar.take<int>(nnz + 1);
+    int *err = ar.take<int>(4);
+    void *sort_tmp = ar.take<char>(sort_bytes);
+    void *scan_tmp = ar.take<char>(scan_bytes);
+    int h_err = 0;
+    k_fill_i32<<<ga, nthr, 0, s>>>(mark, 0, n_a + 1);
+    k_fill_i32<<<1, 64, 0, s>>>(err, 0, 4);
+    k_order_inverse<<<ga, nthr, 0, s>>>(order, n_a, mark, inv, err);
+    if (hipMemcpyAsync(&h_err, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        ar.release();
+        return BGPC_E_HIP;
+    }
+    if (h_err) {
+        ar.release();
+        (void)hipStreamSynchronize(s);
+        return BGPC_E_INVALID;
+    }
+    // rank-ordered vertex rows
+    int *deg = mark;   // free again after the permutation check
+    k_rank_degree<<<ga, nthr, 0, s>>>(g.a_off, order, n_a, deg);
+    k_fill_i32<<<1, 64, 0, s>>>(noff, 0, 1);
+    bool ok = rocprim::inclusive_scan(scan_tmp, scan_bytes, (const int *)deg, noff + 1, (size_t)n_a,
+                                      rocprim::plus<int>(), s) == hipSuccess;
+    const int gw = grid_for((long)n_a * WAVE, nthr, di.cus * 16);
+    Graph ng;
+    if (!a.d2) {
+        k_rank_rows<<<gw, nthr, 0, s>>>(g.a_off, g.a_idx, order, n_a, noff, nullptr, nidx);
+        k_map_ids<<<grid_for(nnz, nthr, di.cus * 16), nthr, 0, s>>>(g.b_idx, nnz, inv, tmp);
+        ok = ok && (nnz == 0 ||
+                    rocprim::segmented_radix_sort_keys(sort_tmp, sort_bytes, (const int *)tmp, nidx2, (unsigned)nnz,
+                                                      (unsigned)n_b, g.b_off, g.b_off + 1, 0u, 32u, s) == hipSuccess);
+        ng = Graph{n_a, n_b, noff, nidx, g.b_off, nidx2};
+    } else {
+        k_rank_rows<<<gw, nthr, 0, s>>>(g.a_off, g.a_idx, order, n_a, noff, inv, tmp);
+        ok = ok && (nnz == 0 ||
+                    rocprim::segmented_radix_sort_keys(sort_tmp, sort_bytes, (const int *)tmp, nidx, (unsigned)nnz,
+                                                      (unsigned)n_a, (const int *)noff, (const int *)noff + 1, 0u, 32u,
+                                                      s) == hipSuccess);
+        ng = Graph{n_a, n_a, noff, nidx, noff, nidx};
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        ar.release();
+        (void)hipStreamSynchronize(s);
+        return BGPC_E_HIP;
+    }
+    if (a.o->flags & BGPC_RESUME) k_gather_i32<<<ga, nthr, 0, s>>>(a.st, order, n_a, ncol);
+    RunArgs ra = a;
+    ra.g = ng;
+    ra.st = ncol;
+    rc = a.d2 ? run<true>(ra) : run<false>(ra);
+    if (rc == BGPC_OK || rc == BGPC_E_NOT_CONVERGED) k_gather_i32<<<ga, nthr, 0, s>>>(ncol, inv, n_a, a.st);
+    if (hipGetLastError() != hipSuccess && (rc == BGPC_OK || rc == BGPC_E_NOT_CONVERGED)) rc = BGPC_E_HIP;
+    ar.release();
+    (void)hipStreamSynchronize(s);
+    return rc;
+}
+
+}  // namespace bgpc
+
 namespace bgpc {
 
 void release_thread_state()
@@ -849,7 +1003,6 @@ BGPC_API int bgpc_color(const bgpc_csr *csr_A, const bgpc_csr *csr_B, const int3
     if (!csr_ok(csr_A) || !csr_ok(csr_B) || !colors_out || !opts_ok(o)) return BGPC_E_INVALID;
     if (csr_A->n_rows != csr_B->n_cols || csr_A->n_cols != csr_B->n_rows || csr_A->nnz != csr_B->nnz)
         return BGPC_E_INVALID;
-    if (order) return BGPC_E_UNSUPPORTED;
     hipStream_t s = (hipStream_t)o.stream;
     if (o.flags & BGPC_STRICT) {
         int v = validate_bipartite(csr_A, csr_B, s);
@@ -862,7 +1015,7 @@ BGPC_API int bgpc_color(const bgpc_csr *csr_A, const bgpc_csr *csr_B, const int3
     a.o = &o;
     a.st = colors_out;
     a.s = s;
-    return run<false>(a);
+    return order ? run_ordered(a, order) : run<false>(a);
 }
 
 BGPC_API int d2gc_color(const bgpc_csr *adj, const int32_t *order, const bgpc_opts *opts, int32_t *colors_out)
@@ -871,7 +1024,6 @@ BGPC_API int d2gc_color(const bgpc_csr *adj, const int32_t *order, const bgpc_op
     if (opts) o = *opts;
     else bgpc_opts_default(&o);
     if (!csr_ok(adj) || !colors_out || !opts_ok(o) || adj->n_rows != adj->n_cols) return BGPC_E_INVALID;
-    if (order) return BGPC_E_UNSUPPORTED;
     hipStream_t s = (hipStream_t)o.stream;
     if (o.flags & BGPC_STRICT) {
         int v = validate_symmetric(adj, s);
@@ -884,7 +1036,7 @@ BGPC_API int d2gc_color(const bgpc_csr *adj, const int32_t *order, const bgpc_op
     a.o = &o;
     a.st = colors_out;
     a.s = s;
-    return run<true>(a);
+    return order ? run_ordered(a, order) : run<true>(a);
 }
 
 BGPC_API int color_stats(const int32_t *colors, int64_t n, void *stream, bgpc_stats *out)

@@ -26,7 +26,10 @@ def _gpu_bgpc(cuda, g, dev=None, **kw):
     init = kw.pop("init_colors", None)
     if init is not None:
         out.copy_(torch.from_numpy(np.asarray(init, np.int32)))
-    res = bgpc.bgpc_color(A, B, None, out, log_cap=kw.pop("log_cap", 4096), **kw)
+    order = kw.pop("order", None)
+    if order is not None:
+        order = torch.from_numpy(np.asarray(order, np.int32)).to(cuda)
+    res = bgpc.bgpc_color(A, B, order, out, log_cap=kw.pop("log_cap", 4096), **kw)
     torch.cuda.synchronize()
     return res, out.cpu().numpy()
 
@@ -38,7 +41,10 @@ def _gpu_d2(cuda, adj, dev=None, **kw):
     init = kw.pop("init_colors", None)
     if init is not None:
         out.copy_(torch.from_numpy(np.asarray(init, np.int32)))
-    res = bgpc.d2gc_color(D, None, out, log_cap=kw.pop("log_cap", 4096), **kw)
+    order = kw.pop("order", None)
+    if order is not None:
+        order = torch.from_numpy(np.asarray(order, np.int32)).to(cuda)
+    res = bgpc.d2gc_color(D, order, out, log_cap=kw.pop("log_cap", 4096), **kw)
     torch.cuda.synchronize()
     return res, out.cpu().numpy()
 
@@ -333,3 +339,63 @@ def test_dense_small_graphs(cuda, shape):
         assert res.status == part.status and np.array_equal(colors, part.colors)
         for key in ("w", "losers", "max_color"):
             assert np.array_equal(res.log[key], part.log[key]), key
+
+
+def _degree_order(off):
+    """Largest degree first, ties by id (a simple caller ordering)."""
+    deg = np.diff(np.asarray(off, dtype=np.int64))
+    return np.lexsort((np.arange(deg.shape[0]), -deg)).astype(np.int32)
+
+
+@pytest.mark.parametrize("mask,policy", [(0, 0), (0b1, 0), (0, 1), (0b11, 2)], ids=["vv", "n1", "b1", "n1n2_b2"])
+def test_caller_order(cuda, mask, policy):
+    """Ranks from a caller permutation (random, and degree-descending): the
+    library relabels on the device; the oracle relabels on the host."""
+    g = synth.random_uniform(3000, 2500, 2, 12, 21)
+    perms = [np.random.Generator(np.random.PCG64(5)).permutation(g.n_a).astype(np.int32), _degree_order(g.a_off)]
+    for perm in perms:
+        ref = oracle.bgpc(g, net_color_mask=mask, policy=policy, order=perm)
+        res, colors = _gpu_bgpc(cuda, g, net_color_mask=mask, policy=policy, order=perm)
+        _compare_full(res, colors, ref)
+
+
+def test_caller_order_big_nets_d2_resume(cuda):
+    """Nets above 64 members under an order (rows re-sorted on the device),
+    distance-2 under an order, and resuming from partial colors with one."""
+    g = synth.skewed(6000, 6000, seed=23, kmax=600, name="skewed_small_order")
+    perm = np.random.Generator(np.random.PCG64(6)).permutation(g.n_a).astype(np.int32)
+    ref = oracle.bgpc(g, net_color_mask=1, order=perm)
+    res, colors = _gpu_bgpc(cuda, g, net_color_mask=1, order=perm)
+    _compare_full(res, colors, ref)
+    adj = synth.rmat(10, 8, 0.57, 0.19, 0.19, seed=7)
+    dperm = _degree_order(adj.off)
+    for mask in (0, 0b1):
+        ref = oracle.d2gc(adj, net_color_mask=mask, order=dperm)
+        res, colors = _gpu_d2(cuda, adj, net_color_mask=mask, order=dperm)
+        _compare_full(res, colors, ref)
+    part = oracle.bgpc(g, net_color_mask=1, order=perm, max_rounds=2)
+    ref = oracle.bgpc(g, order=perm, init_colors=part.colors, start_round=2, net_color_mask=1)
+    res, colors = _gpu_bgpc(cuda, g, order=perm, init_colors=part.colors, start_round=2, net_color_mask=1,
+                            flags=bgpc.RESUME)
+    _compare_full(res, colors, ref)
+
+
+def test_caller_order_rejected_when_not_a_permutation(cuda):
+    g = synth.random_uniform(500, 400, 2, 6, 22)
+    bad = np.arange(g.n_a, dtype=np.int32)
+    bad[7] = bad[8]
+    res, _ = _gpu_bgpc(cuda, g, order=bad)
+    assert res.status == bgpc.E_INVALID
+    bad[7] = g.n_a + 3
+    res, _ = _gpu_bgpc(cuda, g, order=bad)
+    assert res.status == bgpc.E_INVALID
+
+
+def test_caller_order_edge_cases(cuda):
+    """Vertices in no net, and a single vertex, under a reversing order."""
+    for g in (synth.from_nets(6, []), synth.from_nets(5, [[1, 3], [], [0, 1, 2, 3, 4]]), synth.from_nets(1, [[0]])):
+        perm = np.arange(g.n_a, dtype=np.int32)[::-1].copy()
+        for mask in (0, 1):
+            ref = oracle.bgpc(g, net_color_mask=mask, order=perm)
+            res, colors = _gpu_bgpc(cuda, g, net_color_mask=mask, order=perm)
+            _compare_full(res, colors, ref)
