@@ -178,6 +178,22 @@ struct RunArgs {
     hipStream_t s;
 };
 
+// workgroups of k_vcolor_ff resident per compute unit (occupancy query, once)
+template <bool D2>
+int resident_per_cu()
+{
+    static std::atomic<int> cached{0};
+    int v = cached.load(std::memory_order_relaxed);
+    if (v == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_vcolor_ff<D2>, 64, 0) != hipSuccess || v <= 0) {
+            (void)hipGetLastError();
+            v = 32;
+        }
+        cached.store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
 template <bool D2>
 int run(const RunArgs &a)
 {
@@ -268,6 +284,12 @@ int run(const RunArgs &a)
     // possible color grows; at most half of the free device memory
     uint64_t *hw = nullptr;
     int PH = 0;
+    // balancing policies: rows of color words of the vertices of many nets,
+    // precomputed per round (F, H rows of PH + 1 words)
+    int *hv_id = nullptr, *hv_list = nullptr, *hv_counts = nullptr;
+    HeavySlice *hv_slices = nullptr;
+    uint64_t *hv_F = nullptr;
+    int hv_H = 0, hv_stride = 0;
     long mc_ub = -1;   // upper bound of every color present before the next round
     // (decided from the graph's shape below)
     bool planes_ok = !(o.flags & BGPC_INCREMENTAL);
@@ -404,6 +426,25 @@ int run(const RunArgs &a)
         }
 
         if (any_net_round) k_owner<D2><<<g_a, nthr, 0, s>>>(g, owner);
+        if (policy != BGPC_FIRST_FIT && planes_ok) {
+            // vertices of more than HEAVY_NETS nets (fewer than incidences / HEAVY_NETS)
+            const long inc = a.nnz + (D2 ? n_a : 0);
+            const long cap_h = std::min<long>(n_a, inc / (HEAVY_NETS + 1) + 1);
+            const long cap_s = inc / HEAVY_SLICE + cap_h + 1;
+            int h_counts[2] = {0, 0};
+            bool ok = hipMallocAsync((void **)&hv_id, sizeof(int) * ((size_t)n_a + 1), s) == hipSuccess &&
+                      hipMallocAsync((void **)&hv_list, sizeof(int) * (size_t)cap_h, s) == hipSuccess &&
+                      hipMallocAsync((void **)&hv_slices, sizeof(HeavySlice) * (size_t)cap_s, s) == hipSuccess &&
+                      hipMallocAsync((void **)&hv_counts, 64, s) == hipSuccess;
+            if (ok) {
+                k_fill_i32<<<1, 64, 0, s>>>(hv_counts, 0, 2);
+                k_heavy_mark<D2><<<g_a, nthr, 0, s>>>(g, hv_id, hv_list, hv_slices, hv_counts);
+                ok = hipMemcpyAsync(h_counts, hv_counts, sizeof(h_counts), hipMemcpyDeviceToHost, s) == hipSuccess &&
+                     hipStreamSynchronize(s) == hipSuccess;
+            }
+            if (!ok) (void)hipGetLastError();
+            hv_H = ok ? h_counts[0] : 0;   // none (or no room): every vertex walks its own nets
+        }
 
         // ---- initial state
         k_fill_u8<<<g_a, nthr, 0, s>>>(lose, 0, n_a + 1);
@@ -480,7 +521,10 @@ int run(const RunArgs &a)
             gsz = std::max<long>(8, (gsz + 7) / 8 * 8);
             return (int)gsz;
         };
-        const int g_w64a = grid64(n_a);
+        // first-fit: one resident pass of workgroups (the LDS staging buffer
+        // limits residency; a second partial pass of workgroups costs more than
+        // the longer per-wave loop)
+        const int g_w64a = std::min(grid64(n_a), std::max(8, di.cus * resident_per_cu<D2>() / 8 * 8));
         const int g_w64b = grid64(n_b);
         while (!done && issued < max_rounds) {
             // keep at most LOOKAHEAD rounds in flight beyond the last one seen
@@ -640,8 +684,32 @@ int run(const RunArgs &a)
                                                                                nullptr, nullptr, nullptr, nullptr,
                                                                                hw, PH, ffc, dty);
                 } else {
+                    const uint64_t *Fp = nullptr;
+                    if (hv_H > 0 && PH > 0) {
+                        if (hv_stride != PH + 1) {
+                            // rows follow the number of color words (rewritten every round)
+                            if (hv_F) (void)hipFreeAsync(hv_F, s);
+                            hv_F = nullptr;
+                            hv_stride = 0;
+                            if (hipMallocAsync((void **)&hv_F, (size_t)hv_H * (PH + 1) * 8, s) != hipSuccess) {
+                                (void)hipGetLastError();
+                                hv_F = nullptr;
+                                hv_H = 0;
+                            } else {
+                                hv_stride = PH + 1;
+                            }
+                        }
+                        if (hv_F) {
+                            const long nw = (long)hv_H * (PH + 1);
+                            k_fill_u64<<<grid_for(nw, nthr, di.cus * 8), nthr, 0, s>>>(hv_F, 0ull, nw);
+                            k_heavy_words<D2><<<di.cus * 8, 256, 0, s>>>(g, st, hv_list, hv_slices, hv_counts, mask0,
+                                                                        hw, PH, ctrl, hv_F);
+                            Fp = hv_F;
+                        }
+                    }
                     k_vcolor_chunked<D2><<<g_chunk, 64, wide_bytes, s>>>(g, Wc, ctrl, par, st, mask0, policy, chunk,
-                                                                          lds_bits, hw, PH, dty);
+                                                                          lds_bits, hw, PH, dty, Fp ? hv_id : nullptr,
+                                                                          Fp);
                 }
                 LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), spx)));
                 if (spr && prof_kernel == BGPC_PROF_CONFLICT && PCNT(r))
@@ -736,6 +804,8 @@ finish:
         }
     }
     if (hw) (void)hipFreeAsync(hw, s);
+    for (void *p : {(void *)hv_id, (void *)hv_list, (void *)hv_slices, (void *)hv_counts, (void *)hv_F})
+        if (p) (void)hipFreeAsync(p, s);
     ar.release();
     if (!ar.async) (void)hipGetLastError();
     hipStreamSynchronize(s);

@@ -734,34 +734,167 @@ __device__ int words_free_down(const Graph &g, int w, uint64_t m0, const uint64_
     return -1;
 }
 
-// One policy pick from the color words; -2 when they do not reach far enough.
+// The same two searches over a precomputed row of words Fw[0..PH] (a vertex
+// of many nets), 64 words per step with the whole wave.
+__device__ int row_free_up(const uint64_t *Fw, int PH, int from)
+{
+    const int lane = lane_id();
+    for (int pb = from >> 6; pb <= PH; pb += WAVE) {
+        const int p = pb + lane;
+        uint64_t fr = 0;
+        if (p <= PH) {
+            uint64_t m = Fw[p];
+            if (p == (from >> 6)) m |= (1ull << (from & 63)) - 1ull;
+            fr = ~m;
+        }
+        const uint64_t bal = __ballot(fr != 0);
+        if (bal) {
+            const int j = __builtin_ctzll(bal);
+            return 64 * (pb + j) + __builtin_ctzll(shfl64(fr, j));
+        }
+    }
+    return -2;
+}
+
+__device__ int row_free_down(const uint64_t *Fw, int PH, int from)
+{
+    if (from < 0) return -1;
+    if ((from >> 6) > PH) return -2;
+    const int lane = lane_id();
+    for (int pb = from >> 6; pb >= 0; pb -= WAVE) {
+        const int p = pb - lane;
+        uint64_t fr = 0;
+        if (p >= 0) {
+            fr = ~Fw[p];
+            if (p == (from >> 6)) fr &= bits_upto(from & 63);
+        }
+        const uint64_t bal = __ballot(fr != 0);
+        if (bal) {
+            const int j = __builtin_ctzll(bal);
+            return 64 * (pb - j) + 63 - __builtin_clzll(shfl64(fr, j));
+        }
+    }
+    return -1;
+}
+
+// One policy pick from the color words (Fw: w's precomputed row, or null);
+// -2 when they do not reach far enough.
 template <bool D2>
 __device__ int pick_words(const Graph &g, int w, uint64_t m0, const uint64_t *mask0, const uint64_t *hw, int PH,
-                          int policy, const PolicyState &s)
+                          int policy, const PolicyState &s, const uint64_t *Fw)
 {
+    auto up = [&](int from) {
+        return Fw ? row_free_up(Fw, PH, from) : words_free_up<D2>(g, w, m0, mask0, hw, PH, from);
+    };
+    auto down = [&](int from) {
+        return Fw ? row_free_down(Fw, PH, from) : words_free_down<D2>(g, w, m0, mask0, hw, PH, from);
+    };
     if (policy == 1 && (w & 1) == 0) {   // B1, even rank
-        int c = words_free_down<D2>(g, w, m0, mask0, hw, PH, s.col_max);
-        if (c == -1) c = words_free_up<D2>(g, w, m0, mask0, hw, PH, s.col_max + 1);
+        int c = down(s.col_max);
+        if (c == -1) c = up(s.col_max + 1);
         return c;
     }
     if (policy == 2) {
-        int c = words_free_up<D2>(g, w, m0, mask0, hw, PH, s.col_next);
+        int c = up(s.col_next);
         if (c == -2) return -2;
-        if (c > s.col_max) c = words_free_up<D2>(g, w, m0, mask0, hw, PH, 0);
+        if (c > s.col_max) c = up(0);
         return c;
     }
-    return words_free_up<D2>(g, w, m0, mask0, hw, PH, 0);
+    return up(0);
+}
+
+// Vertices of many nets under the balancing policies: their color words are
+// ORed over all their nets once per round by the whole device (a wave per
+// slice of HEAVY_SLICE nets, lanes over consecutive words of each net's row),
+// not by the single wave that walks their chunk.
+constexpr int HEAVY_NETS = 128;    // more nets than this: words precomputed
+constexpr int HEAVY_SLICE = 256;   // nets per wave of the precomputation
+
+struct HeavySlice {
+    int h, k0;   // heavy vertex index, first net of the slice
+};
+
+// hid[w] = index of w among the heavy vertices, or -1; hlist[h] = w; slices
+// of each heavy vertex's nets.  counts[0] = heavy vertices, counts[1] = slices.
+template <bool D2>
+__global__ void k_heavy_mark(Graph g, int *hid, int *hlist, HeavySlice *slices, int *counts)
+{
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < g.n_a; w += gridDim.x * blockDim.x) {
+        const int d = Acc<D2>::nets_count(g, w);
+        if (d <= HEAVY_NETS) {
+            hid[w] = -1;
+            continue;
+        }
+        const int h = atomicAdd(&counts[0], 1);
+        const int k = (d + HEAVY_SLICE - 1) / HEAVY_SLICE;
+        const int base = atomicAdd(&counts[1], k);
+        hlist[h] = w;
+        hid[w] = h;
+        for (int j = 0; j < k; j++) slices[base + j] = HeavySlice{h, j * HEAVY_SLICE};
+    }
+}
+
+// Row h of F (words 0..PH, zeroed before): OR over the nets of heavy vertex
+// hlist[h] of word p (mask0 for p = 0, else color word p - 1), for the heavy
+// vertices not yet colored.  Words past the largest color so far stay zero.
+template <bool D2>
+__global__ void __launch_bounds__(256) k_heavy_words(Graph g, const int *st, const int *hlist,
+                                                     const HeavySlice *slices, const int *counts,
+                                                     const uint64_t *mask0, const uint64_t *hw, int PH,
+                                                     const Ctrl *ctrl, uint64_t *F)
+{
+    constexpr int NWV = 256 / WAVE;
+    __shared__ int s_net[NWV][HEAVY_SLICE];
+    const int lane = lane_id(), wid = threadIdx.x / WAVE;
+    const int ns = counts[1];
+    const int pmax = min(PH, max(ctrl->max_color, 0) >> 6);
+    const int nwv = gridDim.x * NWV;
+    for (int sl = blockIdx.x * NWV + wid; sl < ns; sl += nwv) {
+        const HeavySlice S = slices[sl];
+        const int w = hlist[S.h];
+        const int sw = st[w];
+        if (sw >= 0 && !(sw & TENT)) continue;   // colored: not in the worklist
+        const int cnt = min(HEAVY_SLICE, Acc<D2>::nets_count(g, w) - S.k0);
+        for (int k = lane; k < cnt; k += WAVE) s_net[wid][k] = Acc<D2>::net_at(g, w, S.k0 + k);
+        wave_sync();
+        uint64_t *row = F + (long)S.h * (PH + 1);
+        for (int p0 = 0; p0 <= pmax; p0 += WAVE) {
+            const int p = p0 + lane;
+            uint64_t acc = 0;
+            if (p <= pmax) {
+                int k = 0;
+                for (; k + 8 <= cnt; k += 8) {
+                    uint64_t x[8];
+#pragma unroll
+                    for (int q = 0; q < 8; q++) {
+                        const int v = s_net[wid][k + q];
+                        x[q] = p == 0 ? mask0[v] : hw[(long)v * PH + p - 1];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; q++) acc |= x[q];
+                }
+                for (; k < cnt; k++) {
+                    const int v = s_net[wid][k];
+                    acc |= p == 0 ? mask0[v] : hw[(long)v * PH + p - 1];
+                }
+            }
+            if (acc) atomicOr((unsigned long long *)&row[p], acc);
+        }
+        wave_sync();
+    }
 }
 
 // One wave (block of 64) per chunk of `chunk` consecutive worklist entries;
 // the policy state runs through the chunk in worklist order.  Lanes compute
 // the low masks of 64 entries at a time; an entry whose pick needs colors
-// >= 64 searches the higher color words with the whole wave, or, past the
-// allocated words, builds its full forbidden bitmap with the whole wave.
+// >= 64 searches the higher color words with the whole wave (a vertex of many
+// nets in its precomputed row of F), or, past the allocated words, builds its
+// full forbidden bitmap with the whole wave.
 template <bool D2>
 __global__ void __launch_bounds__(64) k_vcolor_chunked(Graph g, const int *W, Ctrl *ctrl, int par, int *st,
                                                         const uint64_t *mask0, int policy, int chunk, int lds_bits,
-                                                        const uint64_t *hw, int PH, uint8_t *dirty)
+                                                        const uint64_t *hw, int PH, uint8_t *dirty, const int *hid,
+                                                        const uint64_t *F)
 {
     extern __shared__ uint32_t dyn[];
     __shared__ int s_net[65], s_pre[65], s_scan[4], s_res;
@@ -774,20 +907,28 @@ __global__ void __launch_bounds__(64) k_vcolor_chunked(Graph g, const int *W, Ct
         int cap = -1;
         for (int sub = lo; sub < hi; sub += WAVE) {
             int i = sub + lane;
-            int w = -1;
+            int w = -1, h = -1;
             uint64_t m = 0;
             if (i < hi) {
                 w = W[i];
-                m = D2 ? mask0[w] : 0ull;
-                for (int k = g.a_off[w]; k < g.a_off[w + 1]; k++) m |= mask0[g.a_idx[k]];
+                h = F ? hid[w] : -1;
+                if (h >= 0) {
+                    m = F[(long)h * (PH + 1)];
+                } else {
+                    m = D2 ? mask0[w] : 0ull;
+                    for (int k = g.a_off[w]; k < g.a_off[w + 1]; k++) m |= mask0[g.a_idx[k]];
+                }
             }
             int cnt = min(WAVE, hi - sub);
             for (int j = 0; j < cnt; j++) {
                 int wj = __shfl(w, j);
+                const int hj = __shfl(h, j);
                 uint64_t mj = shfl64(m, j);
                 int col;
                 if (!pick_low(policy, mj, wj, s, &col)) {
-                    col = PH > 0 ? pick_words<D2>(g, wj, mj, mask0, hw, PH, policy, s) : -2;
+                    col = PH > 0 ? pick_words<D2>(g, wj, mj, mask0, hw, PH, policy, s,
+                                                  hj >= 0 ? F + (long)hj * (PH + 1) : nullptr)
+                                 : -2;
                     if (col == -2) {
                         if (cap < 0) cap = ctrl->max_color + 2;
                         if (cap > lds_bits) {
@@ -1396,8 +1537,9 @@ __global__ void k_conflict_big(Graph g, const int *st, uint8_t *lose, uint8_t *d
 // after a net-based round that may evict colored vertices): losers become
 // uncolored, winners keep their proposal and, when the masks are maintained
 // incrementally (update_masks), set its bit in the masks of their nets (each
-// wave walks its winners' rows as one flat range).  Writes the number of
-// uncolored entries of each tile.
+// wave queues its winners of a tile in LDS and walks their rows 64 winners at
+// a time as one flat range, so the row offsets and the rows are each one
+// round of loads).  Writes the number of uncolored entries of each tile.
 template <bool D2>
 __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, Ctrl *ctrl, int par, int *st,
                                                       uint8_t *lose, uint64_t *mask0, int *tile_count,
@@ -1405,9 +1547,11 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
                                                       int PH, const int *lcnt)
 {
     constexpr int NWV = TILE_BLOCK / WAVE;
+    constexpr int WQ = 2 * WAVE;   // winners queued per wave before their rows are walked
     __shared__ int s_scan[8];
+    __shared__ int s_u[NWV][WQ];
+    __shared__ uint8_t s_col[NWV][WQ];
     __shared__ int s_pre[NWV][64], s_beg[NWV][64];
-    __shared__ unsigned long long s_bit[NWV][64];
     const int n = list ? ctrl->n_w[par] : g.n_a;
     const int ntiles = (n + TILE - 1) / TILE;
     const int lane = lane_id(), wid = threadIdx.x / WAVE;
@@ -1415,10 +1559,47 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
         ctrl->n_w[par ^ 1] = 0;
         ctrl->n_heavy = 0;
     }
+    // the queued winners' rows, 64 winners at a time: row offsets in one
+    // pass, then the rows as one flat range, one mask word update per entry
+    auto walk = [&](int qn) {
+        for (int c0 = 0; c0 < qn; c0 += 64) {
+            const int j = c0 + lane;
+            int beg = 0, d = 0;
+            if (j < qn) {
+                const int u = s_u[wid][j];
+                beg = g.a_off[u];
+                d = g.a_off[u + 1] - beg;
+            }
+            const int incl = wave_incl_scan(d);
+            const int total = __shfl(incl, 63);
+            s_pre[wid][lane] = incl - d;
+            s_beg[wid][lane] = beg;
+            wave_sync();
+            for (int f0 = 0; f0 < total; f0 += 256) {
+                int tgt[4];
+                unsigned long long bt[4];
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    int f = f0 + q * 64 + lane;
+                    tgt[q] = -1;
+                    bt[q] = 0;
+                    if (f < total) {
+                        int r = row_of(s_pre[wid], f);
+                        tgt[q] = g.a_idx[s_beg[wid][r] + f - s_pre[wid][r]];
+                        bt[q] = 1ull << s_col[wid][c0 + r];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+                    if (tgt[q] >= 0) atomicOr((unsigned long long *)&mask0[tgt[q]], bt[q]);
+            }
+            wave_sync();
+        }
+    };
     constexpr int KS = TILE / TILE_BLOCK;
     int evicted = 0, mx = -1;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        int cnt = 0;
+        int cnt = 0, qn = 0;
         int us[KS], ss[KS];
         uint8_t ls[KS];
 #pragma unroll
@@ -1432,8 +1613,8 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
             ls[k] = us[k] >= 0 ? (lcnt ? (uint8_t)(lcnt[us[k]] > 0) : lose[us[k]]) : 0;
         }
         for (int k = 0; k < KS; k++) {
-            int beg = 0, d = 0;
-            unsigned long long bit = 0;
+            bool q64 = false;
+            int col = 0;
             if (us[k] >= 0) {
                 int u = us[k];
                 int s = ss[k];
@@ -1447,14 +1628,12 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
                 } else if (s < 0) {
                     cnt++;
                 } else {
-                    int col = s & COLOR_MASK;
+                    col = s & COLOR_MASK;
                     if (s & TENT) {
                         st[u] = col;
                         if (update_masks && col < 64) {
-                            bit = 1ull << col;
-                            beg = g.a_off[u];
-                            d = g.a_off[u + 1] - beg;
-                            if (D2) atomicOr((unsigned long long *)&mask0[u], bit);
+                            q64 = true;
+                            if (D2) atomicOr((unsigned long long *)&mask0[u], 1ull << col);
                         } else if (update_masks && (col >> 6) - 1 < PH) {
                             // higher color word of every net of u
                             const int p = (col >> 6) - 1;
@@ -1468,35 +1647,23 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
                 }
             }
             if (update_masks) {
-                // each wave walks its own winners' rows (its own LDS slice:
-                // wave-level ordering suffices; waves without winners skip)
-                int incl = wave_incl_scan(d);
-                int total = __shfl(incl, 63);
-                if (total == 0) continue;
-                s_pre[wid][lane] = incl - d;
-                s_beg[wid][lane] = beg;
-                s_bit[wid][lane] = bit;
-                wave_sync();
-                for (int f0 = 0; f0 < total; f0 += 256) {
-                    int tgt[4];
-                    unsigned long long bt[4];
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        int f = f0 + q * 64 + lane;
-                        tgt[q] = -1;
-                        bt[q] = 0;
-                        if (f < total) {
-                            int j = row_of(s_pre[wid], f);
-                            tgt[q] = g.a_idx[s_beg[wid][j] + f - s_pre[wid][j]];
-                            bt[q] = s_bit[wid][j];
-                        }
-                    }
-#pragma unroll
-                    for (int q = 0; q < 4; q++)
-                        if (tgt[q] >= 0) atomicOr((unsigned long long *)&mask0[tgt[q]], bt[q]);
+                const uint64_t bal = __ballot(q64);
+                if (q64) {
+                    const int r = qn + __builtin_popcountll(bal & ((1ull << lane) - 1ull));
+                    s_u[wid][r] = us[k];
+                    s_col[wid][r] = (uint8_t)col;
                 }
-                wave_sync();
+                qn += __builtin_popcountll(bal);
+                if (qn > WQ - WAVE) {
+                    wave_sync();
+                    walk(qn);
+                    qn = 0;
+                }
             }
+        }
+        if (update_masks && qn > 0) {
+            wave_sync();
+            walk(qn);
         }
         cnt = block_sum(cnt, s_scan);
         if (threadIdx.x == 0) tile_count[t] = cnt;

@@ -152,8 +152,11 @@ def test_big_nets(cuda):
 
 
 def test_skewed_small(cuda):
+    """Vertices of up to 1,603 nets: under B1/B2 their color words are
+    precomputed per round (more than 128 nets) and searched as one row."""
     g = synth.skewed(30000, 30000, seed=3, kmax=3000)
-    for kw in (dict(net_color_mask=1), dict(net_color_mask=1, policy=1), dict(net_color_mask=1, policy=2)):
+    for kw in (dict(net_color_mask=1), dict(net_color_mask=1, policy=1), dict(net_color_mask=1, policy=2),
+               dict(net_color_mask=1, policy=1, chunk=7), dict(policy=2, chunk=200)):
         ref = oracle.bgpc(g, **kw)
         res, colors = _gpu_bgpc(cuda, g, **kw)
         _compare_full(res, colors, ref)
@@ -171,6 +174,11 @@ def test_d2gc_rmat_small(cuda, mask):
 def test_d2gc_policies(cuda):
     adj = synth.rmat(10, 4, 0.57, 0.19, 0.19, seed=10)
     for kw in (dict(policy=1), dict(policy=2), dict(policy=1, net_color_mask=1)):
+        ref = oracle.d2gc(adj, **kw)
+        res, colors = _gpu_d2(cuda, adj, **kw)
+        _compare_full(res, colors, ref)
+    adj = synth.rmat(11, 8, 0.57, 0.19, 0.19, seed=9)   # 21 vertices of more than 128 closed neighbourhoods
+    for kw in (dict(policy=1, net_color_mask=1), dict(policy=2, net_color_mask=1), dict(policy=2, chunk=5)):
         ref = oracle.d2gc(adj, **kw)
         res, colors = _gpu_d2(cuda, adj, **kw)
         _compare_full(res, colors, ref)
