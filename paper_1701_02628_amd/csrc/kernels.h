@@ -777,17 +777,97 @@ __device__ int row_free_down(const uint64_t *Fw, int PH, int from)
     return -1;
 }
 
+// The nets of a vertex of at most 2 * WAVE nets held in registers for the
+// searches of one pick: lanes form groups of L (a power of two >= the net
+// count, at most WAVE); each group ORs one word, WAVE / L words per pass.
+struct NetRegs {
+    int v0, v1, L;
+};
+
+template <bool D2>
+__device__ NetRegs load_nets(const Graph &g, int w, int nn)
+{
+    NetRegs r;
+    r.L = 1;
+    while (r.L < nn && r.L < WAVE) r.L <<= 1;
+    const int k = lane_id() & (r.L - 1);
+    r.v0 = k < nn ? Acc<D2>::net_at(g, w, k) : -1;
+    r.v1 = (r.L == WAVE && k + WAVE < nn) ? Acc<D2>::net_at(g, w, k + WAVE) : -1;
+    return r;
+}
+
+// word p (0 <= p <= PH, else 0) of the group's nets, in every lane of the group
+__device__ __forceinline__ uint64_t group_word_or(const NetRegs &r, const uint64_t *mask0, const uint64_t *hw, int PH,
+                                                  int p)
+{
+    uint64_t m = 0;
+    if (p >= 0 && p <= PH) {
+        if (r.v0 >= 0) m |= p == 0 ? mask0[r.v0] : hw[(long)r.v0 * PH + p - 1];
+        if (r.v1 >= 0) m |= p == 0 ? mask0[r.v1] : hw[(long)r.v1 * PH + p - 1];
+    }
+    for (int d = r.L / 2; d > 0; d >>= 1) m |= shfl64(m, lane_id() ^ d);
+    return m;
+}
+
+__device__ int regs_free_up(const NetRegs &r, uint64_t m0, const uint64_t *mask0, const uint64_t *hw, int PH, int from)
+{
+    const int lane = lane_id(), G = WAVE / r.L, q = lane / r.L;
+    const bool lead = (lane & (r.L - 1)) == 0;
+    for (int pb = from >> 6; pb <= PH; pb += G) {
+        const int p = pb + q;
+        uint64_t m = group_word_or(r, mask0, hw, PH, p);   // every lane: the groups shuffle
+        if (p == 0) m = m0;
+        if (p == (from >> 6)) m |= (1ull << (from & 63)) - 1ull;
+        const uint64_t fr = p <= PH ? ~m : 0ull;
+        const uint64_t bal = __ballot(lead && fr != 0);
+        if (bal) {
+            const int j = __builtin_ctzll(bal);
+            return 64 * (pb + j / r.L) + __builtin_ctzll(shfl64(fr, j));
+        }
+    }
+    return -2;
+}
+
+__device__ int regs_free_down(const NetRegs &r, uint64_t m0, const uint64_t *mask0, const uint64_t *hw, int PH,
+                              int from)
+{
+    if (from < 0) return -1;
+    if ((from >> 6) > PH) return -2;
+    const int lane = lane_id(), G = WAVE / r.L, q = lane / r.L;
+    const bool lead = (lane & (r.L - 1)) == 0;
+    for (int pb = from >> 6; pb >= 0; pb -= G) {
+        const int p = pb - q;
+        uint64_t m = group_word_or(r, mask0, hw, PH, p);   // every lane: the groups shuffle
+        if (p == 0) m = m0;
+        uint64_t fr = p >= 0 ? ~m : 0ull;
+        if (p == (from >> 6)) fr &= bits_upto(from & 63);
+        const uint64_t bal = __ballot(lead && fr != 0);
+        if (bal) {
+            const int j = __builtin_ctzll(bal);   // lowest lane: highest word
+            return 64 * (pb - j / r.L) + 63 - __builtin_clzll(shfl64(fr, j));
+        }
+    }
+    return -1;
+}
+
 // One policy pick from the color words (Fw: w's precomputed row, or null);
 // -2 when they do not reach far enough.
 template <bool D2>
 __device__ int pick_words(const Graph &g, int w, uint64_t m0, const uint64_t *mask0, const uint64_t *hw, int PH,
                           int policy, const PolicyState &s, const uint64_t *Fw)
 {
+    const int nn = Fw ? 0 : Acc<D2>::nets_count(g, w);
+    const bool regs = !Fw && nn <= 2 * WAVE;
+    NetRegs r = {-1, -1, 1};
+    if (regs) r = load_nets<D2>(g, w, nn);
     auto up = [&](int from) {
-        return Fw ? row_free_up(Fw, PH, from) : words_free_up<D2>(g, w, m0, mask0, hw, PH, from);
+        return Fw ? row_free_up(Fw, PH, from)
+                  : regs ? regs_free_up(r, m0, mask0, hw, PH, from) : words_free_up<D2>(g, w, m0, mask0, hw, PH, from);
     };
     auto down = [&](int from) {
-        return Fw ? row_free_down(Fw, PH, from) : words_free_down<D2>(g, w, m0, mask0, hw, PH, from);
+        return Fw ? row_free_down(Fw, PH, from)
+                  : regs ? regs_free_down(r, m0, mask0, hw, PH, from)
+                         : words_free_down<D2>(g, w, m0, mask0, hw, PH, from);
     };
     if (policy == 1 && (w & 1) == 0) {   // B1, even rank
         int c = down(s.col_max);
@@ -904,13 +984,14 @@ __global__ void __launch_bounds__(64) k_vcolor_chunked(Graph g, const int *W, Ct
     for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
         PolicyState s = {0, 0};
         int lo = ch * chunk, hi = min(lo + chunk, n);
-        int cap = -1;
+        int cap = -1, cmax = -1;
         for (int sub = lo; sub < hi; sub += WAVE) {
             int i = sub + lane;
-            int w = -1, h = -1;
+            int w = -1, h = -1, sw = 0;
             uint64_t m = 0;
             if (i < hi) {
                 w = W[i];
+                if (dirty) sw = st[w];   // only this wave writes st[w] in this launch
                 h = F ? hid[w] : -1;
                 if (h >= 0) {
                     m = F[(long)h * (PH + 1)];
@@ -945,15 +1026,17 @@ __global__ void __launch_bounds__(64) k_vcolor_chunked(Graph g, const int *W, Ct
                 policy_update(policy, col, s);
                 if (dirty) {
                     // standing proposals: a changed proposal re-opens wj's nets
-                    const bool changed = st[wj] != (TENT | col);
+                    const bool changed = __shfl(sw, j) != (TENT | col);
                     if (changed) mark_nets_dirty<D2>(g, wj, dirty, lane, WAVE);
                 }
-                if (lane == 0) {
-                    st[wj] = TENT | col;
-                    max_to(&ctrl->max_color, col);
-                }
+                if (lane == 0) st[wj] = TENT | col;
+                cmax = max(cmax, col);
             }
         }
+        // colors >= cap count as free in the fallback bitmaps, and cap was read
+        // from the largest color of the snapshot: the chunk's own picks need not
+        // be visible before it ends
+        if (lane == 0 && cmax >= 0) max_to(&ctrl->max_color, cmax);
     }
 }
 
