@@ -607,7 +607,7 @@ int run(const RunArgs &a)
                 if (!D2) k_ncolor_isolated<<<g_a, nthr, 0, s>>>(g, Wc, ctrl, par, st);
                 LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 0, PCNT(r), sp_none)));
                 if (n_big)
-                    k_conflict_big<D2><<<g_big, 256, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 0,
+                    k_conflict_big<D2><<<g_big, BIG_BLOCK, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 0,
                                                                            sp_none);
                 const bool full = r > 0 || resume;
                 if (full) {
@@ -715,7 +715,7 @@ int run(const RunArgs &a)
                 if (spr && prof_kernel == BGPC_PROF_CONFLICT && PCNT(r))
                     k_census<D2><<<g_b, nthr, 0, s>>>(g, st, PCNT(r));
                 if (n_big)
-                    k_conflict_big<D2><<<g_big, 256, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 1,
+                    k_conflict_big<D2><<<g_big, BIG_BLOCK, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 1,
                                                                            spx);
                 k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1, hw, PH,
                                                       spr ? sp_cnt : nullptr);

@@ -1522,9 +1522,12 @@ __device__ __forceinline__ unsigned hash_color(int c) { return (unsigned)c * 265
 // Block per net larger than SMALL_NET.  Nets up to HASH_MAX members use an
 // LDS hash color -> lowest-ranked holder; larger nets sweep the colors in
 // windows of WIN_COLORS with a direct-mapped table.
+constexpr int BIG_BLOCK = 256;                          // threads of k_conflict_big
+constexpr int BIG_PER_THREAD = HASH_MAX / BIG_BLOCK;    // members per thread of a hashed net
 template <bool D2>
-__global__ void k_conflict_big(Graph g, const int *st, uint8_t *lose, uint8_t *done, const int *big,
-                               const int *n_big_p, Ctrl *ctrl, int tent_only, SPState sp)
+__global__ void __launch_bounds__(BIG_BLOCK) k_conflict_big(Graph g, const int *st, uint8_t *lose, uint8_t *done,
+                                                            const int *big, const int *n_big_p, Ctrl *ctrl,
+                                                            int tent_only, SPState sp)
 {
     extern __shared__ int sh[];
     __shared__ int s_scan[20];
@@ -1535,18 +1538,27 @@ __global__ void k_conflict_big(Graph g, const int *st, uint8_t *lose, uint8_t *d
         if (done[v] || (sp.lbits && !sp.dirty[v])) continue;
         const long lpos = sp.lbits ? sp_lpos<D2>(g, v) : 0;
         int sz = Acc<D2>::size(g, v);
-        int pending = 0;
-        for (int k = tid; k < sz; k += nt) {
-            int s = st[Acc<D2>::member(g, v, k)];
-            pending += (s < 0 || (s & TENT)) ? 1 : 0;
-        }
-        pending = block_sum(pending, s_scan);
-        if (sp.lbits && tid == 0) sp.dirty[v] = 0;
-        if (pending == 0) {
-            if (tid == 0) done[v] = 1;
-            continue;
-        }
         if (sz <= HASH_MAX) {
+            // members and states read once into registers (the block holds
+            // BIG_PER_THREAD per thread), all loads of a batch in flight
+            int xs[BIG_PER_THREAD], ss[BIG_PER_THREAD];
+#pragma unroll
+            for (int i = 0; i < BIG_PER_THREAD; i++) {
+                const int k = tid + i * BIG_BLOCK;
+                xs[i] = k < sz ? Acc<D2>::member(g, v, k) : -1;
+            }
+            int pending = 0;
+#pragma unroll
+            for (int i = 0; i < BIG_PER_THREAD; i++) {
+                ss[i] = xs[i] >= 0 ? st[xs[i]] : 0;
+                pending += (xs[i] >= 0 && (ss[i] < 0 || (ss[i] & TENT))) ? 1 : 0;
+            }
+            pending = block_sum(pending, s_scan);
+            if (sp.lbits && tid == 0) sp.dirty[v] = 0;
+            if (pending == 0) {
+                if (tid == 0) done[v] = 1;
+                continue;
+            }
             int cap = 64;
             while (cap < 2 * sz) cap <<= 1;
             int *keys = sh, *minr = sh + cap;
@@ -1555,11 +1567,11 @@ __global__ void k_conflict_big(Graph g, const int *st, uint8_t *lose, uint8_t *d
                 minr[i] = 0x7fffffff;
             }
             __syncthreads();
-            for (int k = tid; k < sz; k += nt) {
-                int x = Acc<D2>::member(g, v, k);
-                int s = st[x];
-                if (tent_only && !(s >= 0 && (s & TENT))) continue;
-                int c = cur_color(s);
+#pragma unroll
+            for (int i = 0; i < BIG_PER_THREAD; i++) {
+                const int x = xs[i], s = ss[i];
+                if (x < 0 || (tent_only && !(s >= 0 && (s & TENT)))) continue;
+                const int c = cur_color(s);
                 if (c < 0) continue;
                 unsigned h = hash_color(c) & (cap - 1);
                 for (;;) {
@@ -1572,19 +1584,32 @@ __global__ void k_conflict_big(Graph g, const int *st, uint8_t *lose, uint8_t *d
                 }
             }
             __syncthreads();
-            for (int k = tid; k < sz; k += nt) {
-                int x = Acc<D2>::member(g, v, k);
-                int s = st[x];
-                if (tent_only && !(s >= 0 && (s & TENT))) continue;
-                int c = cur_color(s);
+#pragma unroll
+            for (int i = 0; i < BIG_PER_THREAD; i++) {
+                const int x = xs[i], s = ss[i];
+                if (x < 0 || (tent_only && !(s >= 0 && (s & TENT)))) continue;
+                const int c = cur_color(s);
                 if (c < 0) continue;
                 unsigned h = hash_color(c) & (cap - 1);
                 while (keys[h] != c) h = (h + 1) & (cap - 1);
-                if (sp.lbits) sp_set(sp, lpos + k, x, minr[h] != x);
+                if (sp.lbits) sp_set(sp, lpos + tid + i * BIG_BLOCK, x, minr[h] != x);
                 else if (minr[h] != x) lose[x] = 1;
             }
             __syncthreads();
-        } else {
+            continue;
+        }
+        int pending = 0;
+        for (int k = tid; k < sz; k += nt) {
+            int s = st[Acc<D2>::member(g, v, k)];
+            pending += (s < 0 || (s & TENT)) ? 1 : 0;
+        }
+        pending = block_sum(pending, s_scan);
+        if (sp.lbits && tid == 0) sp.dirty[v] = 0;
+        if (pending == 0) {
+            if (tid == 0) done[v] = 1;
+            continue;
+        }
+        {
             int maxc = ctrl->max_color;
             for (int base = 0; base <= maxc; base += WIN_COLORS) {
                 for (int i = tid; i < WIN_COLORS; i += nt) sh[i] = 0x7fffffff;
@@ -1633,7 +1658,7 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
     constexpr int WQ = 2 * WAVE;   // winners queued per wave before their rows are walked
     __shared__ int s_scan[8];
     __shared__ int s_u[NWV][WQ];
-    __shared__ uint8_t s_col[NWV][WQ];
+    __shared__ int s_col[NWV][WQ];
     __shared__ int s_pre[NWV][64], s_beg[NWV][64];
     const int n = list ? ctrl->n_w[par] : g.n_a;
     const int ntiles = (n + TILE - 1) / TILE;
@@ -1643,7 +1668,8 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
         ctrl->n_heavy = 0;
     }
     // the queued winners' rows, 64 winners at a time: row offsets in one
-    // pass, then the rows as one flat range, one mask word update per entry
+    // pass, then the rows as one flat range, one color word update per entry
+    // (mask0 for colors below 64, else the color's higher word)
     auto walk = [&](int qn) {
         for (int c0 = 0; c0 < qn; c0 += 64) {
             const int j = c0 + lane;
@@ -1659,22 +1685,25 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
             s_beg[wid][lane] = beg;
             wave_sync();
             for (int f0 = 0; f0 < total; f0 += 256) {
-                int tgt[4];
-                unsigned long long bt[4];
+                int tgt[4], cq[4];
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
                     int f = f0 + q * 64 + lane;
                     tgt[q] = -1;
-                    bt[q] = 0;
+                    cq[q] = 0;
                     if (f < total) {
                         int r = row_of(s_pre[wid], f);
                         tgt[q] = g.a_idx[s_beg[wid][r] + f - s_pre[wid][r]];
-                        bt[q] = 1ull << s_col[wid][c0 + r];
+                        cq[q] = s_col[wid][c0 + r];
                     }
                 }
 #pragma unroll
-                for (int q = 0; q < 4; q++)
-                    if (tgt[q] >= 0) atomicOr((unsigned long long *)&mask0[tgt[q]], bt[q]);
+                for (int q = 0; q < 4; q++) {
+                    if (tgt[q] < 0) continue;
+                    const int c = cq[q];
+                    uint64_t *wd = c < 64 ? &mask0[tgt[q]] : &hw[(long)tgt[q] * PH + (c >> 6) - 1];
+                    atomicOr((unsigned long long *)wd, 1ull << (c & 63));
+                }
             }
             wave_sync();
         }
@@ -1714,16 +1743,14 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
                     col = s & COLOR_MASK;
                     if (s & TENT) {
                         st[u] = col;
-                        if (update_masks && col < 64) {
+                        // the color's word in every net of u (colors past the
+                        // allocated words are not tracked)
+                        if (update_masks && (col < 64 || (col >> 6) - 1 < PH)) {
                             q64 = true;
-                            if (D2) atomicOr((unsigned long long *)&mask0[u], 1ull << col);
-                        } else if (update_masks && (col >> 6) - 1 < PH) {
-                            // higher color word of every net of u
-                            const int p = (col >> 6) - 1;
-                            const unsigned long long b = 1ull << (col & 63);
-                            const int nn = Acc<D2>::nets_count(g, u);
-                            for (int q = 0; q < nn; q++)
-                                atomicOr((unsigned long long *)&hw[(long)Acc<D2>::net_at(g, u, q) * PH + p], b);
+                            if (D2) {   // the closed neighbourhood of u itself
+                                uint64_t *wd = col < 64 ? &mask0[u] : &hw[(long)u * PH + (col >> 6) - 1];
+                                atomicOr((unsigned long long *)wd, 1ull << (col & 63));
+                            }
                         }
                     }
                     mx = max(mx, col);
@@ -1734,7 +1761,7 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
                 if (q64) {
                     const int r = qn + __builtin_popcountll(bal & ((1ull << lane) - 1ull));
                     s_u[wid][r] = us[k];
-                    s_col[wid][r] = (uint8_t)col;
+                    s_col[wid][r] = col;
                 }
                 qn += __builtin_popcountll(bal);
                 if (qn > WQ - WAVE) {
