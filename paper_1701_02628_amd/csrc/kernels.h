@@ -1524,13 +1524,16 @@ __device__ __forceinline__ unsigned hash_color(int c) { return (unsigned)c * 265
 // windows of WIN_COLORS with a direct-mapped table.
 constexpr int BIG_BLOCK = 256;                          // threads of k_conflict_big
 constexpr int BIG_PER_THREAD = HASH_MAX / BIG_BLOCK;    // members per thread of a hashed net
+constexpr int BIG_LIST = 2048;   // proposals of a larger net resolved by the hash (3 + 4 ints each in LDS)
+static_assert(3 * BIG_LIST + 2 * (2 * BIG_LIST) <= WIN_COLORS && (BIG_LIST & (BIG_LIST - 1)) == 0 && 2 * (2 * HASH_MAX) <= WIN_COLORS,
+              "k_conflict_big's LDS layouts fit its WIN_COLORS-int allocation");
 template <bool D2>
 __global__ void __launch_bounds__(BIG_BLOCK) k_conflict_big(Graph g, const int *st, uint8_t *lose, uint8_t *done,
                                                             const int *big, const int *n_big_p, Ctrl *ctrl,
                                                             int tent_only, SPState sp)
 {
     extern __shared__ int sh[];
-    __shared__ int s_scan[20];
+    __shared__ int s_scan[20], s_cnt;
     const int n_big = *n_big_p;
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int bi = blockIdx.x; bi < n_big; bi += gridDim.x) {
@@ -1598,15 +1601,64 @@ __global__ void __launch_bounds__(BIG_BLOCK) k_conflict_big(Graph g, const int *
             __syncthreads();
             continue;
         }
+        // larger nets: one pass counts the pending members and, when only
+        // proposals take part, lists them in LDS; few enough of them go
+        // through the hash, else the colors are swept in windows
+        int *lst = sh;                       // (position, member, color) per proposal
+        int *hsh = sh + 3 * BIG_LIST;        // hash of the listed proposals
+        if (tid == 0) s_cnt = 0;
+        __syncthreads();
         int pending = 0;
         for (int k = tid; k < sz; k += nt) {
-            int s = st[Acc<D2>::member(g, v, k)];
+            const int x = Acc<D2>::member(g, v, k);
+            const int s = st[x];
             pending += (s < 0 || (s & TENT)) ? 1 : 0;
+            if (tent_only && s >= 0 && (s & TENT)) {
+                const int q = atomicAdd(&s_cnt, 1);
+                if (q < BIG_LIST) {
+                    lst[3 * q] = k;
+                    lst[3 * q + 1] = x;
+                    lst[3 * q + 2] = cur_color(s);
+                }
+            }
         }
         pending = block_sum(pending, s_scan);
         if (sp.lbits && tid == 0) sp.dirty[v] = 0;
         if (pending == 0) {
             if (tid == 0) done[v] = 1;
+            continue;
+        }
+        const int nl = s_cnt;
+        if (tent_only && nl <= BIG_LIST) {
+            int cap = 64;
+            while (cap < 2 * nl) cap <<= 1;
+            int *keys = hsh, *minr = hsh + cap;
+            for (int i = tid; i < cap; i += nt) {
+                keys[i] = -1;
+                minr[i] = 0x7fffffff;
+            }
+            __syncthreads();
+            for (int q = tid; q < nl; q += nt) {
+                const int x = lst[3 * q + 1], c = lst[3 * q + 2];
+                unsigned h = hash_color(c) & (cap - 1);
+                for (;;) {
+                    int prev = atomicCAS(&keys[h], -1, c);
+                    if (prev == -1 || prev == c) {
+                        atomicMin(&minr[h], x);
+                        break;
+                    }
+                    h = (h + 1) & (cap - 1);
+                }
+            }
+            __syncthreads();
+            for (int q = tid; q < nl; q += nt) {
+                const int k = lst[3 * q], x = lst[3 * q + 1], c = lst[3 * q + 2];
+                unsigned h = hash_color(c) & (cap - 1);
+                while (keys[h] != c) h = (h + 1) & (cap - 1);
+                if (sp.lbits) sp_set(sp, lpos + k, x, minr[h] != x);
+                else if (minr[h] != x) lose[x] = 1;
+            }
+            __syncthreads();
             continue;
         }
         {
