@@ -221,10 +221,12 @@ int run(const RunArgs &a)
     for (int r = 0; r < max_rounds && start_round + r < 64; r++)
         if (start_round + r >= 0 && ((o.net_color_mask >> (start_round + r)) & 1ull)) any_net_round = true;
     const size_t sp_words = (size_t)((a.nnz + (D2 ? n_b : 0)) / 64 + 4);
+    const long n_huge_cap = std::min<long>(n_b, (a.nnz + (D2 ? n_b : 0)) / (HASH_MAX + 1) + 1) + 1;
     size_t bytes = aligned(n_a + 1, 4) * 4            // W[0], W[1], heavy, first-fit cursors
                    + aligned(n_a + 1, 1)              // lose
                    + aligned(n_b + 1, 8)              // mask0
                    + aligned(n_b + 1, 4)              // big net list
+                   + aligned(n_huge_cap, 4)           // nets above HASH_MAX members
                    + aligned(n_b + 1, 1)              // done nets
                    + aligned(max_tiles, 4)            // tile counts
                    + aligned(1, sizeof(Ctrl))         //
@@ -250,6 +252,7 @@ int run(const RunArgs &a)
     uint8_t *lose = ar.take<uint8_t>(n_a + 1);
     uint64_t *mask0 = ar.take<uint64_t>(n_b + 1);
     int *big = ar.take<int>(n_b + 1);
+    int *huge = ar.take<int>(n_huge_cap);
     uint8_t *done_net = ar.take<uint8_t>(n_b + 1);
     int *tile_count = ar.take<int>(max_tiles);
     Ctrl *ctrl = ar.take<Ctrl>(1);
@@ -363,7 +366,8 @@ int run(const RunArgs &a)
     k_fill_i32<<<1, 64, 0, s>>>(shape, 0, 8);
     k_fill_i32<<<grid_for(rec_cap * (long)sizeof(RoundRec) / 4, nthr, di.cus * 4), nthr, 0, s>>>(
         (int *)rec, 0, rec_cap * (long)sizeof(RoundRec) / 4);
-    k_net_shape<D2><<<g_b, nthr, 0, s>>>(g, &shape[0], big, &shape[1], (unsigned long long *)&shape[4], &shape[2]);
+    k_net_shape<D2><<<g_b, nthr, 0, s>>>(g, &shape[0], big, &shape[1], (unsigned long long *)&shape[4], &shape[2],
+                                         huge, &shape[3]);
     LAUNCH_CHECK();
     if (hipMemcpyAsync(h_shape, shape, sizeof(h_shape), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
@@ -373,6 +377,7 @@ int run(const RunArgs &a)
     {
         const int max_net = h_shape[0];
         const int n_big = h_shape[1];
+        const int n_huge = h_shape[3];
         // distance-2 degree bound: most nets of a vertex x largest net
         const long two_hop = std::min<long>((long)h_shape[2] * (long)max_net, 1L << 30);
         unsigned long long walk;
@@ -420,6 +425,23 @@ int run(const RunArgs &a)
             goto finish;
         }
         const int conflict_bytes = (int)(WIN_COLORS * sizeof(int));
+        // nets above HASH_MAX members in vertex-based rounds: block per net, a
+        // proposal list as long as the LDS allows (7 ints per proposal)
+        int huge_list = 0;
+        const int huge_lds = std::min(di.lds_max, 163840) - 1024;
+        if (n_huge > 0 && huge_lds >= conflict_bytes) {
+            huge_list = 64;
+            while (7 * 4 * (2 * huge_list) <= huge_lds) huge_list <<= 1;
+        }
+        const int huge_bytes = std::max(7 * 4 * huge_list, conflict_bytes);
+        if (huge_list && huge_bytes > 65536 &&
+            hipFuncSetAttribute((const void *)k_conflict_huge<D2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                huge_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            huge_list = 0;   // the block-per-net kernel takes them as well
+        }
+        const int huge_on = huge_list > 0 ? 1 : 0;
+        const int g_huge = std::max(1, std::min(n_huge, di.cus * 2));
         if (lds_total < conflict_bytes) {
             st_code = BGPC_E_UNSUPPORTED;
             goto finish;
@@ -608,7 +630,7 @@ int run(const RunArgs &a)
                 LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 0, PCNT(r), sp_none)));
                 if (n_big)
                     k_conflict_big<D2><<<g_big, BIG_BLOCK, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 0,
-                                                                           sp_none);
+                                                                           sp_none, 0);
                 const bool full = r > 0 || resume;
                 if (full) {
                     k_set_max_final<<<1, 64, 0, s>>>(ctrl, -1);
@@ -716,7 +738,10 @@ int run(const RunArgs &a)
                     k_census<D2><<<g_b, nthr, 0, s>>>(g, st, PCNT(r));
                 if (n_big)
                     k_conflict_big<D2><<<g_big, BIG_BLOCK, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 1,
-                                                                           spx);
+                                                                           spx, huge_on);
+                if (huge_on)
+                    k_conflict_huge<D2><<<g_huge, HUGE_BLOCK, huge_bytes, s>>>(g, st, lose, done_net, huge, &shape[3],
+                                                                             ctrl, 1, spx, huge_list);
                 k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1, hw, PH,
                                                       spr ? sp_cnt : nullptr);
                 k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 0, 1, host);

@@ -128,10 +128,11 @@ __global__ void k_init_ctrl(Ctrl *c, int n_w, int max_color)
 }
 
 // Per-graph shape figures: largest net, and a bound on every vertex's
-// distance-2 neighbourhood (sum of the sizes of its nets); big-net list.
+// distance-2 neighbourhood (sum of the sizes of its nets); lists of the nets
+// above SMALL_NET and above HASH_MAX members.
 template <bool D2>
 __global__ void k_net_shape(Graph g, int *max_net, int *big_list, int *n_big, unsigned long long *walk,
-                            int *max_deg)
+                            int *max_deg, int *huge_list, int *n_huge)
 {
     int local = 0, deg = 0;
     unsigned long long w = 0;
@@ -140,6 +141,7 @@ __global__ void k_net_shape(Graph g, int *max_net, int *big_list, int *n_big, un
         local = max(local, sz);
         w += (unsigned long long)sz * (unsigned long long)sz;
         if (sz > SMALL_NET) big_list[atomicAdd(n_big, 1)] = v;
+        if (sz > HASH_MAX) huge_list[atomicAdd(n_huge, 1)] = v;
     }
     for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < g.n_a; u += gridDim.x * blockDim.x)
         deg = max(deg, Acc<D2>::nets_count(g, u));
@@ -1527,10 +1529,112 @@ constexpr int BIG_PER_THREAD = HASH_MAX / BIG_BLOCK;    // members per thread of
 constexpr int BIG_LIST = 2048;   // proposals of a larger net resolved by the hash (3 + 4 ints each in LDS)
 static_assert(3 * BIG_LIST + 2 * (2 * BIG_LIST) <= WIN_COLORS && (BIG_LIST & (BIG_LIST - 1)) == 0 && 2 * (2 * HASH_MAX) <= WIN_COLORS,
               "k_conflict_big's LDS layouts fit its WIN_COLORS-int allocation");
+// Removal in one net larger than HASH_MAX, by the whole block.  One pass
+// (four members per thread in flight) counts the pending members and, when
+// only proposals take part, lists them in LDS; up to list_cap of them (a
+// power of two; 7 ints each) are resolved with an LDS hash color -> lowest
+// holder, otherwise the colors are swept in windows of WIN_COLORS.  sh holds
+// max(7 * list_cap, WIN_COLORS) ints.
+template <bool D2>
+__device__ void conflict_large(const Graph &g, const int *st, uint8_t *lose, uint8_t *done, int v, int sz, long lpos,
+                               int tent_only, const SPState &sp, int *sh, int list_cap, int maxc, int *s_scan,
+                               int *s_cnt)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    int *lst = sh;                      // (position, member, color) per proposal
+    int *hsh = sh + 3 * list_cap;       // hash of the listed proposals
+    if (tid == 0) *s_cnt = 0;
+    __syncthreads();
+    int pending = 0;
+    for (int k0 = tid; k0 < sz; k0 += 4 * nt) {
+        int xs[4], ss[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) xs[i] = k0 + i * nt < sz ? Acc<D2>::member(g, v, k0 + i * nt) : -1;
+#pragma unroll
+        for (int i = 0; i < 4; i++) ss[i] = xs[i] >= 0 ? st[xs[i]] : 0;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            if (xs[i] < 0) continue;
+            const int s = ss[i];
+            pending += (s < 0 || (s & TENT)) ? 1 : 0;
+            if (tent_only && s >= 0 && (s & TENT)) {
+                const int q = atomicAdd(s_cnt, 1);
+                if (q < list_cap) {
+                    lst[3 * q] = k0 + i * nt;
+                    lst[3 * q + 1] = xs[i];
+                    lst[3 * q + 2] = cur_color(s);
+                }
+            }
+        }
+    }
+    pending = block_sum(pending, s_scan);
+    if (sp.lbits && tid == 0) sp.dirty[v] = 0;
+    if (pending == 0) {
+        if (tid == 0) done[v] = 1;
+        return;
+    }
+    const int nl = *s_cnt;
+    if (tent_only && nl <= list_cap) {
+        int cap = 64;
+        while (cap < 2 * nl) cap <<= 1;
+        int *keys = hsh, *minr = hsh + cap;
+        for (int i = tid; i < cap; i += nt) {
+            keys[i] = -1;
+            minr[i] = 0x7fffffff;
+        }
+        __syncthreads();
+        for (int q = tid; q < nl; q += nt) {
+            const int x = lst[3 * q + 1], c = lst[3 * q + 2];
+            unsigned h = hash_color(c) & (cap - 1);
+            for (;;) {
+                int prev = atomicCAS(&keys[h], -1, c);
+                if (prev == -1 || prev == c) {
+                    atomicMin(&minr[h], x);
+                    break;
+                }
+                h = (h + 1) & (cap - 1);
+            }
+        }
+        __syncthreads();
+        for (int q = tid; q < nl; q += nt) {
+            const int k = lst[3 * q], x = lst[3 * q + 1], c = lst[3 * q + 2];
+            unsigned h = hash_color(c) & (cap - 1);
+            while (keys[h] != c) h = (h + 1) & (cap - 1);
+            if (sp.lbits) sp_set(sp, lpos + k, x, minr[h] != x);
+            else if (minr[h] != x) lose[x] = 1;
+        }
+        __syncthreads();
+        return;
+    }
+    for (int base = 0; base <= maxc; base += WIN_COLORS) {
+        for (int i = tid; i < WIN_COLORS; i += nt) sh[i] = 0x7fffffff;
+        __syncthreads();
+        for (int k = tid; k < sz; k += nt) {
+            int x = Acc<D2>::member(g, v, k);
+            int s = st[x];
+            if (tent_only && !(s >= 0 && (s & TENT))) continue;
+            int c = cur_color(s) - base;
+            if (c >= 0 && c < WIN_COLORS) atomicMin(&sh[c], x);
+        }
+        __syncthreads();
+        for (int k = tid; k < sz; k += nt) {
+            int x = Acc<D2>::member(g, v, k);
+            int s = st[x];
+            if (tent_only && !(s >= 0 && (s & TENT))) continue;
+            int c = cur_color(s) - base;
+            if (c >= 0 && c < WIN_COLORS) {
+                if (sp.lbits) sp_set(sp, lpos + k, x, sh[c] != x);
+                else if (sh[c] != x) lose[x] = 1;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <bool D2>
 __global__ void __launch_bounds__(BIG_BLOCK) k_conflict_big(Graph g, const int *st, uint8_t *lose, uint8_t *done,
                                                             const int *big, const int *n_big_p, Ctrl *ctrl,
-                                                            int tent_only, SPState sp)
+                                                            int tent_only, SPState sp, int huge_elsewhere)
 {
     extern __shared__ int sh[];
     __shared__ int s_scan[20], s_cnt;
@@ -1601,92 +1705,30 @@ __global__ void __launch_bounds__(BIG_BLOCK) k_conflict_big(Graph g, const int *
             __syncthreads();
             continue;
         }
-        // larger nets: one pass counts the pending members and, when only
-        // proposals take part, lists them in LDS; few enough of them go
-        // through the hash, else the colors are swept in windows
-        int *lst = sh;                       // (position, member, color) per proposal
-        int *hsh = sh + 3 * BIG_LIST;        // hash of the listed proposals
-        if (tid == 0) s_cnt = 0;
-        __syncthreads();
-        int pending = 0;
-        for (int k = tid; k < sz; k += nt) {
-            const int x = Acc<D2>::member(g, v, k);
-            const int s = st[x];
-            pending += (s < 0 || (s & TENT)) ? 1 : 0;
-            if (tent_only && s >= 0 && (s & TENT)) {
-                const int q = atomicAdd(&s_cnt, 1);
-                if (q < BIG_LIST) {
-                    lst[3 * q] = k;
-                    lst[3 * q + 1] = x;
-                    lst[3 * q + 2] = cur_color(s);
-                }
-            }
-        }
-        pending = block_sum(pending, s_scan);
-        if (sp.lbits && tid == 0) sp.dirty[v] = 0;
-        if (pending == 0) {
-            if (tid == 0) done[v] = 1;
-            continue;
-        }
-        const int nl = s_cnt;
-        if (tent_only && nl <= BIG_LIST) {
-            int cap = 64;
-            while (cap < 2 * nl) cap <<= 1;
-            int *keys = hsh, *minr = hsh + cap;
-            for (int i = tid; i < cap; i += nt) {
-                keys[i] = -1;
-                minr[i] = 0x7fffffff;
-            }
-            __syncthreads();
-            for (int q = tid; q < nl; q += nt) {
-                const int x = lst[3 * q + 1], c = lst[3 * q + 2];
-                unsigned h = hash_color(c) & (cap - 1);
-                for (;;) {
-                    int prev = atomicCAS(&keys[h], -1, c);
-                    if (prev == -1 || prev == c) {
-                        atomicMin(&minr[h], x);
-                        break;
-                    }
-                    h = (h + 1) & (cap - 1);
-                }
-            }
-            __syncthreads();
-            for (int q = tid; q < nl; q += nt) {
-                const int k = lst[3 * q], x = lst[3 * q + 1], c = lst[3 * q + 2];
-                unsigned h = hash_color(c) & (cap - 1);
-                while (keys[h] != c) h = (h + 1) & (cap - 1);
-                if (sp.lbits) sp_set(sp, lpos + k, x, minr[h] != x);
-                else if (minr[h] != x) lose[x] = 1;
-            }
-            __syncthreads();
-            continue;
-        }
-        {
-            int maxc = ctrl->max_color;
-            for (int base = 0; base <= maxc; base += WIN_COLORS) {
-                for (int i = tid; i < WIN_COLORS; i += nt) sh[i] = 0x7fffffff;
-                __syncthreads();
-                for (int k = tid; k < sz; k += nt) {
-                    int x = Acc<D2>::member(g, v, k);
-                    int s = st[x];
-                    if (tent_only && !(s >= 0 && (s & TENT))) continue;
-                    int c = cur_color(s) - base;
-                    if (c >= 0 && c < WIN_COLORS) atomicMin(&sh[c], x);
-                }
-                __syncthreads();
-                for (int k = tid; k < sz; k += nt) {
-                    int x = Acc<D2>::member(g, v, k);
-                    int s = st[x];
-                    if (tent_only && !(s >= 0 && (s & TENT))) continue;
-                    int c = cur_color(s) - base;
-                    if (c >= 0 && c < WIN_COLORS) {
-                        if (sp.lbits) sp_set(sp, lpos + k, x, sh[c] != x);
-                        else if (sh[c] != x) lose[x] = 1;
-                    }
-                }
-                __syncthreads();
-            }
-        }
+        if (huge_elsewhere && sz > HASH_MAX) continue;   // k_conflict_huge
+        conflict_large<D2>(g, st, lose, done, v, sz, lpos, tent_only, sp, sh, BIG_LIST, ctrl->max_color, s_scan,
+                           &s_cnt);
+    }
+}
+
+// Nets larger than HASH_MAX (their own list, built with the shape figures)
+// in vertex-based rounds: a block of HUGE_BLOCK threads per net with a
+// proposal list as large as the LDS holds.
+constexpr int HUGE_BLOCK = 1024;
+template <bool D2>
+__global__ void __launch_bounds__(HUGE_BLOCK) k_conflict_huge(Graph g, const int *st, uint8_t *lose, uint8_t *done,
+                                                              const int *huge, const int *n_huge_p, Ctrl *ctrl,
+                                                              int tent_only, SPState sp, int list_cap)
+{
+    extern __shared__ int sh[];
+    __shared__ int s_scan[20], s_cnt;
+    const int n_huge = *n_huge_p;
+    for (int hi = blockIdx.x; hi < n_huge; hi += gridDim.x) {
+        const int v = huge[hi];
+        if (done[v] || (sp.lbits && !sp.dirty[v])) continue;
+        const long lpos = sp.lbits ? sp_lpos<D2>(g, v) : 0;
+        conflict_large<D2>(g, st, lose, done, v, Acc<D2>::size(g, v), lpos, tent_only, sp, sh, list_cap,
+                           ctrl->max_color, s_scan, &s_cnt);
     }
 }
 

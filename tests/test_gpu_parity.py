@@ -162,6 +162,23 @@ def test_skewed_small(cuda):
         _compare_full(res, colors, ref)
 
 
+def test_d2gc_hubs(cuda):
+    """Two hubs whose closed neighbourhoods exceed 4,096 members: removal in
+    those nets lists the proposals in LDS, or sweeps color windows when there
+    are too many of them."""
+    rng = np.random.Generator(np.random.PCG64(8))
+    n = 8000
+    edges = [(0, i) for i in range(1, 5001)] + [(n - 1, i) for i in range(2000, n - 1)]
+    e = rng.integers(1, n, size=(20000, 2))
+    edges += [(int(a), int(b)) for a, b in e if a != b]
+    adj = synth.adjacency_from_edges(n, edges)
+    assert int((np.diff(adj.off) + 1 > 4096).sum()) == 2
+    for kw in (dict(net_color_mask=1), dict(net_color_mask=0b11), dict(), dict(policy=1, net_color_mask=1)):
+        ref = oracle.d2gc(adj, log_cap=8192, **kw)
+        res, colors = _gpu_d2(cuda, adj, log_cap=8192, **kw)
+        _compare_full(res, colors, ref)
+
+
 @pytest.mark.parametrize("mask", [0, 1, 0b10, 0b11])
 def test_d2gc_rmat_small(cuda, mask):
     adj = synth.rmat(11, 8, 0.57, 0.19, 0.19, seed=9)
