@@ -395,6 +395,31 @@ __device__ int block_find_free_down(const uint32_t *bits, int cap_bits, int from
 // ---------------------------------------------------------------------------
 // vertex-based coloring, first-fit
 
+constexpr int COOP_NETS = 256;   // rows longer than this are ORed by the whole wave
+
+// OR of mask0 over the d nets in row[0..d), by the whole wave (eight loads in
+// flight per lane); every lane gets the result.
+__device__ uint64_t wave_row_or(const int *row, int d, const uint64_t *mask0)
+{
+    const int lane = lane_id();
+    uint64_t m = 0;
+    for (int k0 = 0; k0 < d; k0 += 8 * WAVE) {
+        int nets[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const int k = k0 + q * WAVE + lane;
+            nets[q] = k < d ? row[k] : -1;
+        }
+        uint64_t mm[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) mm[q] = nets[q] >= 0 ? mask0[nets[q]] : 0ull;
+#pragma unroll
+        for (int q = 0; q < 8; q++) m |= mm[q];
+    }
+    for (int o = WAVE / 2; o > 0; o >>= 1) m |= shfl64(m, lane ^ o);
+    return m;
+}
+
 // One wave per 64 worklist entries: F(w) restricted to colors 0..63 is the OR
 // of the masks of w's nets.  The wave first copies the 64 rows of nets(w)
 // into LDS as one flat range (coalesced index loads, four in flight per
@@ -489,17 +514,26 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
                 for (int q = 0; q < 16; q++) m |= mm[q];
             }
         } else {
-            for (int k0 = 0; k0 < d; k0 += 8) {
+            // rows read in place; rows longer than COOP_NETS are ORed by the
+            // whole wave afterwards
+            const int dl = d > COOP_NETS ? 0 : d;
+            for (int k0 = 0; k0 < dl; k0 += 8) {
                 int nets[8];
 #pragma unroll
-                for (int q = 0; q < 8; q++) nets[q] = (k0 + q < d) ? g.a_idx[beg + k0 + q] : -1;
+                for (int q = 0; q < 8; q++) nets[q] = (k0 + q < dl) ? g.a_idx[beg + k0 + q] : -1;
                 uint64_t mm[8];
 #pragma unroll
                 for (int q = 0; q < 8; q++) mm[q] = nets[q] >= 0 ? mask0[nets[q]] : 0ull;
 #pragma unroll
                 for (int q = 0; q < 8; q++) m |= mm[q];
             }
+            for (uint64_t bal = __ballot(d > COOP_NETS); bal; bal &= bal - 1) {
+                const int j = __builtin_ctzll(bal);
+                const uint64_t acc = wave_row_or(g.a_idx + __shfl(beg, j), __shfl(d, j), mask0);
+                if (lane == j) m |= acc;
+            }
         }
+        bool coop_mark = false;   // a long row's nets re-opened by the whole wave
         if (w >= 0) {
             int col = -1;
             if (~m) {
@@ -520,6 +554,9 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
                     if (staged) {
                         if (D2) dirty[w] = 1;
                         for (int k = 0; k < d; k++) dirty[s_idx[sofs + k]] = 1;
+                    } else if (d > COOP_NETS) {
+                        if (D2) dirty[w] = 1;
+                        coop_mark = true;
                     } else {
                         mark_nets_dirty<D2>(g, w, dirty, 0, 1);
                     }
@@ -528,6 +565,11 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
             } else {
                 heavy[atomicAdd(&ctrl->n_heavy, 1)] = w;
             }
+        }
+        for (uint64_t bal = __ballot(coop_mark); bal; bal &= bal - 1) {
+            const int j = __builtin_ctzll(bal);
+            const int bj = __shfl(beg, j), dj = __shfl(d, j);
+            for (int k = lane; k < dj; k += WAVE) dirty[g.a_idx[bj + k]] = 1;
         }
         __syncthreads();
     }
@@ -560,11 +602,22 @@ __global__ void k_vcolor_wide(Graph g, const int *heavy, Ctrl *ctrl, int *st, in
             const int from = max(64, ffc ? ffc[w] : 0);
             for (int p0 = (from >> 6) - 1; p0 < PH && col < 0; p0 += 8) {
                 unsigned long long acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                for (int k = tid; k < nn; k += nt) {
-                    const uint64_t *row = hw + (long)Acc<D2>::net_at(g, w, k) * PH;
+                // four nets per thread per step: their ids, then their 32 words, in flight
+                for (int k0 = tid; k0 < nn; k0 += 4 * nt) {
+                    int vs[4];
 #pragma unroll
-                    for (int q = 0; q < 8; q++)
-                        if (p0 + q < PH) acc[q] |= row[p0 + q];
+                    for (int i = 0; i < 4; i++) vs[i] = k0 + i * nt < nn ? Acc<D2>::net_at(g, w, k0 + i * nt) : -1;
+                    unsigned long long x[4][8];
+#pragma unroll
+                    for (int i = 0; i < 4; i++) {
+                        const uint64_t *row = hw + (long)(vs[i] < 0 ? 0 : vs[i]) * PH;
+#pragma unroll
+                        for (int q = 0; q < 8; q++) x[i][q] = (vs[i] >= 0 && p0 + q < PH) ? row[p0 + q] : 0ull;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; i++)
+#pragma unroll
+                        for (int q = 0; q < 8; q++) acc[q] |= x[i][q];
                 }
 #pragma unroll
                 for (int q = 0; q < 8; q++) {
