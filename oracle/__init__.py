@@ -238,3 +238,31 @@ def color_stats(colors) -> dict:
     return {"n_distinct": int(oi[0]), "max_color": int(oi[1]), "card_min": int(oi[2]),
             "card_max": int(oi[3]), "n_empty_below_max": int(oi[4]),
             "card_mean": float(od[0]), "card_std": float(od[1])}
+
+
+def order_largest_first(g) -> np.ndarray:
+    """Largest-first processing order of a bipartite graph: vertices by
+    decreasing key(u) = sum over the nets v of u of (|vtxs(v)| - 1), an upper
+    bound of u's distance-2 degree, ties by increasing id.  The paper's
+    experiments compare processing orders (Section VI: natural and
+    smallest-last); this degree order is the cheap one.  Returns order[k] =
+    the vertex of rank k."""
+    n_a = int(g.n_a)
+    a_off = np.asarray(g.a_off, dtype=np.int64)
+    sizes = np.diff(np.asarray(g.b_off, dtype=np.int64))
+    key = np.zeros(n_a, dtype=np.int64)
+    owner = np.repeat(np.arange(n_a), np.diff(a_off))   # vertex of each (vertex, net) incidence
+    np.add.at(key, owner, sizes[np.asarray(g.a_idx, dtype=np.int64)] - 1)
+    return np.lexsort((np.arange(n_a), -key)).astype(np.int32)
+
+
+def d2gc_order_largest_first(adj) -> np.ndarray:
+    """The same order for distance-2 coloring: the nets are the closed
+    neighbourhoods N[x], so key(u) = sum over x in N[u] of |nbor(x)|."""
+    n = int(adj.n)
+    off = np.asarray(adj.off, dtype=np.int64)
+    deg = np.diff(off)
+    key = deg.copy()   # x = u itself
+    owner = np.repeat(np.arange(n), deg)
+    np.add.at(key, owner, deg[np.asarray(adj.idx, dtype=np.int64)])
+    return np.lexsort((np.arange(n), -key)).astype(np.int32)

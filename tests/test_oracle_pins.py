@@ -362,3 +362,51 @@ def test_first_fit_neighbour_list_form_equals_literal_gather():
         assert np.array_equal(a.colors, b.colors) and a.rounds == b.rounds
         assert np.array_equal(a.log["w"], b.log["w"])
         assert a.rounds == g.n_a or len(np.unique(a.colors)) < g.n_a
+
+
+def test_largest_first_worked_example():
+    """E1 (nets {0,1,2}, {1,3}, {2,3,4}, {0,4}): keys by hand are
+    u0: 2 + 1, u1: 2 + 1, u2: 2 + 2, u3: 1 + 2, u4: 2 + 1 -> order 2, 0, 1, 3, 4."""
+    g = synth.from_nets(5, [[0, 1, 2], [1, 3], [2, 3, 4], [0, 4]])
+    assert oracle.order_largest_first(g).tolist() == [2, 0, 1, 3, 4]
+    # single net of k: all keys k - 1, ties by id -> the natural order
+    assert oracle.order_largest_first(synth.from_nets(6, [list(range(6))])).tolist() == list(range(6))
+
+
+def _pair_count_key(g):
+    """Number of (net, other member) pairs of each vertex, enumerated member
+    by member from the net lists."""
+    key = [0] * g.n_a
+    for v in range(g.n_b):
+        members = g.b_idx[g.b_off[v]:g.b_off[v + 1]].tolist()
+        for u in members:
+            key[u] += sum(1 for x in members if x != u)
+    return key
+
+
+@pytest.mark.parametrize("seed", [51, 52])
+def test_largest_first_sorted_by_pair_count(seed):
+    g = synth.random_uniform(400, 300, 1, 9, seed)
+    order = oracle.order_largest_first(g)
+    assert sorted(order.tolist()) == list(range(g.n_a))
+    key = _pair_count_key(g)
+    for a, b in zip(order[:-1], order[1:]):
+        assert key[a] > key[b] or (key[a] == key[b] and a < b)
+    # the key bounds the distance-2 degree from above
+    rows = np.repeat(np.arange(g.n_b), np.diff(g.b_off))
+    M = sp.csr_matrix((np.ones(g.nnz), (rows, g.b_idx)), shape=(g.n_b, g.n_a))
+    C = (M.T @ M).tocsr()
+    C.setdiag(0)
+    C.eliminate_zeros()
+    assert all(np.diff(C.indptr)[u] <= key[u] for u in range(g.n_a))
+
+
+def test_d2gc_largest_first_sorted_by_two_hop_walks():
+    adj = synth.rmat(8, 4, 0.57, 0.19, 0.19, seed=12)
+    n = adj.n
+    nbrs = [adj.idx[adj.off[u]:adj.off[u + 1]].tolist() for u in range(n)]
+    key = [len(nbrs[u]) + sum(len(nbrs[x]) for x in nbrs[u]) for u in range(n)]
+    order = oracle.d2gc_order_largest_first(adj)
+    assert sorted(order.tolist()) == list(range(n))
+    for a, b in zip(order[:-1], order[1:]):
+        assert key[a] > key[b] or (key[a] == key[b] and a < b)
