@@ -182,6 +182,27 @@ BGPC_API int d2gc_color(const bgpc_csr *adj, const int32_t *order, const bgpc_op
                         int32_t *colors_out);
 
 /*
+ * Largest-first processing order (the paper's experiments compare processing
+ * orders, Section VI; this is the cheap degree-based one, computed on the
+ * device): vertices by decreasing key(u) = sum over the nets v of u of
+ * (|vtxs(v)| - 1) -- the number of (net, other member) pairs of u, an upper
+ * bound of its distance-2 degree -- ties by increasing id.  For distance-2
+ * coloring the nets are the closed neighbourhoods: key(u) = sum over x in
+ * N[u] of |nbor(x)|.
+ *   csr_A, csr_B / adj  as for bgpc_color / d2gc_color (trusted: no
+ *                       validation beyond the sizes)
+ *   stream              hipStream_t or NULL; the call returns once the order
+ *                       is complete
+ *   order_out           device int32[|V_A|] (resp. [n]), written with the
+ *                       vertex of each rank; pass it as `order` above
+ * Allocates its own workspace (two uint64 and one int32 per vertex plus the
+ * sort's scratch).  BGPC_E_INVALID for inconsistent sizes or a NULL output.
+ */
+BGPC_API int bgpc_order_largest_first(const bgpc_csr *csr_A, const bgpc_csr *csr_B, void *stream,
+                                      int32_t *order_out);
+BGPC_API int d2gc_order_largest_first(const bgpc_csr *adj, void *stream, int32_t *order_out);
+
+/*
  * Color-set statistics of a coloring (the metrics of the balancing
  * experiments, Section VI): non-empty color sets, largest color, min / max /
  * mean / population standard deviation of the non-empty set cardinalities,

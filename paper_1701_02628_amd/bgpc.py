@@ -106,6 +106,10 @@ def load():
         lib.bgpc_session_poll.restype = ctypes.c_int
         lib.bgpc_session_destroy.argtypes = [ctypes.c_void_p]
         lib.bgpc_session_destroy.restype = None
+        lib.bgpc_order_largest_first.argtypes = [ctypes.POINTER(Csr), ctypes.POINTER(Csr), P, P]
+        lib.bgpc_order_largest_first.restype = ctypes.c_int
+        lib.d2gc_order_largest_first.argtypes = [ctypes.POINTER(Csr), P, P]
+        lib.d2gc_order_largest_first.restype = ctypes.c_int
         lib.bgpc_status_string.argtypes = [ctypes.c_int]
         lib.bgpc_status_string.restype = ctypes.c_char_p
         _lib = lib
@@ -114,7 +118,7 @@ def load():
 
 EXPORTED = ("bgpc_opts_default", "bgpc_color", "d2gc_color", "color_stats", "bgpc_status_string",
             "bgpc_color_batch", "bgpc_session_create", "bgpc_session_submit", "bgpc_session_poll",
-            "bgpc_session_destroy")
+            "bgpc_session_destroy", "bgpc_order_largest_first", "d2gc_order_largest_first")
 
 
 def status_string(code: int) -> str:
@@ -240,6 +244,32 @@ def d2gc_color(adj: DeviceCsr, order, colors_out, net_color_mask=0, policy=FIRST
     st = lib.d2gc_color(ctypes.byref(a), order_p, ctypes.byref(o), _dev_ptr(colors_out, "colors_out"))
     del keep
     return _finish(st, rounds, log_arrays, o)
+
+
+def order_largest_first(csr_A: DeviceCsr, csr_B: DeviceCsr, stream=None):
+    """Largest-first order of V_A as an int32 GPU tensor (order[k] = vertex of rank k)."""
+    import torch
+    lib = load()
+    out = torch.empty(max(csr_A.n_rows, 1), dtype=torch.int32, device=csr_A.offsets.device)[:csr_A.n_rows]
+    a, b = csr_A.as_struct(), csr_B.as_struct()
+    st = lib.bgpc_order_largest_first(ctypes.byref(a), ctypes.byref(b), _stream_handle(stream),
+                                      _dev_ptr(out, "order_out") if csr_A.n_rows else None)
+    if st != OK:
+        raise RuntimeError(f"bgpc_order_largest_first failed: {status_string(st)}")
+    return out
+
+
+def d2gc_order_largest_first(adj: DeviceCsr, stream=None):
+    """Largest-first order of a symmetric graph's vertices (closed neighbourhoods as nets)."""
+    import torch
+    lib = load()
+    out = torch.empty(max(adj.n_rows, 1), dtype=torch.int32, device=adj.offsets.device)[:adj.n_rows]
+    a = adj.as_struct()
+    st = lib.d2gc_order_largest_first(ctypes.byref(a), _stream_handle(stream),
+                                      _dev_ptr(out, "order_out") if adj.n_rows else None)
+    if st != OK:
+        raise RuntimeError(f"d2gc_order_largest_first failed: {status_string(st)}")
+    return out
 
 
 def color_stats(colors, stream=None) -> dict:

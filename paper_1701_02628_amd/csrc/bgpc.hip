@@ -7,6 +7,7 @@
 // keeps at most LOOKAHEAD rounds queued beyond what it has seen completed and
 // stops queueing as soon as it sees an empty worklist.
 #include <hip/hip_runtime.h>
+#include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
 #include <rocprim/device/device_segmented_radix_sort.hpp>
 
@@ -961,6 +962,25 @@ __global__ void k_gather_i32(const int *in, const int *perm, int n, int *out)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = in[perm[i]];
 }
 
+// ---- largest-first orders: key(u) = sum over the nets of u of (size - 1),
+// one wave per vertex (lanes over its nets); ids for the stable sort
+template <bool D2>
+__global__ void k_order_key(Graph g, unsigned long long *key, int *ids)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, nwv = gridDim.x * blockDim.x / WAVE;
+    for (int u = wid; u < g.n_a; u += nwv) {
+        const int nn = Acc<D2>::nets_count(g, u);
+        unsigned long long s = 0;
+        for (int k = lane; k < nn; k += WAVE) s += (unsigned long long)(Acc<D2>::size(g, Acc<D2>::net_at(g, u, k)) - 1);
+        for (int d = WAVE / 2; d > 0; d >>= 1) s += (unsigned long long)__shfl_xor((long long)s, d);
+        if (lane == 0) {
+            key[u] = s;
+            ids[u] = u;
+        }
+    }
+}
+
 }  // namespace
 
 namespace bgpc {
@@ -1059,6 +1079,39 @@ int run_ordered(const RunArgs &a, const int32_t *order)
     return rc;
 }
 
+// Vertices by decreasing key, ties by increasing id (the radix sort is stable
+// and the ids enter in increasing order).
+int order_largest_first(const Graph &g, bool d2, hipStream_t s, int32_t *order_out)
+{
+    const int n = g.n_a;
+    if (n == 0) return BGPC_OK;
+    const DevInfo di = dev_info();
+    size_t sort_bytes = 0;
+    if (rocprim::radix_sort_pairs_desc(nullptr, sort_bytes, (const unsigned long long *)nullptr,
+                                       (unsigned long long *)nullptr, (const int *)nullptr, (int *)nullptr,
+                                       (size_t)n, 0u, 64u, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return BGPC_E_HIP;
+    }
+    Arena ar;
+    int rc = ar.reserve(aligned(n, 8) * 2 + aligned(n, 4) + aligned(sort_bytes, 1), s);
+    if (rc != BGPC_OK) return rc;
+    unsigned long long *key = ar.take<unsigned long long>(n);
+    unsigned long long *key_sorted = ar.take<unsigned long long>(n);
+    int *ids = ar.take<int>(n);
+    void *tmp = ar.take<char>(sort_bytes);
+    const int blocks = grid_for((long)n * WAVE, 256, di.cus * 16);
+    if (d2) k_order_key<true><<<blocks, 256, 0, s>>>(g, key, ids);
+    else k_order_key<false><<<blocks, 256, 0, s>>>(g, key, ids);
+    bool ok = hipGetLastError() == hipSuccess &&
+              rocprim::radix_sort_pairs_desc(tmp, sort_bytes, (const unsigned long long *)key, key_sorted,
+                                             (const int *)ids, order_out, (size_t)n, 0u, 64u, s) == hipSuccess;
+    if (!ok) (void)hipGetLastError();
+    ar.release();
+    if (hipStreamSynchronize(s) != hipSuccess) ok = false;
+    return ok ? BGPC_OK : BGPC_E_HIP;
+}
+
 }  // namespace bgpc
 
 namespace bgpc {
@@ -1132,6 +1185,23 @@ BGPC_API int d2gc_color(const bgpc_csr *adj, const int32_t *order, const bgpc_op
     a.st = colors_out;
     a.s = s;
     return order ? run_ordered(a, order) : run<true>(a);
+}
+
+BGPC_API int bgpc_order_largest_first(const bgpc_csr *csr_A, const bgpc_csr *csr_B, void *stream,
+                                      int32_t *order_out)
+{
+    if (!csr_ok(csr_A) || !csr_ok(csr_B) || (csr_A->n_rows > 0 && !order_out)) return BGPC_E_INVALID;
+    if (csr_A->n_rows != csr_B->n_cols || csr_A->n_cols != csr_B->n_rows || csr_A->nnz != csr_B->nnz)
+        return BGPC_E_INVALID;
+    const Graph g{csr_A->n_rows, csr_B->n_rows, csr_A->offsets, csr_A->indices, csr_B->offsets, csr_B->indices};
+    return order_largest_first(g, false, (hipStream_t)stream, order_out);
+}
+
+BGPC_API int d2gc_order_largest_first(const bgpc_csr *adj, void *stream, int32_t *order_out)
+{
+    if (!csr_ok(adj) || adj->n_rows != adj->n_cols || (adj->n_rows > 0 && !order_out)) return BGPC_E_INVALID;
+    const Graph g{adj->n_rows, adj->n_rows, adj->offsets, adj->indices, adj->offsets, adj->indices};
+    return order_largest_first(g, true, (hipStream_t)stream, order_out);
 }
 
 BGPC_API int color_stats(const int32_t *colors, int64_t n, void *stream, bgpc_stats *out)

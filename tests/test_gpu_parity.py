@@ -426,3 +426,25 @@ def test_caller_order_edge_cases(cuda):
             ref = oracle.bgpc(g, net_color_mask=mask, order=perm)
             res, colors = _gpu_bgpc(cuda, g, net_color_mask=mask, order=perm)
             _compare_full(res, colors, ref)
+
+
+def test_largest_first_orders(cuda):
+    """Device largest-first orders equal the oracle's, and coloring under them
+    matches the oracle's run under the same order."""
+    cases = [synth.random_uniform(5003, 4001, 2, 8, 11), synth.skewed(6000, 6000, seed=23, kmax=600, name="sk6k"),
+             synth.stencil27(12), synth.from_nets(7, []), synth.from_nets(5, [[0, 1, 2], [1, 3], [2, 3, 4], [0, 4]])]
+    for g in cases:
+        A, B = bgpc.upload_bipartite(g)
+        got = bgpc.order_largest_first(A, B)
+        ref = oracle.order_largest_first(g)
+        assert np.array_equal(got.cpu().numpy(), ref)
+        for kw in (dict(), dict(net_color_mask=1)):
+            res, colors = _gpu_bgpc(cuda, g, (A, B), order=ref, **kw)
+            _compare_full(res, colors, oracle.bgpc(g, order=ref, **kw))
+    adj = synth.rmat(11, 8, 0.57, 0.19, 0.19, seed=9)
+    D = bgpc.upload_adjacency(adj)
+    got = bgpc.d2gc_order_largest_first(D)
+    ref = oracle.d2gc_order_largest_first(adj)
+    assert np.array_equal(got.cpu().numpy(), ref)
+    res, colors = _gpu_d2(cuda, adj, D, order=ref, net_color_mask=1)
+    _compare_full(res, colors, oracle.d2gc(adj, order=ref, net_color_mask=1))
