@@ -448,3 +448,13 @@ def test_largest_first_orders(cuda):
     assert np.array_equal(got.cpu().numpy(), ref)
     res, colors = _gpu_d2(cuda, adj, D, order=ref, net_color_mask=1)
     _compare_full(res, colors, oracle.d2gc(adj, order=ref, net_color_mask=1))
+
+
+def test_net_round_size_limit(cuda):
+    """A net-based round needs the largest net's bitmap in LDS: a net of
+    230,000 members is past that limit and the call says so before any round."""
+    g = synth.from_nets(230000, [list(range(230000))])
+    res, _ = _gpu_bgpc(cuda, g, net_color_mask=1)
+    assert res.status == bgpc.E_UNSUPPORTED and res.rounds == 0
+    res, colors = _gpu_bgpc(cuda, g, net_color_mask=1 << 5)   # a net-based round later on: refused up front
+    assert res.status == bgpc.E_UNSUPPORTED and res.rounds == 0
