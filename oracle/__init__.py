@@ -23,7 +23,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 
 OK, E_INVALID, E_NOT_CONVERGED, E_INTERNAL = 0, -1, -6, -8
-FIRST_FIT, B1, B2 = 0, 1, 2
+FIRST_FIT, B1, B2, B1_GLOBAL = 0, 1, 2, 3
 
 
 def build(verbose: bool = False) -> str:

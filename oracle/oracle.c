@@ -38,7 +38,7 @@
 #include <omp.h>
 
 enum { OR_OK = 0, OR_E_INVALID = -1, OR_E_NOT_CONVERGED = -6, OR_E_INTERNAL = -8 };
-enum { POL_FF = 0, POL_B1 = 1, POL_B2 = 2 };
+enum { POL_FF = 0, POL_B1 = 1, POL_B2 = 2, POL_B1G = 3 };
 
 typedef struct {
     int32_t n_a, n_b, d2;
@@ -108,11 +108,14 @@ static void fset_add(fset_t *f, int64_t col) { f->mark[col] = f->cur; }
 typedef struct { int64_t col_max, col_next; } chunk_state_t;
 
 /* The color policies.  First-fit: Algorithm 2's closing search.
- * B1: Algorithm 11.  B2: Algorithm 12 (col_max / 3 is an integer floor). */
+ * B1: Algorithm 11.  B2: Algorithm 12 (col_max / 3 is an integer floor).
+ * B1G: Algorithm 11's choice with col_max fixed for the whole round to the
+ * largest color of the round's snapshot (no state carried between vertices;
+ * -1 when nothing is colored yet). */
 static int64_t policy_pick(int policy, const fset_t *F, chunk_state_t *st, int32_t rank)
 {
     int64_t col;
-    if (policy == POL_B1) {
+    if (policy == POL_B1 || policy == POL_B1G) {
         if (rank % 2 == 0) {
             col = st->col_max;
             while (col >= 0 && fset_has(F, col)) col--;
@@ -124,7 +127,7 @@ static int64_t policy_pick(int policy, const fset_t *F, chunk_state_t *st, int32
             col = 0;
             while (fset_has(F, col)) col++;
         }
-        if (col > st->col_max) st->col_max = col;
+        if (policy == POL_B1 && col > st->col_max) st->col_max = col;
     } else if (policy == POL_B2) {
         col = st->col_next;
         while (fset_has(F, col)) col++;
@@ -183,6 +186,9 @@ static int color_vertex_round(const graph_t *g, const int32_t *s, int32_t *t,
 {
     int err = 0;
     int64_t nchunks = (nw + chunk - 1) / chunk;
+    int64_t snap_max = -1;   /* largest color of the snapshot (B1G) */
+    for (int32_t x = 0; x < g->n_a; x++)
+        if (s[x] > snap_max) snap_max = s[x];
     #pragma omp parallel reduction(| : err)
     {
         fset_t F;
@@ -191,7 +197,7 @@ static int color_vertex_round(const graph_t *g, const int32_t *s, int32_t *t,
         } else {
             #pragma omp for schedule(dynamic, 1)
             for (int64_t ch = 0; ch < nchunks; ch++) {
-                chunk_state_t st = {0, 0};
+                chunk_state_t st = {policy == POL_B1G ? snap_max : 0, 0};
                 int64_t lo = ch * chunk, hi = lo + chunk < nw ? lo + chunk : nw;
                 for (int64_t i = lo; i < hi; i++) {
                     int32_t w = W[i];
@@ -524,7 +530,7 @@ int oracle_color(int32_t n_a, int32_t n_b,
                  int32_t log_cap, int32_t *log_mode, int64_t *log_w, int64_t *log_losers,
                  int64_t *log_evicted, int32_t *log_maxc)
 {
-    if (n_a < 0 || n_b < 0 || chunk <= 0 || policy < 0 || policy > 2) return OR_E_INVALID;
+    if (n_a < 0 || n_b < 0 || chunk <= 0 || policy < 0 || policy > 3) return OR_E_INVALID;
     if (d2 && n_a != n_b) return OR_E_INVALID;
     graph_t g = {n_a, n_b, d2, a_off, a_idx, b_off, b_idx};
     if (max_rounds <= 0) max_rounds = n_a + 65;

@@ -410,3 +410,35 @@ def test_d2gc_largest_first_sorted_by_two_hop_walks():
     assert sorted(order.tolist()) == list(range(n))
     for a, b in zip(order[:-1], order[1:]):
         assert key[a] > key[b] or (key[a] == key[b] and a < b)
+
+
+def test_b1_global_worked_examples():
+    """B1 with col_max fixed per round to the snapshot's largest color, by hand.
+    E1: round 0 nothing is colored (col_max = -1, every vertex takes 0); round
+    1 (col_max 0): 1 odd -> 1, 2 even -> 0 taken -> 1, 3 -> 0, 4 even -> 1,
+    then 2 and 4 lose to 1; round 2 (col_max 1): 2 -> 2, 4 even -> 1 free."""
+    g = synth.from_nets(5, [[0, 1, 2], [1, 3], [2, 3, 4], [0, 4]])
+    states = [[0, -1, -1, -1, -1], [0, 1, -1, 0, -1], [0, 1, 2, 0, 1]]
+    for k, expect in enumerate(states, start=1):
+        assert oracle.bgpc(g, policy=oracle.B1_GLOBAL, max_rounds=k).colors.tolist() == expect
+    # nets {0,1}, {1,2}: in round 1 vertex 2 (even, nothing colored around it)
+    # takes col_max = 0 and keeps it; B1's chunk state (col_max 1 after vertex
+    # 1) makes 2 propose 1 and lose once more
+    h = synth.from_nets(5, [[0, 1], [1, 2]])
+    r = oracle.bgpc(h, policy=oracle.B1_GLOBAL)
+    assert (r.rounds, r.colors.tolist()) == (2, [0, 1, 0, 0, 0])
+    assert oracle.bgpc(h, policy=oracle.B1).rounds == 3
+
+
+def test_b1_global_is_stateless():
+    """No state flows between vertices: the chunk size cannot matter."""
+    g = synth.random_uniform(3000, 2500, 2, 12, 61)
+    ref = oracle.bgpc(g, policy=oracle.B1_GLOBAL, chunk=1)
+    for chunk in (7, 64, 5000):
+        r = oracle.bgpc(g, policy=oracle.B1_GLOBAL, chunk=chunk)
+        assert np.array_equal(r.colors, ref.colors) and r.rounds == ref.rounds
+    assert oracle.violations(g, ref.colors) == 0
+    assert not np.array_equal(oracle.bgpc(g, policy=oracle.B1).colors, ref.colors)
+    adj = synth.rmat(8, 4, 0.57, 0.19, 0.19, seed=12)
+    r = oracle.d2gc(adj, policy=oracle.B1_GLOBAL, net_color_mask=1)
+    assert r.status == 0 and oracle.violations(adj, r.colors) == 0
