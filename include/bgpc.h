@@ -82,7 +82,10 @@ typedef struct {
 enum {
     BGPC_FIRST_FIT = 0,   /* Algorithm 2: smallest color not forbidden */
     BGPC_B1 = 1,          /* Algorithm 11: alternate reverse / forward search around col_max */
-    BGPC_B2 = 2           /* Algorithm 12: forward search from col_next, capped at col_max / 3 + 1 */
+    BGPC_B2 = 2,          /* Algorithm 12: forward search from col_next, capped at col_max / 3 + 1 */
+    BGPC_B1_GLOBAL = 3    /* Algorithm 11's choice with col_max fixed for the whole round to the
+                             largest color of the round's snapshot (-1 before any color): no state
+                             passes between vertices, so `chunk` does not matter */
 };
 
 /* opts->flags */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libbgpc.so")
 OK = 0
 E_INVALID, E_UNSORTED, E_NOT_TRANSPOSE, E_NOT_SYMMETRIC = -1, -2, -3, -4
 E_OOM, E_NOT_CONVERGED, E_HIP, E_UNSUPPORTED, E_INTERNAL = -5, -6, -7, -8, -9
-FIRST_FIT, B1, B2 = 0, 1, 2
+FIRST_FIT, B1, B2, B1_GLOBAL = 0, 1, 2, 3
 STRICT, RESUME = 1, 2
 
 

@@ -905,7 +905,7 @@ bool csr_ok(const bgpc_csr *c)
 
 bool opts_ok(const bgpc_opts &o)
 {
-    return o.policy >= 0 && o.policy <= 2 && o.chunk >= 1 && o.max_rounds >= 0 && o.start_round >= 0;
+    return o.policy >= 0 && o.policy <= BGPC_B1_GLOBAL && o.chunk >= 1 && o.max_rounds >= 0 && o.start_round >= 0;
 }
 
 }  // namespace

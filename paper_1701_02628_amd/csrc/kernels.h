@@ -692,7 +692,7 @@ __device__ __forceinline__ uint64_t bits_upto(int a)  // bits 0..a
 __device__ __forceinline__ bool pick_low(int policy, uint64_t m, int rank, const PolicyState &s, int *col)
 {
     uint64_t fr = ~m;
-    if (policy == 1 && (rank & 1) == 0) {  // B1, even rank
+    if ((policy == 1 || policy == 3) && (rank & 1) == 0) {  // B1 (B1G: col_max fixed), even rank
         if (s.col_max > 63) return false;
         uint64_t low = fr & bits_upto(s.col_max);
         if (low) {
@@ -724,7 +724,7 @@ __device__ __forceinline__ bool pick_low(int policy, uint64_t m, int rank, const
 __device__ __forceinline__ int pick_bitmap(int policy, const uint32_t *bits, int cap, int rank, const PolicyState &s,
                                            int *s_res)
 {
-    if (policy == 1 && (rank & 1) == 0) {
+    if ((policy == 1 || policy == 3) && (rank & 1) == 0) {
         int c = block_find_free_down(bits, cap, s.col_max, s_res);
         if (c == -1) c = block_find_free_up(bits, cap, s.col_max + 1, s_res);
         return c;
@@ -739,6 +739,7 @@ __device__ __forceinline__ int pick_bitmap(int policy, const uint32_t *bits, int
 
 __device__ __forceinline__ void policy_update(int policy, int col, PolicyState &s)
 {
+    if (policy == 3) return;   // B1G: col_max stays the snapshot's largest color
     s.col_max = max(s.col_max, col);
     if (policy == 2) s.col_next = min(col + 1, s.col_max / 3 + 1);
 }
@@ -924,7 +925,7 @@ __device__ int pick_words(const Graph &g, int w, uint64_t m0, const uint64_t *ma
                   : regs ? regs_free_down(r, m0, mask0, hw, PH, from)
                          : words_free_down<D2>(g, w, m0, mask0, hw, PH, from);
     };
-    if (policy == 1 && (w & 1) == 0) {   // B1, even rank
+    if ((policy == 1 || policy == 3) && (w & 1) == 0) {   // B1 / B1G, even rank
         int c = down(s.col_max);
         if (c == -1) c = up(s.col_max + 1);
         return c;
@@ -1036,8 +1037,11 @@ __global__ void __launch_bounds__(64) k_vcolor_chunked(Graph g, const int *W, Ct
     const int n = ctrl->n_w[par];
     const int nchunks = (n + chunk - 1) / chunk;
     const int lane = threadIdx.x;
+    // B1G: col_max is the largest color of the round's snapshot (the running
+    // maximum of the colors kept, final before this launch)
+    const int g_max = policy == 3 ? ctrl->pad[0] : 0;
     for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-        PolicyState s = {0, 0};
+        PolicyState s = {g_max, 0};
         int lo = ch * chunk, hi = min(lo + chunk, n);
         int cap = -1, cmax = -1;
         for (int sub = lo; sub < hi; sub += WAVE) {

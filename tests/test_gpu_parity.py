@@ -107,6 +107,8 @@ SCHEDULES = [
     ("B2-T100", dict(policy=2, chunk=100)),
     ("N1-B1", dict(net_color_mask=1, policy=1, chunk=64)),
     ("N1-B2", dict(net_color_mask=1, policy=2, chunk=64)),
+    ("B1G", dict(policy=3, chunk=64)),
+    ("N1-B1G-T5", dict(net_color_mask=1, policy=3, chunk=5)),
 ]
 
 GRAPHS = [
@@ -131,7 +133,8 @@ def test_random_schedules(cuda, shape, sched):
 def test_colors_beyond_64(cuda):
     """Dense nets push first-fit past 63: the wide paths and pairwise checks."""
     g = synth.random_uniform(3000, 2500, 40, 90, 21)
-    for kw in (dict(), dict(net_color_mask=1), dict(policy=1), dict(policy=2), dict(net_color_mask=0b11)):
+    for kw in (dict(), dict(net_color_mask=1), dict(policy=1), dict(policy=2), dict(net_color_mask=0b11),
+               dict(policy=3)):
         ref = oracle.bgpc(g, **kw)
         res, colors = _gpu_bgpc(cuda, g, **kw)
         _compare_full(res, colors, ref)
@@ -156,7 +159,7 @@ def test_skewed_small(cuda):
     precomputed per round (more than 128 nets) and searched as one row."""
     g = synth.skewed(30000, 30000, seed=3, kmax=3000)
     for kw in (dict(net_color_mask=1), dict(net_color_mask=1, policy=1), dict(net_color_mask=1, policy=2),
-               dict(net_color_mask=1, policy=1, chunk=7), dict(policy=2, chunk=200)):
+               dict(net_color_mask=1, policy=1, chunk=7), dict(policy=2, chunk=200), dict(net_color_mask=1, policy=3)):
         ref = oracle.bgpc(g, **kw)
         res, colors = _gpu_bgpc(cuda, g, **kw)
         _compare_full(res, colors, ref)
@@ -192,7 +195,7 @@ def test_d2gc_rmat_small(cuda, mask):
 
 def test_d2gc_policies(cuda):
     adj = synth.rmat(10, 4, 0.57, 0.19, 0.19, seed=10)
-    for kw in (dict(policy=1), dict(policy=2), dict(policy=1, net_color_mask=1)):
+    for kw in (dict(policy=1), dict(policy=2), dict(policy=1, net_color_mask=1), dict(policy=3, net_color_mask=1)):
         ref = oracle.d2gc(adj, **kw)
         res, colors = _gpu_d2(cuda, adj, **kw)
         _compare_full(res, colors, ref)
@@ -458,3 +461,14 @@ def test_net_round_size_limit(cuda):
     assert res.status == bgpc.E_UNSUPPORTED and res.rounds == 0
     res, colors = _gpu_bgpc(cuda, g, net_color_mask=1 << 5)   # a net-based round later on: refused up front
     assert res.status == bgpc.E_UNSUPPORTED and res.rounds == 0
+
+
+def test_b1_global_resume(cuda):
+    """B1G reads col_max from the colors already present: resuming must see
+    the ones it was handed."""
+    g = synth.random_uniform(9000, 7000, 2, 12, 31)
+    part = oracle.bgpc(g, policy=3, max_rounds=3)
+    ref = oracle.bgpc(g, policy=3, init_colors=part.colors, start_round=3)
+    res, colors = _gpu_bgpc(cuda, g, policy=3, init_colors=part.colors, start_round=3, flags=bgpc.RESUME)
+    _compare_full(res, colors, ref)
+    assert np.array_equal(colors, oracle.bgpc(g, policy=3).colors)
