@@ -20,7 +20,8 @@
  *     rule); losers become uncolored and form the next round's worklist;
  *   - vertex-based rounds choose by first-fit (Algorithms 2 and 4) or by the
  *     balancing policies B1 / B2 (Algorithms 11 and 12), whose state restarts
- *     every `chunk` consecutive worklist entries;
+ *     every `chunk` consecutive worklist entries (or by B1 with one bound for
+ *     the whole round, BGPC_B1_GLOBAL);
  *   - net-based rounds (Algorithms 8 and 9) run reverse first-fit inside each
  *     net holding an uncolored vertex, starting at |vtxs(v)| - 1; a vertex
  *     takes the proposal of its owner net only: the largest net containing
