@@ -24,6 +24,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 
 OK, E_INVALID, E_NOT_CONVERGED, E_INTERNAL = 0, -1, -6, -8
 FIRST_FIT, B1, B2, B1_GLOBAL = 0, 1, 2, 3
+NET_ALG8, NET_ALG6, NET_ALG6_REVERSE = 0, 1, 2
 
 
 def build(verbose: bool = False) -> str:
@@ -47,7 +48,7 @@ def _load():
         P = ctypes.c_void_p
         i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
         lib.oracle_color.argtypes = [i32, i32, P, P, P, P, i32, u64, i32, i32, i32, i32, i32,
-                                     P, P, i32, P, P, P, P, P]
+                                     i32, i32, u64, P, P, i32, P, P, P, P, P, P, P]
         lib.oracle_color.restype = ctypes.c_int
         lib.oracle_seq_greedy.argtypes = [i32, i32, P, P, P, P, i32, P]
         lib.oracle_seq_greedy.restype = ctypes.c_int
@@ -123,7 +124,8 @@ class Result:
 
 
 def _run(n_a, n_b, a_off, a_idx, b_off, b_idx, d2, net_color_mask, policy, chunk,
-         max_rounds, start_round, init_colors, log_cap, literal_ff=False):
+         max_rounds, start_round, init_colors, log_cap, literal_ff=False, net_alg=NET_ALG8,
+         net_balance=False, vertex_removal_mask=0):
     lib = _load()
     a_off, b_off = _c64(a_off), _c64(b_off)
     a_idx, b_idx = _c32(a_idx), _c32(b_idx)
@@ -134,23 +136,33 @@ def _run(n_a, n_b, a_off, a_idx, b_off, b_idx, d2, net_color_mask, policy, chunk
     ll = np.zeros(log_cap, dtype=np.int64)
     le = np.zeros(log_cap, dtype=np.int64)
     lc = np.zeros(log_cap, dtype=np.int32)
+    ht = np.zeros(log_cap, dtype=np.uint64)
+    hc = np.zeros(log_cap, dtype=np.uint64)
     st = lib.oracle_color(n_a, n_b, _ptr(a_off), _ptr(a_idx), _ptr(b_off), _ptr(b_idx),
                           int(d2), ctypes.c_uint64(net_color_mask & (2 ** 64 - 1)), int(policy), int(chunk),
-                          int(max_rounds), int(start_round), int(bool(literal_ff)), _ptr(colors), _ptr(rounds),
-                          log_cap, _ptr(lm), _ptr(lw), _ptr(ll), _ptr(le), _ptr(lc))
+                          int(max_rounds), int(start_round), int(bool(literal_ff)), int(net_alg),
+                          int(bool(net_balance)), ctypes.c_uint64(vertex_removal_mask & (2 ** 64 - 1)),
+                          _ptr(colors), _ptr(rounds),
+                          log_cap, _ptr(lm), _ptr(lw), _ptr(ll), _ptr(le), _ptr(lc), _ptr(ht), _ptr(hc))
     r = int(rounds[0])
     k = min(r, log_cap)
     log = {"mode": lm[:k].copy(), "w": lw[:k].copy(), "losers": ll[:k].copy(),
-           "evicted": le[:k].copy(), "max_color": lc[:k].copy()}
+           "evicted": le[:k].copy(), "max_color": lc[:k].copy(), "hash_t": ht[:k].copy(),
+           "hash_c": hc[:k].copy()}
     return int(st), colors, r, log
 
 
 def bgpc(g, net_color_mask: int = 0, policy: int = FIRST_FIT, chunk: int = 64,
          max_rounds: int = 0, order=None, init_colors=None, start_round: int = 0,
-         log_cap: int = 4096, literal_ff: bool = False) -> Result:
+         log_cap: int = 4096, literal_ff: bool = False, net_alg: int = NET_ALG8,
+         net_balance: bool = False, vertex_removal_mask: int = 0) -> Result:
     """Bipartite-graph partial coloring of V_A (Sections II-III, V).
     literal_ff: first-fit rounds gather F(w) member by member instead of
-    through per-net color sets (same result, much slower on large nets)."""
+    through per-net color sets (same result, much slower on large nets).
+    net_alg: the net-based coloring of Algorithm 8 (default), Algorithm 6, or
+    Algorithm 6 with the reverse start; net_balance: net-based rounds choose
+    by the policy (Section V).  vertex_removal_mask: rounds whose conflicts
+    are checked in the vertex form where that form is exact (same results)."""
     n_a, n_b = int(g.n_a), int(g.n_b)
     a_off, a_idx, b_off, b_idx = g.a_off, g.a_idx, g.b_off, g.b_idx
     inv = None
@@ -161,7 +173,8 @@ def bgpc(g, net_color_mask: int = 0, policy: int = FIRST_FIT, chunk: int = 64,
         if init_colors is not None:
             init_colors = np.asarray(init_colors)[order]
     st, colors, r, log = _run(n_a, n_b, a_off, a_idx, b_off, b_idx, 0, net_color_mask, policy, chunk,
-                              max_rounds, start_round, init_colors, log_cap, literal_ff)
+                              max_rounds, start_round, init_colors, log_cap, literal_ff, net_alg,
+                              net_balance, vertex_removal_mask)
     if inv is not None:
         colors = colors[inv]
     return Result(st, colors, r, log)
@@ -169,7 +182,8 @@ def bgpc(g, net_color_mask: int = 0, policy: int = FIRST_FIT, chunk: int = 64,
 
 def d2gc(adj, net_color_mask: int = 0, policy: int = FIRST_FIT, chunk: int = 64,
          max_rounds: int = 0, order=None, init_colors=None, start_round: int = 0,
-         log_cap: int = 4096, literal_ff: bool = False) -> Result:
+         log_cap: int = 4096, literal_ff: bool = False, net_alg: int = NET_ALG8,
+         net_balance: bool = False, vertex_removal_mask: int = 0) -> Result:
     """Distance-2 coloring of a symmetric graph without self loops (Section IV)."""
     n = int(adj.n)
     off, idx = adj.off, adj.idx
@@ -180,7 +194,8 @@ def d2gc(adj, net_color_mask: int = 0, policy: int = FIRST_FIT, chunk: int = 64,
         if init_colors is not None:
             init_colors = np.asarray(init_colors)[order]
     st, colors, r, log = _run(n, n, off, idx, off, idx, 1, net_color_mask, policy, chunk,
-                              max_rounds, start_round, init_colors, log_cap, literal_ff)
+                              max_rounds, start_round, init_colors, log_cap, literal_ff, net_alg,
+                              net_balance, vertex_removal_mask)
     if inv is not None:
         colors = colors[inv]
     return Result(st, colors, r, log)

@@ -107,42 +107,59 @@ static void fset_add(fset_t *f, int64_t col) { f->mark[col] = f->cur; }
 
 typedef struct { int64_t col_max, col_next; } chunk_state_t;
 
-/* The color policies.  First-fit: Algorithm 2's closing search.
- * B1: Algorithm 11.  B2: Algorithm 12 (col_max / 3 is an integer floor).
- * B1G: Algorithm 11's choice with col_max fixed for the whole round to the
- * largest color of the round's snapshot (no state carried between vertices;
- * -1 when nothing is colored yet). */
+/* smallest color >= from that is not in F */
+static int64_t free_at_or_above(const fset_t *F, int64_t from)
+{
+    int64_t c = from;
+    while (fset_has(F, c)) c++;
+    return c;
+}
+
+/* largest color <= from that is not in F, or -1 when [0, from] is all in F */
+static int64_t free_at_or_below(const fset_t *F, int64_t from)
+{
+    int64_t c = from;
+    while (c >= 0 && fset_has(F, c)) c--;
+    return c;
+}
+
+/* The color policies, each stated as the color it picks for a forbidden set F.
+ *   First-fit (Algorithm 2): the smallest free color.
+ *   B1 (Algorithm 11): an even rank takes the largest free color not above
+ *     col_max, or, when [0, col_max] is all forbidden, the smallest free color
+ *     above col_max; an odd rank takes first-fit.  col_max then grows to the
+ *     pick.
+ *   B1G: B1's pick with col_max fixed for the whole round to the largest
+ *     color of the round's snapshot (-1 before any color); no state passes
+ *     between vertices.
+ *   B2 (Algorithm 12): the smallest free color at or above col_next if it does
+ *     not exceed col_max, else first-fit.  col_max grows to the pick and
+ *     col_next becomes the pick + 1 capped at col_max / 3 + 1 (integer floor). */
 static int64_t policy_pick(int policy, const fset_t *F, chunk_state_t *st, int32_t rank)
 {
     int64_t col;
-    if (policy == POL_B1 || policy == POL_B1G) {
+    switch (policy) {
+    case POL_B1:
+    case POL_B1G:
         if (rank % 2 == 0) {
-            col = st->col_max;
-            while (col >= 0 && fset_has(F, col)) col--;
-            if (col == -1) {
-                col = st->col_max + 1;
-                while (fset_has(F, col)) col++;
-            }
+            col = free_at_or_below(F, st->col_max);
+            if (col < 0) col = free_at_or_above(F, st->col_max + 1);
         } else {
-            col = 0;
-            while (fset_has(F, col)) col++;
+            col = free_at_or_above(F, 0);
         }
         if (policy == POL_B1 && col > st->col_max) st->col_max = col;
-    } else if (policy == POL_B2) {
-        col = st->col_next;
-        while (fset_has(F, col)) col++;
-        if (col > st->col_max) {
-            col = 0;
-            while (fset_has(F, col)) col++;
-        }
+        return col;
+    case POL_B2: {
+        col = free_at_or_above(F, st->col_next);
+        if (col > st->col_max) col = free_at_or_above(F, 0);
         if (col > st->col_max) st->col_max = col;
-        int64_t cap = st->col_max / 3 + 1;
-        st->col_next = (col + 1 < cap) ? col + 1 : cap;
-    } else {
-        col = 0;
-        while (fset_has(F, col)) col++;
+        const int64_t cap = st->col_max / 3 + 1;
+        st->col_next = col + 1 < cap ? col + 1 : cap;
+        return col;
     }
-    return col;
+    default:
+        return free_at_or_above(F, 0);
+    }
 }
 
 /* owner(u): the net of u with the most vertices, ties to the lowest net id. */
@@ -401,18 +418,40 @@ static int color_vertex_round_nbor(const graph_t *g, const nbor_t *nb, const int
 }
 
 /*
- * Net-based coloring (Algorithm 8; Algorithm 9 in distance-2 mode): every net
- * with an uncolored member gathers the colors of its colored members into F,
- * queues the rest, and hands out colors from the top of [0, |vtxs(v)|)
- * downwards, skipping F (reverse first-fit).  Only the owner net's proposal is
- * written.  Worklist vertices without any net take the policy's color for an
- * empty F.
+ * Net-based coloring (Sections III and IV).  Every net with an uncolored
+ * member hands colors to its uncolored members in adjacency order
+ * (distance-2: the center first, Algorithm 9); only the owner net's proposal
+ * is written.  Worklist vertices without any net take the policy's color for
+ * an empty F.  The variants:
+ *   NET_ALG8    Algorithm 8: F = the colors of the colored members (a first
+ *               pass), then reverse first-fit from |vtxs(v)| - 1 (distance-2:
+ *               |nbor(v)|), each handed color joining F.
+ *   NET_ALG6    Algorithm 6 (first-fit inside the net, no first pass): the
+ *               members are visited once, in order; a colored member adds its
+ *               color to F, an uncolored one takes the smallest color not in
+ *               F at or above the previous pick, which then joins F.  A colored
+ *               member whose color an earlier member was just given keeps it
+ *               in this round (snapshot colors are fixed); the removal step
+ *               evicts it, since the earlier member has the lower rank.
+ *   NET_ALG6R   Algorithm 6 with the reverse start: the same single pass, the
+ *               pick being the largest color not in F at or below the
+ *               previous one, starting from |vtxs(v)| - 1.
+ * With net_balance (Section V: the balancing heuristics apply to nets as to
+ * vertices), Algorithm 8's first pass is kept and each uncolored member takes
+ * policy_pick(F) instead of the reverse first-fit color, the net id taking
+ * the place of the vertex id in B1's parity; the policy state runs through
+ * `chunk` consecutive net ids (a virtual thread) and restarts every round.
  */
+enum { NET_ALG8 = 0, NET_ALG6 = 1, NET_ALG6R = 2 };
+
 static int color_net_round(const graph_t *g, const int32_t *s, int32_t *t,
                            const int32_t *owner, const int32_t *W, int64_t nw,
-                           int policy, int64_t color_cap, int64_t max_size)
+                           int policy, int net_alg, int net_balance, int32_t chunk,
+                           int64_t snap_max, int64_t color_cap, int64_t max_size)
 {
     int err = 0;
+    const int32_t span = net_balance ? chunk : 1;   /* nets sharing one policy state */
+    const int64_t nchunks = ((int64_t)g->n_b + span - 1) / span;
     #pragma omp parallel reduction(| : err)
     {
         fset_t F;
@@ -420,33 +459,60 @@ static int color_net_round(const graph_t *g, const int32_t *s, int32_t *t,
         if (fset_init(&F, color_cap) || !L) {
             err |= 1;
         } else {
-            #pragma omp for schedule(dynamic, 256)
-            for (int32_t v = 0; v < g->n_b; v++) {
-                int64_t kv = vtxs_count(g, v);
-                int any_uncolored = 0;
-                for (int64_t b = 0; b < kv; b++)
-                    if (s[vtx_at(g, v, b)] == -1) any_uncolored = 1;
-                if (!any_uncolored) continue;
-                fset_clear(&F);
-                int64_t nl = 0;
-                for (int64_t b = 0; b < kv; b++) {
-                    int32_t x = vtx_at(g, v, b);
-                    if (s[x] != -1 && !fset_has(&F, s[x])) {
-                        fset_add(&F, s[x]);
+            #pragma omp for schedule(dynamic, 64)
+            for (int64_t ch = 0; ch < nchunks; ch++) {
+                chunk_state_t state = {policy == POL_B1G ? snap_max : 0, 0};
+                const int64_t lo = ch * span;
+                const int64_t hi = lo + span < g->n_b ? lo + span : g->n_b;
+                for (int32_t v = (int32_t)lo; v < hi; v++) {
+                    int64_t kv = vtxs_count(g, v);
+                    int any_uncolored = 0;
+                    for (int64_t b = 0; b < kv; b++)
+                        if (s[vtx_at(g, v, b)] == -1) any_uncolored = 1;
+                    if (!any_uncolored) continue;
+                    fset_clear(&F);
+                    if (net_alg == NET_ALG8) {
+                        int64_t nl = 0;
+                        for (int64_t b = 0; b < kv; b++) {
+                            int32_t x = vtx_at(g, v, b);
+                            if (s[x] != -1 && !fset_has(&F, s[x])) {
+                                fset_add(&F, s[x]);
+                            } else {
+                                /* a colored x whose color is already in F would mean
+                                 * two colored members of one net share a color,
+                                 * which the removal step never leaves behind */
+                                if (s[x] != -1) err |= 4;
+                                L[nl++] = x;
+                            }
+                        }
+                        int64_t col = kv - 1;   /* |vtxs(v)| - 1; distance-2: |nbor(v)| */
+                        for (int64_t i = 0; i < nl; i++) {
+                            if (net_balance) {
+                                col = policy_pick(policy, &F, &state, v);
+                            } else {
+                                col = free_at_or_below(&F, col);
+                                if (col < 0) err |= 8;
+                            }
+                            if (col + 1 >= color_cap) { err |= 2; break; }
+                            if (owner[L[i]] == v) t[L[i]] = (int32_t)col;
+                            fset_add(&F, col);
+                        }
                     } else {
-                        /* a colored x whose color is already in F would mean two
-                         * colored members of one net share a color, which the
-                         * removal step never leaves behind */
-                        if (s[x] != -1) err |= 4;
-                        L[nl++] = x;
+                        const int forward = net_alg == NET_ALG6;
+                        int64_t col = forward ? 0 : kv - 1;
+                        for (int64_t b = 0; b < kv; b++) {
+                            int32_t x = vtx_at(g, v, b);
+                            if (s[x] != -1) {
+                                fset_add(&F, s[x]);
+                                continue;
+                            }
+                            col = forward ? free_at_or_above(&F, col) : free_at_or_below(&F, col);
+                            if (col < 0) err |= 8;
+                            if (col < 0 || col + 1 >= color_cap) { err |= 2; break; }
+                            if (owner[x] == v) t[x] = (int32_t)col;
+                            fset_add(&F, col);
+                        }
                     }
-                }
-                int64_t col = kv - 1;   /* |vtxs(v)| - 1; distance-2: |nbor(v)| */
-                for (int64_t i = 0; i < nl; i++) {
-                    while (col >= 0 && fset_has(&F, col)) col--;
-                    if (col < 0) err |= 8;
-                    if (owner[L[i]] == v) t[L[i]] = (int32_t)col;
-                    col--;
                 }
             }
             #pragma omp for schedule(static)
@@ -510,6 +576,51 @@ static int remove_conflicts(const graph_t *g, const int32_t *t, uint8_t *lose, i
 }
 
 /*
+ * Removal in the vertex form (Algorithm 5 with Algorithm 3's test): only the
+ * worklist is checked; w loses iff a vertex x sharing a net with w has
+ * t[x] == t[w] and x < w.  Equal to the net form whenever every vertex that
+ * was colored before the round keeps a color no worklist vertex proposes:
+ * after a vertex-based round (a proposal avoids every colored neighbour's
+ * color) and after a net-based round that started with nothing colored.
+ */
+static int remove_conflicts_vertex(const graph_t *g, const int32_t *t, const int32_t *W, int64_t nw,
+                                   uint8_t *lose)
+{
+    memset(lose, 0, (size_t)g->n_a);
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < nw; i++) {
+        int32_t w = W[i];
+        if (t[w] == -1) continue;
+        int lost = 0;
+        int64_t kn = nets_count(g, w);
+        for (int64_t a = 0; a < kn && !lost; a++) {
+            int32_t v = net_at(g, w, a);
+            int64_t kv = vtxs_count(g, v);
+            for (int64_t b = 0; b < kv && !lost; b++) {
+                int32_t x = vtx_at(g, v, b);
+                if (x < w && t[x] == t[w]) lost = 1;
+            }
+        }
+        lose[w] = (uint8_t)lost;
+    }
+    return OR_OK;
+}
+
+/* FNV-1a, 64-bit, over the little-endian bytes of a[0..n) */
+static uint64_t fnv1a_i32(const int32_t *a, int64_t n)
+{
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (int64_t i = 0; i < n; i++) {
+        uint32_t v = (uint32_t)a[i];
+        for (int k = 0; k < 4; k++) {
+            h ^= (v >> (8 * k)) & 0xffu;
+            h *= 0x100000001b3ull;
+        }
+    }
+    return h;
+}
+
+/*
  * The speculative loop of Algorithm 1 on V_color = V_A.
  *   colors     in: starting coloring (all -1, or a conflict-free partial one
  *              to resume from); out: the coloring reached.
@@ -518,19 +629,30 @@ static int remove_conflicts(const graph_t *g, const int32_t *t, uint8_t *lose, i
  *              as printed) instead of through the per-net color sets.
  *   max_rounds   rounds to run at most (0: n_a + 65); status -6 when the
  *              worklist is still non-empty after them.
+ *   net_alg    net-based rounds: NET_ALG8, NET_ALG6 or NET_ALG6R (see
+ *              color_net_round); net_balance: net-based rounds choose by the
+ *              policy (Algorithm 8's first pass, then policy_pick per member).
+ *   vertex_removal_mask  bit r (r < 64; rounds past 63 follow bit 63): round
+ *              r checks conflicts in the vertex form, when that form is exact
+ *              (a vertex-based round, or a net-based round that started with
+ *              nothing colored); otherwise, and for clear bits, the net form.
  *   log_*      optional per-round records (mode, |W_r|, losers, evicted
- *              colored vertices, max color after the round), log_cap entries.
+ *              colored vertices, max color after the round, FNV-1a-64 of the
+ *              tentative colors t after the coloring step and of the colors
+ *              after the round), log_cap entries.
  */
 int oracle_color(int32_t n_a, int32_t n_b,
                  const int64_t *a_off, const int32_t *a_idx,
                  const int64_t *b_off, const int32_t *b_idx,
                  int32_t d2, uint64_t net_color_mask, int32_t policy, int32_t chunk,
                  int32_t max_rounds, int32_t start_round, int32_t literal_ff,
+                 int32_t net_alg, int32_t net_balance, uint64_t vertex_removal_mask,
                  int32_t *colors, int32_t *rounds_out,
                  int32_t log_cap, int32_t *log_mode, int64_t *log_w, int64_t *log_losers,
-                 int64_t *log_evicted, int32_t *log_maxc)
+                 int64_t *log_evicted, int32_t *log_maxc, uint64_t *log_hash_t, uint64_t *log_hash_c)
 {
     if (n_a < 0 || n_b < 0 || chunk <= 0 || policy < 0 || policy > 3) return OR_E_INVALID;
+    if (net_alg < NET_ALG8 || net_alg > NET_ALG6R || (net_balance && net_alg != NET_ALG8)) return OR_E_INVALID;
     if (d2 && n_a != n_b) return OR_E_INVALID;
     graph_t g = {n_a, n_b, d2, a_off, a_idx, b_off, b_idx};
     if (max_rounds <= 0) max_rounds = n_a + 65;
@@ -575,19 +697,27 @@ int oracle_color(int32_t n_a, int32_t n_b,
         /* every color a round can produce stays below this bound */
         int64_t cap = maxc + 2 + (int64_t)chunk + 2;
         if (max_size + 2 > cap) cap = max_size + 2;
+        /* balanced net rounds: a pick exceeds the chunk's col_max by at most the
+         * net's size, and col_max starts at 0 (B1G: the snapshot's largest color) */
+        if (net_mode && net_balance) cap = (maxc > 0 ? maxc : 0) + (int64_t)chunk * (max_size + 1) + 4;
 
         memcpy(t, s, sizeof(int32_t) * (size_t)n_a);
         int e;
-        if (net_mode) e = color_net_round(&g, s, t, owner, W, nw, policy, cap, max_size);
+        if (net_mode) e = color_net_round(&g, s, t, owner, W, nw, policy, net_alg, net_balance, chunk, maxc, cap,
+                                          max_size);
         else if (policy == POL_FF && !literal_ff && nb.off) e = color_vertex_round_nbor(&g, &nb, s, t, W, nw);
         else if (policy == POL_FF && !literal_ff) e = color_vertex_round_sets(&g, s, t, W, nw);
         else e = color_vertex_round(&g, s, t, W, nw, policy, chunk, cap);
         if (e) { status = e; break; }
+        if (r < log_cap && log_hash_t) log_hash_t[r] = fnv1a_i32(t, n_a);
         int64_t tmax = -1;
         for (int32_t u = 0; u < n_a; u++)
             if (t[u] > tmax) tmax = t[u];
         if (tmax + 2 > cap) cap = tmax + 2;
-        e = remove_conflicts(&g, t, lose, cap);
+        const int vbit = round_id < 64 ? round_id : 63;
+        const int vertex_form = ((vertex_removal_mask >> vbit) & 1u) && (!net_mode || maxc < 0);
+        if (vertex_form) e = remove_conflicts_vertex(&g, t, W, nw, lose);
+        else e = remove_conflicts(&g, t, lose, cap);
         if (e) { status = e; break; }
         int64_t losers = 0, evicted = 0, nmax = -1;
         for (int32_t u = 0; u < n_a; u++) {
@@ -606,6 +736,7 @@ int oracle_color(int32_t n_a, int32_t n_b,
             if (log_losers) log_losers[r] = losers;
             if (log_evicted) log_evicted[r] = evicted;
             if (log_maxc) log_maxc[r] = (int32_t)nmax;
+            if (log_hash_c) log_hash_c[r] = fnv1a_i32(colors, n_a);
         }
         r++;
     }

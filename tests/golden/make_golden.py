@@ -28,6 +28,18 @@ OUT = os.path.join(HERE, "workloads.json")
 BATCH_SAMPLE = list(range(0, 4096, 128)) + [5, 7, 8]
 
 
+def batch_large_sample(k: int = 24) -> list:
+    """k graphs of the batched workload spread over the sizes above 1.2e6
+    expected memberships (n_B times the mean net size 16.5) with more than
+    20,000 vertices, chosen from the generator's sizes alone: large sparse
+    graphs, the ones one workgroup would take longest on."""
+    sizes = np.array([synth.batch_sizes(i) for i in range(4096)])
+    na, nb = sizes[:, 0], sizes[:, 1]
+    big = np.nonzero((nb * 16.5 > 1.2e6) & (na > 20000))[0]
+    by_size = big[np.argsort(nb[big], kind="stable")]
+    return sorted(int(i) for i in by_size[np.linspace(0, len(by_size) - 1, k).astype(int)])
+
+
 def colors_sha(colors) -> str:
     return hashlib.sha256(np.ascontiguousarray(colors, dtype=np.int32).tobytes()).hexdigest()
 
@@ -54,7 +66,9 @@ def make(groups):
         g = synth.config(1)
         d = g.digest()
         out = {}
-        for name, mask in (("vv", 0), ("n1", 0b1), ("v_then_n", 0b10), ("n1n2", 0b11)):
+        # mask 0b1 is the paper's N1-N2 (net-based coloring in the first
+        # round), 0b11 its N2-N2 (the first two rounds)
+        for name, mask in (("vv", 0), ("n1", 0b1), ("v_then_n", 0b10), ("n2n2", 0b11)):
             t = time.time()
             out[name] = entry(d, oracle.bgpc(g, net_color_mask=mask))
             print("stencil", name, out[name]["rounds"], f"{time.time() - t:.1f}s", flush=True)
@@ -69,7 +83,14 @@ def make(groups):
             r = oracle.bgpc(g, net_color_mask=1, policy=pol)
             out[name] = entry(d, r, {"stats": oracle.color_stats(r.colors)})
             print("skewed", name, r.rounds, f"{time.time() - t:.1f}s", flush=True)
-        data["skewed4m"] = out
+        data.setdefault("skewed4m", {}).update(out)
+    if "skewed_b1g" in groups:
+        # B1 with one col_max per round (policy 3), net-based first round
+        g = synth.config(2)
+        t = time.time()
+        r = oracle.bgpc(g, net_color_mask=1, policy=3)
+        data.setdefault("skewed4m", {})["n1_b1g"] = entry(g.digest(), r, {"stats": oracle.color_stats(r.colors)})
+        print("skewed n1_b1g", r.rounds, f"{time.time() - t:.1f}s", flush=True)
     if "rmat" in groups:
         a = synth.config(3)
         d = a.digest()
@@ -85,9 +106,20 @@ def make(groups):
             out[str(i)] = entry(g.digest(), oracle.bgpc(g))
             print("batch", i, out[str(i)]["rounds"], f"{time.time() - t:.1f}s", flush=True)
         data["batch4096_sample"] = out
+    if "batch_large" in groups:
+        out = data.setdefault("batch4096_sample", {})
+        for i in batch_large_sample():
+            if str(i) in out:
+                continue
+            g = synth.batch_graph(i)
+            t = time.time()
+            out[str(i)] = entry(g.digest(), oracle.bgpc(g))
+            print("batch", i, out[str(i)]["rounds"], f"{time.time() - t:.1f}s", flush=True)
+            with open(OUT, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
     with open(OUT, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
 
 
 if __name__ == "__main__":
-    make(sys.argv[1:] or ["random20k", "stencil", "skewed", "rmat", "batch"])
+    make(sys.argv[1:] or ["random20k", "stencil", "skewed", "skewed_b1g", "rmat", "batch", "batch_large"])

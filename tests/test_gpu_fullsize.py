@@ -62,7 +62,7 @@ def test_random20k_full(cuda):
         _check(f"random20k/{name}", g.digest(), res, c, GOLD["random20k"][name])
 
 
-@pytest.mark.parametrize("name,mask", [("vv", 0), ("n1", 0b1), ("v_then_n", 0b10), ("n1n2", 0b11)])
+@pytest.mark.parametrize("name,mask", [("vv", 0), ("n1", 0b1), ("v_then_n", 0b10), ("n2n2", 0b11)])
 def test_stencil128_full(cuda, name, mask):
     g, (A, B) = _graph(1)
     res, c = _run(cuda, (A, B), g.n_a, lambda o: bgpc.bgpc_color(A, B, None, o, net_color_mask=mask, log_cap=4096))

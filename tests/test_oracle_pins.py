@@ -102,7 +102,10 @@ def chromatic_number(adj_matrix):
 @pytest.mark.parametrize("case", _cases(), ids=lambda c: c["name"])
 def test_worked_examples(case):
     g = _graph(case)
-    kw = dict(net_color_mask=case["net_color_mask"], policy=case["policy"], chunk=case["chunk"])
+    kw = dict(net_color_mask=case["net_color_mask"], policy=case["policy"], chunk=case["chunk"],
+              net_alg=case.get("net_alg", 0), net_balance=case.get("net_balance", False))
+    if "init_colors" in case:
+        kw["init_colors"] = np.array(case["init_colors"], dtype=np.int32)
     states = case["states"]
     for k, expect in enumerate(states, start=1):
         r = _run(g, max_rounds=k, **kw)
@@ -442,3 +445,180 @@ def test_b1_global_is_stateless():
     adj = synth.rmat(8, 4, 0.57, 0.19, 0.19, seed=12)
     r = oracle.d2gc(adj, policy=oracle.B1_GLOBAL, net_color_mask=1)
     assert r.status == 0 and oracle.violations(adj, r.colors) == 0
+
+
+# ---------------------------------------------------------------------------
+# the validity counter (the assertion the device tests rest on)
+#
+# oracle.violations counts, per net, every member whose color an earlier
+# member of the same net already holds, plus every uncolored vertex once.
+# Each case below is counted by hand from that definition.
+
+E1_NETS = [[0, 1, 2], [1, 3], [2, 3, 4], [0, 4]]
+
+
+@pytest.mark.parametrize("colors,expected", [
+    ([0, 1, 2, 0, 1], 0),        # E1's final coloring: valid
+    ([0, 0, 2, 0, 1], 2),        # 0,1 clash in {0,1,2}; 1,3 clash in {1,3}
+    ([5, 5, 5, 1, 0], 2),        # three equal members of one net: two repeats
+    ([0, 1, -1, 0, 1], 1),       # one uncolored vertex, no clash
+    ([-1, -1, -1, -1, -1], 5),   # nothing colored
+    ([0, 1, 2, 2, 0], 2),        # {2,3,4}: 2,3 share 2; {0,4}: 0,4 share 0
+    ([0, 0, -1, 0, 0], 5),       # 1 uncolored + {0,1,2}, {1,3}, {2,3,4}, {0,4} once each
+])
+def test_violations_by_hand_bipartite(colors, expected):
+    g = synth.from_nets(5, E1_NETS)
+    assert oracle.violations(g, np.array(colors, dtype=np.int32)) == expected
+
+
+@pytest.mark.parametrize("colors,expected", [
+    ([0, 1, 2], 0),    # path 0-1-2 colored apart
+    ([0, 1, 0], 1),    # distance-2 clash: 0 and 2 both in N[1]
+    ([0, 0, 1], 2),    # distance-1 clash, seen in N[0] and in N[1]
+    ([3, 3, 3], 4),    # N[0]: one repeat, N[1]: two, N[2]: one
+    ([1, -1, 2], 1),   # the center uncolored
+])
+def test_violations_by_hand_distance2(colors, expected):
+    adj = synth.adjacency_from_edges(3, [(0, 1), (1, 2)])
+    assert oracle.violations(adj, np.array(colors, dtype=np.int32)) == expected
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_violations_match_scipy_count(seed):
+    """Random colorings with few colors (many clashes), some entries -1: the
+    count equals the uncolored vertices plus, per net, members minus distinct
+    colors among the colored members (scipy incidence, numpy)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    for g in (synth.random_uniform(400, 300, 2, 9, seed), synth.rmat(8, 6, 0.57, 0.19, 0.19, seed=seed)):
+        n = g.n_a if hasattr(g, "n_a") else g.n
+        colors = rng.integers(-1, 6, size=n).astype(np.int32)
+        m = incidence(g).tocoo()
+        col = colors[m.col]
+        keep = col >= 0
+        rows, cc = m.row[keep], col[keep]
+        pairs = np.unique(np.stack([rows, cc]), axis=1).shape[1]
+        expected = int((colors < 0).sum()) + int(keep.sum()) - pairs
+        assert oracle.violations(g, colors) == expected
+
+
+def test_seq_greedy_d2_independent():
+    """Sequential distance-2 first-fit: vertex u takes the smallest color of no
+    lower vertex within distance 2, the distance-2 relation taken from the
+    scipy product (A + I)^2."""
+    for seed in (2, 3):
+        adj = synth.rmat(9, 6, 0.57, 0.19, 0.19, seed=seed)
+        c = conflict_graph(adj)
+        colors = np.full(adj.n, -1)
+        for u in range(adj.n):
+            used = {int(colors[x]) for x in c[u].indices if x < u}
+            k = 0
+            while k in used:
+                k += 1
+            colors[u] = k
+        got = oracle.seq_greedy_d2(adj)
+        assert np.array_equal(got, colors)
+        assert independent_violations(adj, got) == 0
+
+
+# ---------------------------------------------------------------------------
+# removal forms, round hashes, net-based variants
+
+
+def _fnv1a64(a):
+    """FNV-1a 64 over the little-endian bytes of an int32 array (the
+    published definition: offset basis 0xcbf29ce484222325, prime 0x100000001b3)."""
+    h = 0xcbf29ce484222325
+    for b in np.ascontiguousarray(a, dtype="<i4").tobytes():
+        h = ((h ^ b) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(net_color_mask=1), dict(net_color_mask=0b10), dict(policy=1),
+                                dict(policy=2, chunk=7), dict(net_color_mask=1, net_alg=1)], ids=str)
+def test_vertex_form_removal_equals_net_form(kw):
+    """Where the vertex form is used (vertex-based rounds, a net-based round
+    that starts with nothing colored), it finds exactly the net form's losers:
+    every round's record and hashes agree."""
+    for g in (synth.random_uniform(3000, 2500, 2, 9, 61), synth.stencil27(8)):
+        a = oracle.bgpc(g, **kw)
+        b = oracle.bgpc(g, vertex_removal_mask=(1 << 64) - 1, **kw)
+        assert a.status == b.status == oracle.OK
+        assert np.array_equal(a.colors, b.colors) and a.rounds == b.rounds
+        for k in a.log:
+            assert np.array_equal(a.log[k], b.log[k]), k
+    adj = synth.rmat(9, 6, 0.57, 0.19, 0.19, seed=8)
+    a = oracle.d2gc(adj, net_color_mask=1)
+    b = oracle.d2gc(adj, net_color_mask=1, vertex_removal_mask=(1 << 64) - 1)
+    assert np.array_equal(a.colors, b.colors) and np.array_equal(a.log["hash_c"], b.log["hash_c"])
+
+
+def test_round_hashes():
+    """hash_c of the last round is the FNV-1a of the final colors; round 0
+    of vertex-based first-fit proposes 0 everywhere, so hash_t of round 0 is
+    the hash of n zeros; each round's hash_c is that round's state."""
+    g = synth.from_nets(5, E1_NETS)
+    r = oracle.bgpc(g)
+    assert int(r.log["hash_c"][-1]) == _fnv1a64(r.colors)
+    assert int(r.log["hash_t"][0]) == _fnv1a64(np.zeros(5, np.int32))
+    for k, state in enumerate([[0, -1, -1, -1, -1], [0, 1, -1, 0, -1]]):
+        assert int(r.log["hash_c"][k]) == _fnv1a64(np.array(state, np.int32))
+    # round 1 proposals: F(1)={0}, F(2)={0}, F(3)={}, F(4)={0} -> t=[0,1,1,0,1]
+    assert int(r.log["hash_t"][1]) == _fnv1a64(np.array([0, 1, 1, 0, 1], np.int32))
+    assert _fnv1a64(np.zeros(0, np.int32)) == 0xcbf29ce484222325
+
+
+@pytest.mark.parametrize("seed", [71, 72])
+def test_algorithm6_first_round_closed_form(seed):
+    """With nothing colored, Algorithm 6 hands member position p of a net the
+    color p (forward) or |vtxs(v)| - 1 - p (reverse start, which is
+    Algorithm 8's round); a vertex keeps its owner net's color unless a
+    lower vertex sharing a net got the same one."""
+    g = synth.random_uniform(2000, 1500, 2, 12, seed)
+    sizes = np.diff(g.b_off)
+    owner = np.full(g.n_a, -1)
+    best = np.full(g.n_a, -1)
+    for v in range(g.n_b):
+        for u in g.b_idx[g.b_off[v]:g.b_off[v + 1]]:
+            if sizes[v] > best[u]:
+                best[u], owner[u] = sizes[v], v
+    for alg in (1, 2):
+        t = np.zeros(g.n_a, np.int64)
+        for u in range(g.n_a):
+            if owner[u] < 0:
+                continue
+            row = g.b_idx[g.b_off[owner[u]]:g.b_off[owner[u] + 1]]
+            p = int(np.searchsorted(row, u))
+            t[u] = p if alg == 1 else sizes[owner[u]] - 1 - p
+        c = conflict_graph(g).tocoo()
+        lose = np.zeros(g.n_a, bool)
+        m = (t[c.row] == t[c.col]) & (c.col < c.row)
+        lose[c.row[m]] = True
+        expect = np.where(lose, -1, t)
+        r = oracle.bgpc(g, net_color_mask=1, net_alg=alg, max_rounds=1)
+        assert np.array_equal(r.colors, expect)
+    a8 = oracle.bgpc(g, net_color_mask=1)
+    a6r = oracle.bgpc(g, net_color_mask=1, net_alg=2)
+    assert np.array_equal(a8.colors, a6r.colors)
+
+
+@pytest.mark.parametrize("kw", [dict(net_alg=1), dict(net_alg=2), dict(net_balance=True, policy=1),
+                                dict(net_balance=True, policy=2), dict(net_balance=True, policy=3),
+                                dict(net_balance=True, policy=2, chunk=5)], ids=str)
+def test_net_variants_valid_and_bounded(kw):
+    for mask in (1, 0b11, 0b101):
+        g = synth.random_uniform(1500, 1200, 2, 14, 81)
+        r = oracle.bgpc(g, net_color_mask=mask, **kw)
+        assert r.status == oracle.OK
+        assert independent_violations(g, r.colors) == 0
+        assert r.rounds <= bin(mask).count("1") + g.n_a
+        assert len(np.unique(r.colors)) >= max_net_size(g)
+    adj = synth.rmat(9, 6, 0.57, 0.19, 0.19, seed=9)
+    r = oracle.d2gc(adj, net_color_mask=1, **kw)
+    assert r.status == oracle.OK and independent_violations(adj, r.colors) == 0
+
+
+def test_net_balance_first_fit_policy_is_plain_reverse_rejected():
+    """net_balance only selects a policy's net-based form; combined with an
+    Algorithm 6 variant the call is rejected."""
+    g = synth.from_nets(5, E1_NETS)
+    assert oracle.bgpc(g, net_color_mask=1, net_balance=True, net_alg=1).status == oracle.E_INVALID
