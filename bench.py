@@ -54,11 +54,19 @@ def parse():
                    help="batch4096: skip the one-call-per-graph leg (about three minutes)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="first copy 256 MiB device to device (a kernel of known traffic for HBM counters)")
+    p.add_argument("--counter-run", action="store_true",
+                   help="stencil128: one plain call and exit (the program the rocprofv3 --pmc passes profile)")
+    p.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "WORKLOAD"),
+                   help="no GPU: read the FETCH_SIZE and WRITE_SIZE counter CSVs of two --counter-run passes "
+                        "and write the calibrated per-kernel bytes into profiles/traffic.json")
     return p.parse_args()
 
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the coloring of one graph "
               "is not sharded across GPUs in this build", file=sys.stderr)
@@ -87,13 +95,18 @@ def main():
     out = torch.empty(g.n_a, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
 
-    def step(prof=None):
+    def step(prof=None, log_cap=0):
         r = bgpc.bgpc_color(A, B, None, out, net_color_mask=wl["mask"], policy=wl["policy"], stream=stream,
-                            prof=prof)
+                            prof=prof, log_cap=log_cap)
         if r.status != 0:
             raise RuntimeError(f"bgpc_color failed: {bgpc.status_string(r.status)}")
         return r
 
+    if args.counter_run:
+        step()
+        torch.cuda.synchronize()
+        print(json.dumps({"counter_run": args.workload}), flush=True)
+        return
     for _ in range(args.warmup):
         step()
     # dominant kernel: the one with the larger summed event time over a call
@@ -119,35 +132,49 @@ def main():
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1) / args.steps
 
+    # one more call with HIP events between its rounds (per-round times)
+    rlog = step(log_cap=max(rounds, 1) + 8).log
+    round_us = np.asarray(rlog["round_ms"][:rounds], dtype=np.float64) * 1e3
+
     # K more calls with the dominant kernel's launches bracketed by HIP event
     # pairs on the call's stream inside the library (roofline)
-    prof_tot = {"launches": 0, "ms": 0.0, "bytes": 0.0, "bytes_scanned": 0.0}
-    ev2, ev3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev2.record(stream)
+    prof_tot = {"launches": 0, "ms": 0.0, "bytes": 0.0, "bytes_scanned": 0.0, "bytes_states": 0.0}
     for _ in range(args.steps):
         pr = bgpc.Profile(dom_kid, 0, 0.0, 0.0, 0.0)
         step(pr)
-        prof_tot["launches"] += pr.launches
-        prof_tot["ms"] += pr.ms
-        prof_tot["bytes"] += pr.bytes
-        prof_tot["bytes_scanned"] += pr.bytes_scanned
-    ev3.record(stream)
+        for k in prof_tot:
+            prof_tot[k] += getattr(pr, k)
     torch.cuda.synchronize()
-    ms_events = ev2.elapsed_time(ev3) / args.steps
 
     stats = bgpc.color_stats(out)
     value = g.nnz / (ms / 1e3)
-    avg_us = 1e3 * prof_tot["ms"] / max(1, prof_tot["launches"])
-    bytes_per_launch = prof_tot["bytes"] / max(1, prof_tot["launches"])
-    scanned_per_launch = prof_tot["bytes_scanned"] / max(1, prof_tot["launches"])
+    nl = max(1, prof_tot["launches"])
+    avg_us = 1e3 * prof_tot["ms"] / nl
+    bytes_per_launch = prof_tot["bytes"] / nl
     achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
+    traffic = measured_traffic(args.workload)
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                "frac": achieved / 8000.0, "traffic": measured_traffic(args.workload, dom_name),
+                "frac": achieved / 8000.0,
+                "traffic": (traffic or {}).get("kernels", {}).get(dom_name, {}).get("bytes_per_launch"),
                 "launches_per_step": prof_tot["launches"] / args.steps,
                 "avg_launch_us": avg_us, "algorithmic_bytes_per_launch": bytes_per_launch,
-                "scanned_bytes_per_launch": scanned_per_launch,
-                "scanned_GBps": scanned_per_launch / (avg_us * 1e-6) / 1e9,
-                "share_of_step": prof_tot["ms"] / args.steps / ms_events}
+                "algorithmic_bytes_formula": ("per net of the round: 8 + 8 * members (offsets; member ids and "
+                                              "states)" if dom_name == "k_conflict_small" else
+                                              "per entry 16 + 4 per incidence + 8 per distinct net mask"),
+                "scanned_bytes_per_launch": prof_tot["bytes_scanned"] / nl,
+                "scanned_GBps": prof_tot["bytes_scanned"] / nl / (avg_us * 1e-6) / 1e9,
+                "state_once_bytes_per_launch": prof_tot["bytes_states"] / nl,
+                "state_once_GBps": prof_tot["bytes_states"] / nl / (avg_us * 1e-6) / 1e9,
+                "share_of_step": prof_tot["ms"] / args.steps / ms}
+    hbm = None
+    if traffic:
+        call_bytes = sum(k["bytes_per_launch"] * k["launches_per_call"] for k in traffic["kernels"].values())
+        hbm = {"whole_call_bytes": call_bytes, "whole_call_GBps": call_bytes / (ms / 1e3) / 1e9,
+               "hbm_whole_call": call_bytes / (ms / 1e3) / 8e12,
+               "round0_bytes": traffic.get("round0_bytes"), "round0_us": float(round_us[0]) if rounds else None,
+               "hbm_round0": (traffic["round0_bytes"] / (round_us[0] * 1e-6) / 8e12
+                              if rounds and traffic.get("round0_bytes") else None),
+               "source": "profiles/traffic.json (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated on a copy)"}
 
     line = {
         "metric": "BGPC nnz/s at 1 GPU & colors vs seq greedy; batched graphs/s + p99 latency",
@@ -157,7 +184,6 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
-        "ms_per_step_with_kernel_events": ms_events,
         "wall_s_timed": wall,
         "higher_is_better": True,
         "scaling": "weak",
@@ -169,7 +195,12 @@ def main():
         "rounds": rounds,
         "colors": stats["n_distinct"],
         "max_net_size": int(np.diff(g.b_off).max()),
+        "round_us": {"median": float(np.median(round_us)) if rounds else None,
+                     "round0": float(round_us[0]) if rounds else None,
+                     "max": float(round_us.max()) if rounds else None,
+                     "sum_ms": float(round_us.sum() / 1e3)},
         "roofline": roofline,
+        "hbm": hbm,
         "kernel_ms_per_call": {k: v[1] for k, v in kernel_ms.items()},
     }
     if not args.no_cpu_baseline:
@@ -283,33 +314,6 @@ def generate_batch(n):
         return list(pool.imap(_gen, range(n), chunksize=8))
 
 
-def batch_route(g):
-    """Route of one graph in bgpc_color_batch, restated from the library's
-    rule: 'dense' (conflict matrix), 'forbidden_bitmaps', 'net_masks', or
-    'whole_device' (bgpc_color on a second stream)."""
-    import numpy as np
-    sizes = np.diff(np.asarray(g.b_off, dtype=np.int64))
-    walk = float((sizes ** 2).sum())
-    heavy = walk > 128.0 * g.n_a or walk > 4.0 * g.n_a * g.n_a
-    if g.n_a > 0 and heavy and g.n_a <= 16384:
-        return "dense"
-    per = np.repeat(np.arange(g.n_a), np.diff(np.asarray(g.a_off, dtype=np.int64)))
-    wmax = int(np.bincount(per, weights=sizes[g.a_idx], minlength=g.n_a).max()) if g.n_a else 0
-    cap = min(wmax + 2, g.n_a + 1)
-    forb = g.n_a > 0 and heavy and g.n_a * ((cap + 31) // 32) * 4 <= (64 << 20)
-    if (forb and g.nnz > 50000) or g.nnz > 1000000:
-        return "whole_device"
-    return "forbidden_bitmaps" if forb else "net_masks"
-
-
-def batch_modes(graphs):
-    """How many graphs take each route of the batched call."""
-    out = {"dense": 0, "forbidden_bitmaps": 0, "net_masks": 0, "whole_device": 0}
-    for g in graphs:
-        out[batch_route(g)] += 1
-    return out
-
-
 def run_batch(args, wl):
     """Batched graphs/s (one persistent launch) vs plain per-graph calls, and
     p50 / p99 latency of a Poisson request stream through the serving loop."""
@@ -333,8 +337,13 @@ def run_batch(args, wl):
     outs = [torch.empty(g.n_a, dtype=torch.int32, device=dev) for g in graphs]
     total_nnz = sum(g.nnz for g in graphs)
     stream = torch.cuda.current_stream()
-    # batched
-    st, statuses, rounds = bgpc.bgpc_color_batch(devg, outs, stream=stream)
+    # batched (the first call also reports the route each graph took)
+    st, statuses, rounds, routes = bgpc.bgpc_color_batch(devg, outs, stream=stream, with_routes=True)
+    route_names = {bgpc.ROUTE_NET_MASKS: "net_masks", bgpc.ROUTE_BITMAPS: "forbidden_bitmaps",
+                   bgpc.ROUTE_DENSE: "dense", bgpc.ROUTE_WHOLE_DEVICE: "whole_device"}
+    by_route = {v: 0 for v in route_names.values()}
+    for rt in routes:
+        by_route[route_names[rt]] += 1
     if st != 0:
         raise RuntimeError(f"bgpc_color_batch failed: {bgpc.status_string(st)}")
     torch.cuda.synchronize()
@@ -426,7 +435,7 @@ def run_batch(args, wl):
         "nnz_per_s_batched": total_nnz / (ms_batch / 1e3),
         "plain_graphs_per_s": n / (ms_plain / 1e3) if ms_plain else None, "plain_ms_all": ms_plain,
         "batched_over_plain": ms_plain / ms_batch if ms_plain else None,
-        "graphs_by_mode": batch_modes(graphs),
+        "graphs_by_route": by_route,
         "serve": serves[0], "serve_rates": serves,
         "identical": {"plain_vs_batched": None if same_plain is None else bool(same_plain),
                       "served_vs_batched": bool(same_served)},
@@ -447,38 +456,156 @@ def run_batch(args, wl):
     print(json.dumps(line), flush=True)
 
 
-def measured_traffic(workload, kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
-    when the kernel sources changed since those counters were taken."""
+def _kernel_sources_sha():
     import hashlib
+    h = hashlib.sha256()
+    for p in ("paper_1701_02628_amd/csrc/kernels.h", "paper_1701_02628_amd/csrc/common.h"):
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """Calibrated HBM bytes per launch and launches per call of each kernel
+    (and round 0's bytes) from the committed rocprofv3 counter passes, or
+    None when the kernel sources changed since those counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    h = hashlib.sha256()
-    for p in ("paper_1701_02628_amd/csrc/kernels.h", "paper_1701_02628_amd/csrc/common.h"):
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
-    if h.hexdigest() != rec.get("kernel_sources_sha256"):
+    if rec.get("kernel_sources_sha256") != _kernel_sources_sha():
         return None
-    return rec.get(workload, {}).get(kernel)
+    return rec.get(workload)
+
+
+def _read_counter_csv(d):
+    """(kernel name, counter value) per dispatch, in dispatch order, from the
+    counter_collection CSV(s) under directory d."""
+    import csv
+    import glob
+    rows = []
+    for path in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                did = int(r.get("Dispatch_Id") or r.get("Correlation_Id") or len(rows))
+                rows.append((did, r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    merged = {}
+    for did, name, val in rows:   # one row per counter instance: sum per dispatch
+        if did in merged:
+            merged[did] = (name, merged[did][1] + val)
+        else:
+            merged[did] = (name, val)
+    return [merged[k] for k in sorted(merged)]
+
+
+def _short(name):
+    import re
+    m = re.search(r"(k_[A-Za-z0-9_]+)", name)
+    return m.group(1) if m else name.split("(")[0]
+
+
+def summarize_counters(fetch_dir, write_dir, workload):
+    """Per-kernel calibrated HBM bytes of one --counter-run call.
+
+    FETCH_SIZE and WRITE_SIZE are in KiB per dispatch.  The 256 MiB
+    device-to-device copy dispatched first (--copy-calibration) moves 256 MiB
+    each way; the ratio of that to what the counters report is the
+    calibration factor of each counter.  Round 0 is every dispatch from the
+    first coloring launch through the first compaction launch."""
+    fetch, write = _read_counter_csv(fetch_dir), _read_counter_csv(write_dir)
+    if len(fetch) != len(write) or not fetch:
+        raise SystemExit(f"dispatch lists differ or are empty ({len(fetch)} vs {len(write)})")
+    cal = [i for i, (n, _) in enumerate(fetch) if "copyBuffer" in n or "copy" in n.lower()]
+    if not cal:
+        raise SystemExit("no calibration copy among the dispatches (run with --copy-calibration)")
+    c = cal[0]
+    mib256 = 256.0 * 1024.0   # KiB
+    f_read, f_write = mib256 / fetch[c][1], mib256 / write[c][1]
+    kernels = {}
+    round0, in_r0, seen_color = 0.0, False, False
+    for i, ((name, fv), (_, wv)) in enumerate(zip(fetch, write)):
+        if i in cal:
+            continue
+        k = _short(name)
+        b = 1024.0 * (fv * f_read + wv * f_write)
+        e = kernels.setdefault(k, {"bytes_total": 0.0, "launches_per_call": 0})
+        e["bytes_total"] += b
+        e["launches_per_call"] += 1
+        if k.startswith("k_vcolor") or k.startswith("k_ncolor"):
+            if not seen_color:
+                in_r0 = True
+            seen_color = True
+        if in_r0:
+            round0 += b
+            if k == "k_compact":
+                in_r0 = False
+    for e in kernels.values():
+        e["bytes_per_launch"] = e.pop("bytes_total") / e["launches_per_call"]
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    rec = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            rec = json.load(f)
+    if rec.get("kernel_sources_sha256") != _kernel_sources_sha():
+        rec = {}
+    rec["about"] = ("HBM bytes per launch and launches per call of one bgpc_color call, from two rocprofv3 "
+                    "--pmc passes (FETCH_SIZE, then WRITE_SIZE) of bench.py --counter-run --copy-calibration, "
+                    "calibrated on the 256 MiB copy; valid while the kernel sources hash to "
+                    "kernel_sources_sha256")
+    rec["kernel_sources_sha256"] = _kernel_sources_sha()
+    rec[workload] = {"calibration": {"read_factor": f_read, "write_factor": f_write},
+                     "kernels": kernels, "round0_bytes": round0}
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    print(json.dumps(rec[workload], indent=1))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline(g, wl, gpu_colors):
-    """The oracle (plain C, OpenMP on the host cores) on the same workload."""
+    """The oracle (plain C, OpenMP on the host cores) on the same workload;
+    then on one core over the first R rounds (R doubled until 5 s)."""
     import numpy as np
 
     import oracle
+    cores = oracle.num_threads()
     t0 = time.perf_counter()
     ref = oracle.bgpc(g, net_color_mask=wl["mask"], policy=wl["policy"])
     dt = time.perf_counter() - t0
     t1 = time.perf_counter()
     seq = oracle.seq_greedy(g)
     dt_seq = time.perf_counter() - t1
-    return {"value": g.nnz / dt, "unit": "nnz/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "the whole workload, one call", "seconds": dt,
+    oracle.set_threads(1)
+    R, dt1 = 1, 0.0
+    try:
+        while True:
+            t2 = time.perf_counter()
+            oracle.bgpc(g, net_color_mask=wl["mask"], policy=wl["policy"], max_rounds=R)
+            dt1 = time.perf_counter() - t2
+            if dt1 >= 5.0 or R >= ref.rounds:
+                break
+            R *= 2
+    finally:
+        oracle.set_threads(cores)
+    t3 = time.perf_counter()
+    oracle.bgpc(g, net_color_mask=wl["mask"], policy=wl["policy"], max_rounds=R)
+    dtR = time.perf_counter() - t3
+    return {"value": g.nnz / dt, "unit": "nnz/s", "cores": cores, "kind": "oracle",
+            "sample": "the whole workload, one call", "seconds": dt, "cpu_model": _cpu_model(),
             "rounds": ref.rounds, "matches_gpu": bool(np.array_equal(ref.colors, gpu_colors)),
+            "one_core": {"rounds": R, "seconds": dt1, "seconds_same_rounds_all_cores": dtR,
+                         "sample": f"the first {R} of {ref.rounds} rounds on one thread"},
             "seq_greedy_colors": int(len(np.unique(seq))), "seq_greedy_seconds_1core": dt_seq}
 
 

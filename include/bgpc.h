@@ -93,8 +93,31 @@ enum {
 enum {
     BGPC_STRICT = 1u,      /* validate sortedness, transpose / symmetry before coloring */
     BGPC_RESUME = 2u,      /* colors_out holds a conflict-free partial coloring to continue from */
-    BGPC_INCREMENTAL = 4u  /* first-fit vertex rounds recompute only the vertices whose neighbourhood
+    BGPC_INCREMENTAL = 4u, /* first-fit vertex rounds recompute only the vertices whose neighbourhood
                               changed (same results; pays off when few proposals change per round) */
+    BGPC_NET_BALANCE = 8u  /* net-based rounds choose by opts->policy (Section V: the balancing
+                              heuristics "are also similar" for nets): Algorithm 8's first pass
+                              gathers F from the colored members, then every uncolored member in
+                              adjacency order takes the policy's pick from F (B1's parity is the
+                              net id's), each pick joining F; the policy state runs through `chunk`
+                              consecutive net ids and restarts every round.  Requires
+                              net_alg == BGPC_NET_ALG8.  Colors of such rounds can exceed the
+                              largest net; BGPC_E_UNSUPPORTED when a net's picks pass the LDS
+                              bitmap (about 440,000 colors) */
+};
+
+/* net-based coloring variants (opts->net_alg), Section III */
+enum {
+    BGPC_NET_ALG8 = 0,          /* Algorithm 8: first pass over the net gathers the colored members'
+                                   colors, then reverse first-fit from |vtxs(v)| - 1 (distance-2:
+                                   |nbor(v)|, Algorithm 9) for the uncolored members */
+    BGPC_NET_ALG6 = 1,          /* Algorithm 6: one pass in adjacency order; a colored member adds its
+                                   color to F, an uncolored one takes the smallest color at or above
+                                   the previous pick not in F.  A colored member whose color an earlier
+                                   member was just given keeps it this round (snapshot colors) and is
+                                   evicted by the removal step (the earlier member ranks lower) */
+    BGPC_NET_ALG6_REVERSE = 2   /* Algorithm 6 with the reverse start: the same single pass, picks
+                                   going down from |vtxs(v)| - 1 */
 };
 
 /*
@@ -104,6 +127,12 @@ enum {
  * the losers of its removal step, how many of them were colored before the
  * round ("evicted"; only net-based rounds after the first can evict), and the
  * largest color present after the round.  `n` receives the rounds recorded.
+ * hash_t / hash_c: FNV-1a-64 over the little-endian bytes of the int32 array
+ * of tentative colors t (every vertex's color after the round's coloring
+ * step: its proposal, its color, or -1) and of the colors after the round,
+ * both indexed by rank; asking for either makes every round wait for the host
+ * (diagnostics, not for timing).  round_ms: device time of each round,
+ * from HIP events recorded between rounds on opts->stream.
  */
 typedef struct {
     int32_t cap;
@@ -113,15 +142,21 @@ typedef struct {
     int64_t *losers;
     int64_t *evicted;
     int32_t *max_color;
+    uint64_t *hash_t;
+    uint64_t *hash_c;
+    float *round_ms;
 } bgpc_round_log;
 
 /*
  * Optional kernel timing: when opts->prof is set, the driver records a HIP
  * event pair on opts->stream around every launch of the kernel named by
  * `kernel` and returns the summed event time, the number of launches and the
- * algorithmic bytes those launches had to move: the compulsory streams only
- * (row offsets and ids of every row the launch walks, each vertex state or
- * net mask once, the proposals written), never cache re-reads.
+ * algorithmic bytes those launches had to move, compulsory streams only,
+ * never cache re-reads.  Removal (net form, Algorithm 7): per net of the
+ * round -- a net with a member uncolored or proposing -- 8 bytes (its two
+ * offsets) plus 8 per member (its id and its state).  Coloring: per worklist
+ * entry 16 bytes (id, two row offsets, proposal), 4 per incidence (net id),
+ * 8 per distinct net mask.
  */
 enum {
     BGPC_PROF_CONFLICT = 0,   /* net-side removal scan of small nets */
@@ -136,6 +171,9 @@ typedef struct {
     double bytes_scanned;     /* out: the same figure over the nets the removal scan actually read
                                  (vertex-based rounds re-scan only nets whose members changed their
                                  proposals; equal to bytes for the coloring kernel) */
+    double bytes_states;      /* out: removal counted with one offset and the member ids per net and
+                                 every member state read once per round (at most |V_A| states);
+                                 equal to bytes for the coloring kernel */
 } bgpc_profile;
 
 typedef struct {
@@ -150,9 +188,20 @@ typedef struct {
     bgpc_round_log *log;      /* optional */
     int32_t *rounds_out;      /* optional, host: rounds run */
     bgpc_profile *prof;       /* optional kernel timing */
+    uint64_t net_conflict_mask;  /* bit r (r < 64; later rounds follow bit 63) set: round r finds its
+                                    losers net by net (Algorithm 7's form); clear: vertex by vertex
+                                    over the worklist (Algorithm 5's form: each worklist vertex walks
+                                    its distance-2 neighbourhood for a lower-ranked holder of its
+                                    color).  Speed only: both forms give the same losers wherever the
+                                    vertex form is used, which is a vertex-based round or a net-based
+                                    first round without BGPC_RESUME; elsewhere the net form runs
+                                    whatever the bit.  Default all ones */
+    int32_t net_alg;          /* BGPC_NET_ALG8 (default), BGPC_NET_ALG6, BGPC_NET_ALG6_REVERSE */
+    int32_t reserved2;
 } bgpc_opts;
 
-/* Fills *opts with the defaults: vertex-based first-fit rounds, chunk 64. */
+/* Fills *opts with the defaults: vertex-based first-fit rounds, chunk 64,
+ * net-side removal, Algorithm 8 in net-based rounds. */
 BGPC_API void bgpc_opts_default(bgpc_opts *opts);
 
 /*
@@ -226,10 +275,14 @@ typedef struct {
 BGPC_API int color_stats(const int32_t *colors, int64_t n, void *stream, bgpc_stats *out);
 
 /*
- * Batched coloring: many independent bipartite graphs, the vertex-based
- * first-fit rounds of Algorithm 1 for each (other options return
- * BGPC_E_UNSUPPORTED).  Every graph's colors and rounds equal what
- * bgpc_color returns for it alone.  A shape pass on the device measures each
+ * Batched coloring: many independent graphs.  Every graph's colors and rounds
+ * equal what bgpc_color (d2gc_color for d2gc items) returns for it alone with
+ * the same options and order.  Items with the default options (vertex-based
+ * first-fit rounds, flags 0 or BGPC_STRICT), no order and no d2gc share the
+ * persistent launch described next; every other item, and every item when
+ * opts asks for anything else (net-based rounds, a balancing policy,
+ * BGPC_RESUME, Algorithm 6, vertex-form removal), takes the whole-device
+ * route.  A shape pass on the device measures each
  * graph (and checks its arrays, below); then one persistent launch gives whole
  * graphs, largest first, to workgroups that run all of a graph's rounds.  Per
  * graph the workgroup keeps per-net masks of colors 0..127 (sparse graphs),
@@ -239,9 +292,10 @@ BGPC_API int color_stats(const int32_t *colors, int64_t n, void *stream, bgpc_st
  * device (more than 10^6 memberships, or colors past 127 on more than 16384
  * vertices with more than 5 * 10^4 memberships) are colored by bgpc_color on
  * three more streams (one host thread each) while the launch runs.
- *   items    host array; csr_A / csr_B / colors_out device pointers as in
- *            bgpc_color; status and rounds are written per item
- *   opts     NULL or: stream, max_rounds (per graph), flags 0 or BGPC_STRICT
+ *   items    host array; csr_A / csr_B / colors_out / order device pointers
+ *            as in bgpc_color; status, rounds and route are written per item
+ *   opts     NULL or the options of bgpc_color (log and prof are ignored;
+ *            max_rounds applies per graph)
  * Checks: offsets start at 0, never decrease and end at nnz, indices in range
  * (else BGPC_E_INVALID for the batch, that item's status BGPC_E_INVALID and
  * nothing colored).  The two CSRs must be transposes of each other, with
@@ -251,12 +305,23 @@ BGPC_API int color_stats(const int32_t *colors, int64_t n, void *stream, bgpc_st
  * the graphs exceeds half of the free device memory.
  */
 typedef struct {
-    bgpc_csr csr_A;
+    bgpc_csr csr_A;       /* d2gc items: the symmetric adjacency (csr_B is ignored) */
     bgpc_csr csr_B;
     int32_t *colors_out;
     int32_t status;       /* out */
     int32_t rounds;       /* out */
+    const int32_t *order; /* NULL or a device permutation, as for bgpc_color */
+    int32_t d2gc;         /* nonzero: distance-2 coloring of csr_A (as d2gc_color) */
+    int32_t route;        /* out: BGPC_ROUTE_* the item took */
 } bgpc_batch_item;
+
+/* bgpc_batch_item.route */
+enum {
+    BGPC_ROUTE_NET_MASKS = 0,     /* persistent launch, per-net masks of colors 0..127 */
+    BGPC_ROUTE_BITMAPS = 1,       /* persistent launch, per-vertex forbidden-color bitmaps */
+    BGPC_ROUTE_DENSE = 2,         /* persistent launch, conflict bit matrix */
+    BGPC_ROUTE_WHOLE_DEVICE = 3   /* bgpc_color / d2gc_color on a side stream */
+};
 
 BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items, const bgpc_opts *opts);
 

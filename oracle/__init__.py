@@ -57,6 +57,8 @@ def _load():
         lib.oracle_color_stats.argtypes = [P, i64, P, P]
         lib.oracle_color_stats.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = None
         _lib = lib
     return _lib
 
@@ -75,6 +77,11 @@ def _c32(a):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (0 leaves them)."""
+    _load().oracle_set_threads(int(n))
 
 
 # ---------------------------------------------------------------------------

@@ -861,3 +861,9 @@ int oracle_color_stats(const int32_t *colors, int64_t n, int64_t *out_i, double 
 }
 
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+
+/* threads of the parallel loops from now on (the CPU-baseline timings) */
+void oracle_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+}

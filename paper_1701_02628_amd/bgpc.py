@@ -19,7 +19,10 @@ OK = 0
 E_INVALID, E_UNSORTED, E_NOT_TRANSPOSE, E_NOT_SYMMETRIC = -1, -2, -3, -4
 E_OOM, E_NOT_CONVERGED, E_HIP, E_UNSUPPORTED, E_INTERNAL = -5, -6, -7, -8, -9
 FIRST_FIT, B1, B2, B1_GLOBAL = 0, 1, 2, 3
-STRICT, RESUME = 1, 2
+STRICT, RESUME, NET_BALANCE = 1, 2, 8
+NET_ALG8, NET_ALG6, NET_ALG6_REVERSE = 0, 1, 2
+ROUTE_NET_MASKS, ROUTE_BITMAPS, ROUTE_DENSE, ROUTE_WHOLE_DEVICE = 0, 1, 2, 3
+ALL_NET = 2 ** 64 - 1
 
 
 class Csr(ctypes.Structure):
@@ -30,12 +33,13 @@ class Csr(ctypes.Structure):
 class RoundLog(ctypes.Structure):
     _fields_ = [("cap", ctypes.c_int32), ("n", ctypes.c_int32), ("mode", ctypes.c_void_p),
                 ("w_size", ctypes.c_void_p), ("losers", ctypes.c_void_p), ("evicted", ctypes.c_void_p),
-                ("max_color", ctypes.c_void_p)]
+                ("max_color", ctypes.c_void_p), ("hash_t", ctypes.c_void_p), ("hash_c", ctypes.c_void_p),
+                ("round_ms", ctypes.c_void_p)]
 
 
 class Profile(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("launches", ctypes.c_int32), ("ms", ctypes.c_double),
-                ("bytes", ctypes.c_double), ("bytes_scanned", ctypes.c_double)]
+                ("bytes", ctypes.c_double), ("bytes_scanned", ctypes.c_double), ("bytes_states", ctypes.c_double)]
 
 
 PROF_CONFLICT, PROF_COLOR = 0, 1
@@ -46,12 +50,14 @@ class Opts(ctypes.Structure):
     _fields_ = [("net_color_mask", ctypes.c_uint64), ("policy", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("start_round", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p), ("log", ctypes.POINTER(RoundLog)),
-                ("rounds_out", ctypes.POINTER(ctypes.c_int32)), ("prof", ctypes.POINTER(Profile))]
+                ("rounds_out", ctypes.POINTER(ctypes.c_int32)), ("prof", ctypes.POINTER(Profile)),
+                ("net_conflict_mask", ctypes.c_uint64), ("net_alg", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 class BatchItem(ctypes.Structure):
     _fields_ = [("csr_A", Csr), ("csr_B", Csr), ("colors_out", ctypes.c_void_p), ("status", ctypes.c_int32),
-                ("rounds", ctypes.c_int32)]
+                ("rounds", ctypes.c_int32), ("order", ctypes.c_void_p), ("d2gc", ctypes.c_int32),
+                ("route", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -184,11 +190,14 @@ class Result:
         return f"Result(status={self.status}, rounds={self.rounds})"
 
 
-def _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags, stream, log_cap, prof=None):
+def _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags, stream, log_cap, prof=None,
+               net_conflict_mask=ALL_NET, net_alg=NET_ALG8, log_hashes=False):
     lib = load()
     o = Opts()
     lib.bgpc_opts_default(ctypes.byref(o))
     o.net_color_mask = int(net_color_mask) & (2 ** 64 - 1)
+    o.net_conflict_mask = int(net_conflict_mask) & (2 ** 64 - 1)
+    o.net_alg = int(net_alg)
     o.policy, o.chunk, o.max_rounds = int(policy), int(chunk), int(max_rounds)
     o.start_round, o.flags = int(start_round), int(flags)
     o.stream = _stream_handle(stream)
@@ -199,10 +208,15 @@ def _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags, st
     if log_cap:
         log_arrays = {"mode": np.zeros(log_cap, np.int32), "w": np.zeros(log_cap, np.int64),
                       "losers": np.zeros(log_cap, np.int64), "evicted": np.zeros(log_cap, np.int64),
-                      "max_color": np.zeros(log_cap, np.int32)}
+                      "max_color": np.zeros(log_cap, np.int32), "round_ms": np.zeros(log_cap, np.float32)}
+        if log_hashes:
+            log_arrays["hash_t"] = np.zeros(log_cap, np.uint64)
+            log_arrays["hash_c"] = np.zeros(log_cap, np.uint64)
+        hp = (lambda k: log_arrays[k].ctypes.data if k in log_arrays else None)
         lg = RoundLog(log_cap, 0, log_arrays["mode"].ctypes.data, log_arrays["w"].ctypes.data,
                       log_arrays["losers"].ctypes.data, log_arrays["evicted"].ctypes.data,
-                      log_arrays["max_color"].ctypes.data)
+                      log_arrays["max_color"].ctypes.data, hp("hash_t"), hp("hash_c"),
+                      log_arrays["round_ms"].ctypes.data)
         o.log = ctypes.pointer(lg)
         keep.append(lg)
     if prof is not None:
@@ -220,12 +234,13 @@ def _finish(status, rounds, log_arrays, o):
 
 
 def bgpc_color(csr_A: DeviceCsr, csr_B: DeviceCsr, order, colors_out, net_color_mask=0, policy=FIRST_FIT,
-               chunk=64, max_rounds=0, start_round=0, flags=0, stream=None, log_cap=0, prof=None) -> Result:
+               chunk=64, max_rounds=0, start_round=0, flags=0, stream=None, log_cap=0, prof=None,
+               net_conflict_mask=ALL_NET, net_alg=NET_ALG8, log_hashes=False) -> Result:
     """Bipartite-graph partial coloring; colors_out is an int32 GPU tensor of |V_A|.
     prof: optional Profile struct (kernel timing), filled in place."""
     lib = load()
     o, rounds, log_arrays, keep = _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags,
-                                             stream, log_cap, prof)
+                                             stream, log_cap, prof, net_conflict_mask, net_alg, log_hashes)
     a, b = csr_A.as_struct(), csr_B.as_struct()
     order_p = _dev_ptr(order, "order") if order is not None else None
     st = lib.bgpc_color(ctypes.byref(a), ctypes.byref(b), order_p, ctypes.byref(o), _dev_ptr(colors_out, "colors_out"))
@@ -234,11 +249,12 @@ def bgpc_color(csr_A: DeviceCsr, csr_B: DeviceCsr, order, colors_out, net_color_
 
 
 def d2gc_color(adj: DeviceCsr, order, colors_out, net_color_mask=0, policy=FIRST_FIT, chunk=64, max_rounds=0,
-               start_round=0, flags=0, stream=None, log_cap=0, prof=None) -> Result:
+               start_round=0, flags=0, stream=None, log_cap=0, prof=None, net_conflict_mask=ALL_NET,
+               net_alg=NET_ALG8, log_hashes=False) -> Result:
     """Distance-2 coloring of a symmetric graph; colors_out is an int32 GPU tensor of n."""
     lib = load()
     o, rounds, log_arrays, keep = _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags,
-                                             stream, log_cap, prof)
+                                             stream, log_cap, prof, net_conflict_mask, net_alg, log_hashes)
     a = adj.as_struct()
     order_p = _dev_ptr(order, "order") if order is not None else None
     st = lib.d2gc_color(ctypes.byref(a), order_p, ctypes.byref(o), _dev_ptr(colors_out, "colors_out"))
@@ -284,23 +300,35 @@ def color_stats(colors, stream=None) -> dict:
             "card_mean": out.card_mean, "card_std": out.card_std}
 
 
-def bgpc_color_batch(graphs, colors, max_rounds=0, stream=None):
-    """Color many graphs in one persistent launch.
+def bgpc_color_batch(graphs, colors, max_rounds=0, stream=None, orders=None, with_routes=False, **opts):
+    """Color many graphs in one call.
 
-    graphs: list of (csr_A, csr_B) DeviceCsr pairs; colors: list of int32 GPU
-    tensors (|V_A| each).  Returns (status, per-item statuses, per-item rounds).
+    graphs: list of (csr_A, csr_B) DeviceCsr pairs, or a DeviceCsr adjacency
+    for a distance-2 item; colors: list of int32 GPU tensors; orders: None or
+    a list of None / int32 GPU permutations; opts: net_color_mask, policy,
+    chunk, flags, net_conflict_mask, net_alg as for bgpc_color.  Returns
+    (status, per-item statuses, per-item rounds[, per-item routes]).
     """
     lib = load()
     n = len(graphs)
     items = (BatchItem * max(n, 1))()
-    for i, ((A, B), c) in enumerate(zip(graphs, colors)):
-        items[i].csr_A = A.as_struct()
-        items[i].csr_B = B.as_struct()
+    for i, (gr, c) in enumerate(zip(graphs, colors)):
+        if isinstance(gr, DeviceCsr):
+            items[i].csr_A = gr.as_struct()
+            items[i].d2gc = 1
+        else:
+            items[i].csr_A = gr[0].as_struct()
+            items[i].csr_B = gr[1].as_struct()
         items[i].colors_out = _dev_ptr(c, "colors").value
-    o, rounds, _, keep = _make_opts(0, FIRST_FIT, 64, max_rounds, 0, 0, stream, 0)
+        if orders is not None and orders[i] is not None:
+            items[i].order = _dev_ptr(orders[i], "order").value
+    o, rounds, _, keep = _make_opts(opts.get("net_color_mask", 0), opts.get("policy", FIRST_FIT),
+                                    opts.get("chunk", 64), max_rounds, 0, opts.get("flags", 0), stream, 0,
+                                    None, opts.get("net_conflict_mask", ALL_NET), opts.get("net_alg", NET_ALG8))
     st = lib.bgpc_color_batch(items, n, ctypes.byref(o))
     del keep
-    return int(st), [items[i].status for i in range(n)], [items[i].rounds for i in range(n)]
+    out = (int(st), [items[i].status for i in range(n)], [items[i].rounds for i in range(n)])
+    return out + ([items[i].route for i in range(n)],) if with_routes else out
 
 
 class Session:

@@ -58,9 +58,24 @@ bool whole_device(const BatchItem &b)
 bool item_ok(const bgpc_batch_item &it)
 {
     const bgpc_csr &A = it.csr_A, &B = it.csr_B;
-    return A.n_rows >= 0 && A.n_cols >= 0 && A.n_rows < (1 << 30) && A.n_cols < (1 << 30) && A.nnz >= 0 &&
-           A.nnz < (1ll << 31) && A.n_rows == B.n_cols && A.n_cols == B.n_rows && A.nnz == B.nnz && A.offsets &&
-           B.offsets && (A.nnz == 0 || (A.indices && B.indices)) && (A.n_rows == 0 || it.colors_out);
+    const bool a_ok = A.n_rows >= 0 && A.n_cols >= 0 && A.n_rows < (1 << 30) && A.n_cols < (1 << 30) && A.nnz >= 0 &&
+                      A.nnz < (1ll << 31) && A.offsets && (A.nnz == 0 || A.indices) && (A.n_rows == 0 || it.colors_out);
+    if (it.d2gc) return a_ok && A.n_rows == A.n_cols;
+    return a_ok && A.n_rows == B.n_cols && A.n_cols == B.n_rows && A.nnz == B.nnz && B.offsets &&
+           (B.nnz == 0 || B.indices);
+}
+
+// the persistent launch runs the default schedule only: vertex-based
+// first-fit rounds from scratch, net-side removal
+bool default_schedule(const bgpc_opts &o)
+{
+    return o.policy == BGPC_FIRST_FIT && o.net_color_mask == 0 && !(o.flags & ~(uint32_t)BGPC_STRICT) &&
+           o.start_round == 0 && o.net_alg == BGPC_NET_ALG8 && o.net_conflict_mask == ~0ull;
+}
+
+int route_of(int mode)
+{
+    return mode == MODE_DENSE ? BGPC_ROUTE_DENSE : mode == MODE_FORB ? BGPC_ROUTE_BITMAPS : BGPC_ROUTE_NET_MASKS;
 }
 
 }  // namespace
@@ -134,28 +149,38 @@ extern "C" BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items
     if (opts) o = *opts;
     else bgpc_opts_default(&o);
     if (n_items < 0 || (n_items > 0 && !items)) return BGPC_E_INVALID;
-    if (o.policy != BGPC_FIRST_FIT || o.net_color_mask != 0 || (o.flags & ~(uint32_t)BGPC_STRICT) ||
-        o.start_round != 0)
-        return BGPC_E_UNSUPPORTED;   // the batched path runs vertex-based first-fit rounds
+    if (o.policy < 0 || o.policy > BGPC_B1_GLOBAL || o.chunk < 1 || o.max_rounds < 0 || o.start_round < 0 ||
+        o.net_alg < BGPC_NET_ALG8 || o.net_alg > BGPC_NET_ALG6_REVERSE)
+        return BGPC_E_INVALID;
     for (int i = 0; i < n_items; i++)
         if (!item_ok(items[i])) return BGPC_E_INVALID;
     if (n_items == 0) return BGPC_OK;
     hipStream_t s = (hipStream_t)o.stream;
+    // items the persistent launch cannot run (another schedule, a caller
+    // order, distance-2) take the whole-device route as they are
+    const bool dflt = default_schedule(o);
+    std::vector<char> forced(n_items);
+    for (int i = 0; i < n_items; i++) forced[i] = !dflt || items[i].order || items[i].d2gc;
 
     std::vector<BatchItem> h(n_items);
     for (int i = 0; i < n_items; i++) {
         const bgpc_batch_item &it = items[i];
         BatchItem &b = h[i];
         b = BatchItem{};
+        b.colors = it.colors_out;
+        b.status = -1;
+        if (forced[i]) {
+            // measured by nobody: an empty graph for the shape pass
+            b.a_off = b.b_off = it.csr_A.offsets;
+            continue;
+        }
         b.n_a = it.csr_A.n_rows;
         b.n_b = it.csr_B.n_rows;
         b.a_off = it.csr_A.offsets;
         b.a_idx = it.csr_A.indices;
         b.b_off = it.csr_B.offsets;
         b.b_idx = it.csr_B.indices;
-        b.colors = it.colors_out;
         b.max_rounds = o.max_rounds > 0 ? o.max_rounds : b.n_a + 65;
-        b.status = -1;
         b.nnz = (int)it.csr_A.nnz;
     }
     // largest graphs first
@@ -187,7 +212,7 @@ extern "C" BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items
             rc = BGPC_E_HIP;
     }
     for (int i = 0; i < n_items && rc == BGPC_OK; i++)
-        if (h[i].walk < 0) {
+        if (!forced[i] && h[i].walk < 0) {
             items[i].status = BGPC_E_INVALID;
             rc = BGPC_E_INVALID;
         }
@@ -198,7 +223,10 @@ extern "C" BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items
     }
     // the persistent launch takes the graphs in `order` minus the whole-device ones
     std::vector<int> big, queue;
-    for (int k = 0; k < n_items; k++) (whole_device(h[order[k]]) ? big : queue).push_back(order[k]);
+    for (int k = 0; k < n_items; k++)
+        (forced[order[k]] || whole_device(h[order[k]]) ? big : queue).push_back(order[k]);
+    for (int i = 0; i < n_items; i++) items[i].route = route_of(h[i].mode);
+    for (int i : big) items[i].route = BGPC_ROUTE_WHOLE_DEVICE;
     const int nq = (int)queue.size();
     // launches over consecutive runs of the (largest-first) queue whose
     // scratch fits the budget; each launch reuses the one scratch buffer
@@ -273,7 +301,8 @@ extern "C" BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items
                 po.prof = nullptr;
                 int32_t rr = 0;
                 po.rounds_out = &rr;
-                int st = bgpc_color(&it.csr_A, &it.csr_B, nullptr, &po, it.colors_out);
+                int st = it.d2gc ? d2gc_color(&it.csr_A, it.order, &po, it.colors_out)
+                                 : bgpc_color(&it.csr_A, &it.csr_B, it.order, &po, it.colors_out);
                 if (st != BGPC_OK && st != BGPC_E_NOT_CONVERGED) side_rc = st;
                 big_res[j] = {st, rr};
             }

@@ -223,6 +223,8 @@ int run(const RunArgs &a)
         if (start_round + r >= 0 && ((o.net_color_mask >> (start_round + r)) & 1ull)) any_net_round = true;
     const size_t sp_words = (size_t)((a.nnz + (D2 ? n_b : 0)) / 64 + 4);
     const long n_huge_cap = std::min<long>(n_b, (a.nnz + (D2 ? n_b : 0)) / (HASH_MAX + 1) + 1) + 1;
+    const bool inc_flag = (o.flags & BGPC_INCREMENTAL) != 0;
+    const long inc_a = inc_flag ? n_a : 0, inc_b = inc_flag ? n_b : 0;   // incremental lists and bit sets
     size_t bytes = aligned(n_a + 1, 4) * 4            // W[0], W[1], heavy, first-fit cursors
                    + aligned(n_a + 1, 1)              // lose
                    + aligned(n_b + 1, 8)              // mask0
@@ -236,10 +238,10 @@ int run(const RunArgs &a)
                    + aligned((size_t)prof_rounds * PROF_SLOTS * 4 + 1, 8)
                    + (any_net_round ? aligned(n_a + 1, 4) : 0)
                    + aligned(1, sizeof(IncCtrl))
-                   + aligned(n_a + 1, 4) * 4          // incremental lists D0, D1, A, winners
-                   + aligned(n_b + 1, 4) * 2          // nets with a changed proposal / a winner
-                   + aligned(n_a / 32 + 2, 4) * 2     // dirty, affected bit sets
-                   + aligned(n_b / 32 + 2, 4) * 2     // net bit sets
+                   + aligned(inc_a + 1, 4) * 4        // incremental lists D0, D1, A, winners
+                   + aligned(inc_b + 1, 4) * 2        // nets with a changed proposal / a winner
+                   + aligned(inc_a / 32 + 2, 4) * 2   // dirty, affected bit sets
+                   + aligned(inc_b / 32 + 2, 4) * 2   // net bit sets
                    + aligned(sp_words, 8)             // standing proposals: verdict bits
                    + aligned(n_a + 1, 4)              //   loss counts
                    + aligned(n_b + 1, 1);             //   dirty nets
@@ -262,15 +264,23 @@ int run(const RunArgs &a)
     unsigned long long *pcnt = ar.take<unsigned long long>((size_t)prof_rounds * PROF_SLOTS * 4 + 1);
     int *owner = any_net_round ? ar.take<int>(n_a + 1) : nullptr;
     IncCtrl *ic = ar.take<IncCtrl>(1);
-    int *Dl[2] = {ar.take<int>(n_a + 1), ar.take<int>(n_a + 1)};
-    int *Al = ar.take<int>(n_a + 1);
-    int *WINl = ar.take<int>(n_a + 1);
-    int *TCNl = ar.take<int>(n_b + 1);
-    int *CNl = ar.take<int>(n_b + 1);
-    unsigned *dirty_bits = ar.take<unsigned>(n_a / 32 + 2);
-    unsigned *aff_bits = ar.take<unsigned>(n_a / 32 + 2);
-    unsigned *tchg_bits = ar.take<unsigned>(n_b / 32 + 2);
-    unsigned *cn_bits = ar.take<unsigned>(n_b / 32 + 2);
+    int *Dl[2] = {ar.take<int>(inc_a + 1), ar.take<int>(inc_a + 1)};
+    int *Al = ar.take<int>(inc_a + 1);
+    int *WINl = ar.take<int>(inc_a + 1);
+    int *TCNl = ar.take<int>(inc_b + 1);
+    int *CNl = ar.take<int>(inc_b + 1);
+    unsigned *dirty_bits = ar.take<unsigned>(inc_a / 32 + 2);
+    unsigned *aff_bits = ar.take<unsigned>(inc_a / 32 + 2);
+    unsigned *tchg_bits = ar.take<unsigned>(inc_b / 32 + 2);
+    unsigned *cn_bits = ar.take<unsigned>(inc_b / 32 + 2);
+    // clears the incremental rounds' bit sets (opt-in)
+    auto clear_inc_bits = [&]() {
+        if (!inc_flag) return;
+        k_fill_i32<<<grid_for(n_a / 32 + 2, 256, 1024), 256, 0, s>>>((int *)dirty_bits, 0, n_a / 32 + 2);
+        k_fill_i32<<<grid_for(n_a / 32 + 2, 256, 1024), 256, 0, s>>>((int *)aff_bits, 0, n_a / 32 + 2);
+        k_fill_i32<<<grid_for(n_b / 32 + 2, 256, 1024), 256, 0, s>>>((int *)tchg_bits, 0, n_b / 32 + 2);
+        k_fill_i32<<<grid_for(n_b / 32 + 2, 256, 1024), 256, 0, s>>>((int *)cn_bits, 0, n_b / 32 + 2);
+    };
     unsigned long long *sp_bits = ar.take<unsigned long long>(sp_words);
     int *sp_cnt = ar.take<int>(n_a + 1);
     uint8_t *sp_dirty = ar.take<uint8_t>(n_b + 1);
@@ -309,7 +319,22 @@ int run(const RunArgs &a)
     // They pay where a coloring front sweeps many nets round after round (on
     // 2^21 stencil nets: 12% per call); on graphs of 10^4-10^5 nets the
     // bookkeeping costs about as much as it saves, so smaller graphs go without
-    const bool sp_on = !(o.flags & BGPC_INCREMENTAL) && n_b >= (1 << 20);
+    const bool sp_on = !(o.flags & BGPC_INCREMENTAL) && n_b >= (1 << 20) && o.net_conflict_mask == ~0ull;
+    // removal form of round r: the vertex form (Algorithm 5) where its bit is
+    // clear and it is exact -- a vertex-based round, or a net-based first
+    // round that starts with nothing colored -- else the net form
+    auto vertex_form = [&](int r, bool net_mode) {
+        const int bit = std::min(start_round + r, 63);
+        if ((o.net_conflict_mask >> bit) & 1ull) return false;
+        return !net_mode || (r == 0 && !resume);
+    };
+    const bool net_bal = (o.flags & BGPC_NET_BALANCE) != 0;
+    // diagnostics of the round log: FNV-1a hashes (rounds wait for the host)
+    // and per-round event times
+    const bool hash_mode = o.log && o.log->cap > 0 && (o.log->hash_t || o.log->hash_c);
+    int *h_states = nullptr;
+    std::vector<hipEvent_t> round_ev;
+    const bool time_rounds = o.log && o.log->cap > 0 && o.log->round_ms;
     bool sp_reset = true, sp_used = false;
     const SPState sp_none = {nullptr, nullptr, nullptr};
     const SPState sp_state = {sp_bits, sp_cnt, sp_dirty};
@@ -344,6 +369,7 @@ int run(const RunArgs &a)
         o.prof->ms = 0.0;
         o.prof->bytes = 0.0;
         o.prof->bytes_scanned = 0.0;
+        o.prof->bytes_states = 0.0;
     }
 #define PCNT(r) ((r) < prof_rounds ? pcnt + (size_t)(r) * PROF_SLOTS * 4 : nullptr)
     if (prof_rounds)
@@ -362,6 +388,41 @@ int run(const RunArgs &a)
             if (e1_) hipEventRecord(e1_, s);                      \
         }                                                         \
     } while (0)
+
+    // FNV-1a-64 of the int32 colors implied by the states: tentative (every
+    // proposal counts as a color) or snapshot (proposals count as -1)
+    auto hash_states = [&](int r, bool tentative) -> bool {
+        if (!hash_mode || r >= o.log->cap) return true;
+        uint64_t *dst = tentative ? o.log->hash_t : o.log->hash_c;
+        if (!dst) return true;
+        if (hipMemcpyAsync(h_states, st, sizeof(int) * (size_t)n_a, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return false;
+        uint64_t h = 0xcbf29ce484222325ull;
+        for (int i = 0; i < n_a; i++) {
+            const int v = h_states[i];
+            const int c = tentative ? (v < 0 ? -1 : (v & COLOR_MASK)) : ((v >= 0 && !(v & TENT)) ? v : -1);
+            const uint32_t u = (uint32_t)c;
+            for (int b = 0; b < 4; b++) {
+                h ^= (u >> (8 * b)) & 0xffu;
+                h *= 0x100000001b3ull;
+            }
+        }
+        dst[r] = h;
+        return true;
+    };
+    auto mark_round = [&]() {
+        if (!time_rounds || (int)round_ev.size() > o.log->cap) return;
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) == hipSuccess && hipEventRecord(e, s) == hipSuccess) round_ev.push_back(e);
+        else (void)hipGetLastError();
+    };
+    if (hash_mode && hipHostMalloc((void **)&h_states, sizeof(int) * ((size_t)n_a + 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        h_states = nullptr;
+        st_code = BGPC_E_OOM;
+        goto finish;
+    }
 
     // ---- shape of the graph: largest net, big nets, distance-2 bound
     k_fill_i32<<<1, 64, 0, s>>>(shape, 0, 8);
@@ -473,10 +534,7 @@ int run(const RunArgs &a)
         k_fill_u8<<<g_a, nthr, 0, s>>>(lose, 0, n_a + 1);
         k_fill_i32<<<g_a, nthr, 0, s>>>(ffc, 0, n_a + 1);
         k_fill_u8<<<g_b, nthr, 0, s>>>(done_net, 0, n_b + 1);
-        k_fill_i32<<<g_a, nthr, 0, s>>>((int *)dirty_bits, 0, n_a / 32 + 2);
-        k_fill_i32<<<g_a, nthr, 0, s>>>((int *)aff_bits, 0, n_a / 32 + 2);
-        k_fill_i32<<<g_b, nthr, 0, s>>>((int *)tchg_bits, 0, n_b / 32 + 2);
-        k_fill_i32<<<g_b, nthr, 0, s>>>((int *)cn_bits, 0, n_b / 32 + 2);
+        clear_inc_bits();
         if (!resume) {
             k_fill_i32<<<g_a, nthr, 0, s>>>(st, -1, n_a);
             k_iota<<<g_a, nthr, 0, s>>>(W0, n_a);
@@ -549,6 +607,11 @@ int run(const RunArgs &a)
         // the longer per-wave loop)
         const int g_w64a = std::min(grid64(n_a), std::max(8, di.cus * resident_per_cu<D2>() / 8 * 8));
         const int g_w64b = grid64(n_b);
+        // balanced net rounds: a wave per chunk of net ids, an LDS bitmap of
+        // 16 bits per member of the largest net (at least 16 KB), within the budget
+        const int bal_bytes = (int)std::min<long>(lds_budget, std::max<long>(16384, (16L * max_net + 64) / 8 + 64) / 4 * 4);
+        const int g_nbal = std::max(1, std::min((n_b + chunk - 1) / chunk, di.cus * 16));
+        mark_round();
         while (!done && issued < max_rounds) {
             // keep at most LOOKAHEAD rounds in flight beyond the last one seen
             if (use_prog) {
@@ -624,14 +687,28 @@ int run(const RunArgs &a)
             const bool spr = !net_mode && r < inc_start && sp_on;   // this round keeps standing proposals
             if (spr) sp_used = true;
             if (net_mode) {
-                k_ncolor_small<D2><<<g_b, nthr, 0, s>>>(g, st, owner, ctrl);
-                if (n_big) k_ncolor_big<D2><<<g_big, 256, ncolor_words * 4, s>>>(g, st, owner, big, &shape[1], ctrl,
-                                                                                 ncolor_words);
+                if (net_bal) {
+                    k_ncolor_balanced<D2><<<g_nbal, 64, bal_bytes, s>>>(g, st, owner, ctrl, policy, chunk,
+                                                                        bal_bytes * 8);
+                } else {
+                    k_ncolor_small<D2><<<g_b, nthr, 0, s>>>(g, st, owner, ctrl, o.net_alg);
+                    if (n_big)
+                        k_ncolor_big<D2><<<g_big, NBIG_BLOCK, ncolor_words * 4, s>>>(g, st, owner, big, &shape[1],
+                                                                                     ctrl, ncolor_words, o.net_alg);
+                }
                 if (!D2) k_ncolor_isolated<<<g_a, nthr, 0, s>>>(g, Wc, ctrl, par, st);
-                LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 0, PCNT(r), sp_none)));
-                if (n_big)
-                    k_conflict_big<D2><<<g_big, BIG_BLOCK, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 0,
-                                                                           sp_none, 0);
+                if (!hash_states(r, true)) {
+                    st_code = BGPC_E_HIP;
+                    goto finish;
+                }
+                if (vertex_form(r, true)) {
+                    k_conflict_vertex<D2><<<g_a, nthr, 0, s>>>(g, Wc, ctrl, par, st, lose);
+                } else {
+                    LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 0, PCNT(r), sp_none)));
+                    if (n_big)
+                        k_conflict_big<D2><<<g_big, BIG_BLOCK, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1],
+                                                                                   ctrl, 0, sp_none, 0);
+                }
                 const bool full = r > 0 || resume;
                 if (full) {
                     k_set_max_final<<<1, 64, 0, s>>>(ctrl, -1);
@@ -641,10 +718,7 @@ int run(const RunArgs &a)
                     k_mask_rebuild<D2><<<g_b, nthr, 0, s>>>(g, st, mask0, hw, PH);
                     k_fill_i32<<<g_a, nthr, 0, s>>>(ffc, 0, n_a + 1);
                     k_fill_u8<<<g_b, nthr, 0, s>>>(done_net, 0, n_b + 1);
-        k_fill_i32<<<g_a, nthr, 0, s>>>((int *)dirty_bits, 0, n_a / 32 + 2);
-        k_fill_i32<<<g_a, nthr, 0, s>>>((int *)aff_bits, 0, n_a / 32 + 2);
-        k_fill_i32<<<g_b, nthr, 0, s>>>((int *)tchg_bits, 0, n_b / 32 + 2);
-        k_fill_i32<<<g_b, nthr, 0, s>>>((int *)cn_bits, 0, n_b / 32 + 2);
+                    clear_inc_bits();
                 } else {
                     k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1, hw, PH,
                                                           nullptr);
@@ -667,6 +741,10 @@ int run(const RunArgs &a)
                         k_vcolor_wide<D2><<<di.cus * 2, 256, wide_bytes, s>>>(g, heavy, ctrl, st, lds_bits, nullptr,
                                                                                nullptr, nullptr, nullptr, nullptr,
                                                                                hw, PH, ffc, nullptr);
+                    if (!hash_states(r, true)) {
+                        st_code = BGPC_E_HIP;
+                        goto finish;
+                    }
                     LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), sp_none)));
                     k_inc_apply_full<D2><<<g_inc, nthr, 0, s>>>(g, ic, ctrl, par, Wc, st, lose, mask0, cn_bits, CNl);
                 } else {
@@ -676,6 +754,10 @@ int run(const RunArgs &a)
                         k_vcolor_wide<D2><<<di.cus * 2, 256, wide_bytes, s>>>(g, heavy, ctrl, st, lds_bits, ic,
                                                                                aff_bits, Al, tchg_bits, TCNl,
                                                                                nullptr, 0, nullptr, nullptr);
+                    if (!hash_states(r, true)) {
+                        st_code = BGPC_E_HIP;
+                        goto finish;
+                    }
                     k_expand<D2><<<g_inc, nthr, 0, s>>>(g, TCNl, &ic->n_tcn, tchg_bits, st, aff_bits, Al, &ic->n_a);
                     k_inc_conflict<D2><<<g_inc, nthr, 0, s>>>(g, ic, par, Al, aff_bits, st, WINl, ctrl);
                     k_inc_apply<D2><<<g_inc, nthr, 0, s>>>(g, ic, WINl, st, mask0, cn_bits, CNl, ctrl);
@@ -734,20 +816,33 @@ int run(const RunArgs &a)
                                                                           lds_bits, hw, PH, dty, Fp ? hv_id : nullptr,
                                                                           Fp);
                 }
-                LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), spx)));
-                if (spr && prof_kernel == BGPC_PROF_CONFLICT && PCNT(r))
-                    k_census<D2><<<g_b, nthr, 0, s>>>(g, st, PCNT(r));
-                if (n_big)
-                    k_conflict_big<D2><<<g_big, BIG_BLOCK, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1], ctrl, 1,
-                                                                           spx, huge_on);
-                if (huge_on)
-                    k_conflict_huge<D2><<<g_huge, HUGE_BLOCK, huge_bytes, s>>>(g, st, lose, done_net, huge, &shape[3],
-                                                                             ctrl, 1, spx, huge_list);
+                if (!hash_states(r, true)) {
+                    st_code = BGPC_E_HIP;
+                    goto finish;
+                }
+                if (vertex_form(r, false)) {
+                    k_conflict_vertex<D2><<<g_a, nthr, 0, s>>>(g, Wc, ctrl, par, st, lose);
+                } else {
+                    LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), spx)));
+                    if (spr && prof_kernel == BGPC_PROF_CONFLICT && PCNT(r))
+                        k_census<D2><<<g_b, nthr, 0, s>>>(g, st, PCNT(r));
+                    if (n_big)
+                        k_conflict_big<D2><<<g_big, BIG_BLOCK, conflict_bytes, s>>>(g, st, lose, done_net, big, &shape[1],
+                                                                                   ctrl, 1, spx, huge_on);
+                    if (huge_on)
+                        k_conflict_huge<D2><<<g_huge, HUGE_BLOCK, huge_bytes, s>>>(g, st, lose, done_net, huge, &shape[3],
+                                                                                 ctrl, 1, spx, huge_list);
+                }
                 k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1, hw, PH,
                                                       spr ? sp_cnt : nullptr);
                 k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 0, 1, host);
             }
             LAUNCH_CHECK();
+            mark_round();
+            if (!hash_states(r, false)) {
+                st_code = BGPC_E_HIP;
+                goto finish;
+            }
             issued++;
         }
         if (inc_used || sp_used) k_drop_proposals<<<g_a, nthr, 0, s>>>(st, n_a);
@@ -779,7 +874,7 @@ finish:
         if (k > 0 && hipMemcpy(rr_h.data(), rec, sizeof(RoundRec) * k, hipMemcpyDeviceToHost) == hipSuccess &&
             hipMemcpy(pc_h.data(), pcnt, sizeof(unsigned long long) * k * PROF_SLOTS * 4,
                       hipMemcpyDeviceToHost) == hipSuccess) {
-            double bytes = 0.0, scanned = 0.0;
+            double bytes = 0.0, scanned = 0.0, alt = 0.0;
             for (int i = 0; i < k; i++) {
                 double nets = 0, mem = 0, rows = 0, smem = 0;
                 for (int q = 0; q < PROF_SLOTS; q++) {
@@ -789,24 +884,29 @@ finish:
                     smem += (double)pc_h[((size_t)i * PROF_SLOTS + q) * 4 + 3];
                 }
                 if (prof_kernel == BGPC_PROF_CONFLICT) {
-                    // per net of the round (a net with a member in the
-                    // worklist): its end offset + member ids; every member
-                    // state once (at most n_a distinct)
-                    bytes += 4.0 * nets + 4.0 * mem + 4.0 * std::min(mem, (double)n_a);
+                    // net form of removal, per net of the round (a net with a
+                    // member uncolored or proposing): two offsets, then per
+                    // member its id and its state
+                    bytes += 8.0 * nets + 8.0 * mem;
                     // the same over the nets actually read (their count is
-                    // not kept: offsets counted per member / average size)
+                    // not kept: counted per member / average size)
                     const double snets = mem > 0 ? nets * smem / mem : 0.0;
-                    scanned += 4.0 * snets + 4.0 * smem + 4.0 * std::min(smem, (double)n_a);
+                    scanned += 8.0 * snets + 8.0 * smem;
+                    // per net one offset and the member ids, every member
+                    // state read once per round (at most n_a distinct)
+                    alt += 4.0 * nets + 4.0 * mem + 4.0 * std::min(mem, (double)n_a);
                 } else if (prof_kernel == BGPC_PROF_COLOR && rr_h[i].mode == 0) {
                     // per entry: id, two row offsets, proposal; per incidence: net
                     // id; every net mask once (at most n_b distinct)
                     const double b = 16.0 * rr_h[i].w + 4.0 * rows + 8.0 * std::min(rows, (double)n_b);
                     bytes += b;
                     scanned += b;
+                    alt += b;
                 }
             }
             o.prof->bytes_scanned = scanned;
             o.prof->bytes = bytes;
+            o.prof->bytes_states = alt;
         }
     }
     if (st_code == BGPC_OK || st_code == BGPC_E_NOT_CONVERGED) {
@@ -829,6 +929,16 @@ finish:
             }
         }
     }
+    if (time_rounds && (st_code == BGPC_OK || st_code == BGPC_E_NOT_CONVERGED)) {
+        const int k = std::min(std::min(o.log->cap, h_ctrl.rounds), (int)round_ev.size() - 1);
+        for (int i = 0; i < k; i++) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, round_ev[i], round_ev[i + 1]) != hipSuccess) t = -1.f;
+            o.log->round_ms[i] = t;
+        }
+    }
+    for (hipEvent_t e : round_ev) (void)hipEventDestroy(e);
+    if (h_states) (void)hipHostFree(h_states);
     if (hw) (void)hipFreeAsync(hw, s);
     for (void *p : {(void *)hv_id, (void *)hv_list, (void *)hv_slices, (void *)hv_counts, (void *)hv_F})
         if (p) (void)hipFreeAsync(p, s);
@@ -905,7 +1015,9 @@ bool csr_ok(const bgpc_csr *c)
 
 bool opts_ok(const bgpc_opts &o)
 {
-    return o.policy >= 0 && o.policy <= BGPC_B1_GLOBAL && o.chunk >= 1 && o.max_rounds >= 0 && o.start_round >= 0;
+    return o.policy >= 0 && o.policy <= BGPC_B1_GLOBAL && o.chunk >= 1 && o.max_rounds >= 0 && o.start_round >= 0 &&
+           o.net_alg >= BGPC_NET_ALG8 && o.net_alg <= BGPC_NET_ALG6_REVERSE &&
+           (!(o.flags & BGPC_NET_BALANCE) || o.net_alg == BGPC_NET_ALG8);
 }
 
 }  // namespace
@@ -1140,6 +1252,8 @@ BGPC_API void bgpc_opts_default(bgpc_opts *o)
     std::memset(o, 0, sizeof(*o));
     o->policy = BGPC_FIRST_FIT;
     o->chunk = 64;
+    o->net_conflict_mask = ~0ull;
+    o->net_alg = BGPC_NET_ALG8;
 }
 
 BGPC_API int bgpc_color(const bgpc_csr *csr_A, const bgpc_csr *csr_B, const int32_t *order, const bgpc_opts *opts,

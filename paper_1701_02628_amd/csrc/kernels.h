@@ -20,6 +20,7 @@
 namespace bgpc {
 
 constexpr int SMALL_NET = 64;       // nets up to this size run thread-per-net
+constexpr int NBIG_BLOCK = 256;     // threads of k_ncolor_big
 constexpr int TILE = 2048;          // worklist entries per compaction tile
 constexpr int TILE_BLOCK = 256;     // threads of the apply / compaction blocks
 constexpr int HASH_MAX = 4096;      // big nets up to this size use an LDS hash
@@ -1103,15 +1104,45 @@ __global__ void __launch_bounds__(64) k_vcolor_chunked(Graph g, const int *W, Ct
 // net-based coloring (Algorithm 8; Algorithm 9 in distance-2 mode)
 
 // Thread per net of at most SMALL_NET members: the forbidden colors below
-// |vtxs(v)| fit in one 64-bit word; uncolored members in adjacency order take
-// the free colors from |vtxs(v)| - 1 downwards; only the owner net writes.
+// |vtxs(v)| fit in one 64-bit word; only the owner net writes.
+// alg 0 (Algorithm 8): the colored members' colors first, then the uncolored
+// members in adjacency order take the free colors from |vtxs(v)| - 1 down.
+// alg 1 / 2 (Algorithm 6, forward / reverse start): one pass in adjacency
+// order, a colored member's color joining F where it stands; a pick is the
+// nearest free color from the previous pick (up from 0 / down from
+// |vtxs(v)| - 1) and joins F.  Every pick stays inside [0, |vtxs(v)|): at a
+// member's turn F holds fewer colors than the members before it.
 template <bool D2>
-__global__ void k_ncolor_small(Graph g, int *st, const int *owner, Ctrl *ctrl)
+__global__ void k_ncolor_small(Graph g, int *st, const int *owner, Ctrl *ctrl, int alg)
 {
     int local_max = -1;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n_b; v += gridDim.x * blockDim.x) {
         int sz = Acc<D2>::size(g, v);
         if (sz == 0 || sz > SMALL_NET) continue;
+        if (alg != 0) {
+            uint64_t F = 0;
+            int col = alg == 1 ? 0 : sz - 1;
+            for (int k = 0; k < sz; k++) {
+                const int x = Acc<D2>::member(g, v, k);
+                const int c = snap_color(st[x]);
+                if (c >= 0) {
+                    if (c < 64) F |= 1ull << c;
+                    continue;
+                }
+                const uint64_t fr = alg == 1 ? (~F & (~0ull << col)) : (~F & bits_upto(col));
+                if (!fr) {
+                    atomicOr(&ctrl->error, ERR_REVERSE_NEG);
+                    break;
+                }
+                col = alg == 1 ? __builtin_ctzll(fr) : 63 - __builtin_clzll(fr);
+                F |= 1ull << col;
+                if (owner[x] == v) {
+                    st[x] = TENT | col;
+                    local_max = max(local_max, col);
+                }
+            }
+            continue;
+        }
         uint64_t F = 0;
         int nun = 0;
         for (int k = 0; k < sz; k++) {
@@ -1145,12 +1176,17 @@ __global__ void k_ncolor_small(Graph g, int *st, const int *owner, Ctrl *ctrl)
 // bits and the suffix counts of its free colors per 32-bit word; the p-th
 // uncolored member (adjacency order) takes the p-th free color counted from
 // the top.
+// Algorithm 6 (alg 1 / 2) in a big net: the members' snapshot colors are
+// staged blockDim.x at a time and one thread makes the single pass over them
+// (the bitmap of [0, |vtxs(v)|) in LDS), since each pick depends on every
+// member before it.
 template <bool D2>
-__global__ void k_ncolor_big(Graph g, int *st, const int *owner, const int *big, const int *n_big_p, Ctrl *ctrl,
-                             int lds_words)
+__global__ void __launch_bounds__(NBIG_BLOCK) k_ncolor_big(Graph g, int *st, const int *owner, const int *big,
+                                                           const int *n_big_p, Ctrl *ctrl, int lds_words, int alg)
 {
     extern __shared__ uint32_t dyn[];
     __shared__ int s_scan[20];
+    __shared__ int s_x[NBIG_BLOCK], s_c[NBIG_BLOCK];
     const int n_big = *n_big_p;
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int bi = blockIdx.x; bi < n_big; bi += gridDim.x) {
@@ -1165,6 +1201,46 @@ __global__ void k_ncolor_big(Graph g, int *st, const int *owner, const int *big,
         int *suf = (int *)(dyn + nwords);
         for (int i = tid; i < nwords; i += nt) bits[i] = 0;
         __syncthreads();
+        if (alg != 0) {
+            int col = alg == 1 ? 0 : sz - 1;   // meaningful in thread 0 only
+            int lmax = -1;
+            for (int k0 = 0; k0 < sz; k0 += nt) {
+                const int k = k0 + tid;
+                const int x = k < sz ? Acc<D2>::member(g, v, k) : -1;
+                s_x[tid] = x;
+                s_c[tid] = x >= 0 ? snap_color(st[x]) : -2;
+                __syncthreads();
+                if (tid == 0) {
+                    const int cnt = min(nt, sz - k0);
+                    for (int j = 0; j < cnt; j++) {
+                        const int c = s_c[j];
+                        if (c >= 0) {
+                            if (c < sz) bits[c >> 5] |= 1u << (c & 31);
+                            continue;
+                        }
+                        if (alg == 1) {
+                            while (col < sz && ((bits[col >> 5] >> (col & 31)) & 1u)) col++;
+                        } else {
+                            while (col >= 0 && ((bits[col >> 5] >> (col & 31)) & 1u)) col--;
+                        }
+                        if (col < 0 || col >= sz) {
+                            atomicOr(&ctrl->error, ERR_REVERSE_NEG);
+                            break;
+                        }
+                        bits[col >> 5] |= 1u << (col & 31);
+                        const int xj = s_x[j];
+                        if (owner[xj] == v) {
+                            st[xj] = TENT | col;
+                            lmax = max(lmax, col);
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            if (tid == 0 && lmax >= 0) max_to(&ctrl->max_color, lmax);
+            __syncthreads();
+            continue;
+        }
         int nun = 0;
         for (int k = tid; k < sz; k += nt) {
             int c = snap_color(st[Acc<D2>::member(g, v, k)]);
@@ -1240,6 +1316,76 @@ __global__ void k_ncolor_isolated(Graph g, const int *W, Ctrl *ctrl, int par, in
         int w = W[i];
         if (g.a_off[w + 1] == g.a_off[w]) st[w] = TENT | 0;
     }
+}
+
+// Net-based rounds under a balancing policy (BGPC_NET_BALANCE): one wave per
+// chunk of `chunk` consecutive net ids, the policy state running through the
+// chunk's nets in id order.  Per net with an uncolored member: an LDS bitmap
+// of the colored members' snapshot colors below cap = col_max + |vtxs(v)| + 2,
+// then the uncolored members in adjacency order each take the policy's pick
+// (B1's parity from the net id), which joins the bitmap; only the owner net
+// writes the proposal.  No pick reaches cap: F never holds |vtxs(v)| colors,
+// so a search that passes col_max (B1 upward, B2's fallback) only happens
+// when [0, col_max] is all in F and then lands below |vtxs(v)|; every other
+// pick is at most col_max, which therefore stays below
+// max(starting col_max, |vtxs(v)|).
+template <bool D2>
+__global__ void __launch_bounds__(64) k_ncolor_balanced(Graph g, int *st, const int *owner, Ctrl *ctrl, int policy,
+                                                         int chunk, int lds_bits)
+{
+    extern __shared__ uint32_t dyn[];
+    __shared__ int s_res;
+    const int lane = threadIdx.x;
+    const int nch = (g.n_b + chunk - 1) / chunk;
+    // B1G: col_max is the snapshot's largest color for the whole round
+    const int g_max = policy == 3 ? ctrl->pad[0] : 0;
+    int local_max = -1;
+    for (int ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+        PolicyState s = {g_max, 0};
+        const int hi = min(ch * chunk + chunk, g.n_b);
+        for (int v = ch * chunk; v < hi; v++) {
+            const int sz = Acc<D2>::size(g, v);
+            if (sz == 0) continue;
+            int nun = 0;
+            for (int k = lane; k < sz; k += WAVE) nun += snap_color(st[Acc<D2>::member(g, v, k)]) < 0 ? 1 : 0;
+            if (wave_sum(nun) == 0) continue;
+            const int cap = max(s.col_max, 0) + sz + 2;
+            if (cap > lds_bits) {
+                if (lane == 0) atomicOr(&ctrl->error, ERR_COLOR_CAP);
+                return;
+            }
+            const int nwords = (cap + 31) >> 5;
+            for (int q = lane; q < nwords; q += WAVE) dyn[q] = 0;
+            __syncthreads();
+            for (int k = lane; k < sz; k += WAVE) {
+                const int c = snap_color(st[Acc<D2>::member(g, v, k)]);
+                if (c >= 0 && c < cap) atomicOr(&dyn[c >> 5], 1u << (c & 31));
+            }
+            __syncthreads();
+            for (int k0 = 0; k0 < sz; k0 += WAVE) {
+                const int k = k0 + lane;
+                const int x = k < sz ? Acc<D2>::member(g, v, k) : -1;
+                const bool unc = x >= 0 && snap_color(st[x]) < 0;
+                for (uint64_t bal = __ballot(unc); bal; bal &= bal - 1) {
+                    const int j = __builtin_ctzll(bal);
+                    const int xj = __shfl(x, j);
+                    const int col = pick_bitmap(policy, dyn, cap, v, s, &s_res);
+                    if (col >= cap) {   // cannot happen (see above); never write past the bitmap
+                        if (lane == 0) atomicOr(&ctrl->error, ERR_COLOR_CAP);
+                        return;
+                    }
+                    if (lane == 0) {
+                        dyn[col >> 5] |= 1u << (col & 31);
+                        if (owner[xj] == v) st[xj] = TENT | col;
+                    }
+                    __syncthreads();
+                    policy_update(policy, col, s);
+                    if (owner[xj] == v) local_max = max(local_max, col);
+                }
+            }
+        }
+    }
+    if (lane == 0 && local_max >= 0) max_to(&ctrl->max_color, local_max);
 }
 
 // ---------------------------------------------------------------------------
@@ -1786,6 +1932,41 @@ __global__ void __launch_bounds__(HUGE_BLOCK) k_conflict_huge(Graph g, const int
         const long lpos = sp.lbits ? sp_lpos<D2>(g, v) : 0;
         conflict_large<D2>(g, st, lose, done, v, Acc<D2>::size(g, v), lpos, tent_only, sp, sh, list_cap,
                            ctrl->max_color, s_scan, &s_cnt);
+    }
+}
+
+// Removal in the vertex form (Algorithm 5 with Algorithm 3's test): thread
+// per worklist vertex w, which loses iff a lower-ranked vertex sharing a net
+// with w holds w's current color.  Members are ascending in rank (distance-2:
+// the center first, then the ascending neighbours), so a net's walk stops at
+// the first member ranked above w.  Exact where no colored vertex can hold a
+// color a worklist vertex proposes (the driver uses it only there).
+template <bool D2>
+__global__ void k_conflict_vertex(Graph g, const int *W, Ctrl *ctrl, int par, const int *st, uint8_t *lose)
+{
+    const int n = ctrl->n_w[par];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int w = W[i];
+        const int c = cur_color(st[w]);
+        if (c < 0) continue;
+        bool lost = false;
+        const int nn = Acc<D2>::nets_count(g, w);
+        for (int a = 0; a < nn && !lost; a++) {
+            const int v = Acc<D2>::net_at(g, w, a);
+            const int sz = Acc<D2>::size(g, v);
+            for (int k = 0; k < sz; k++) {
+                const int x = Acc<D2>::member(g, v, k);
+                if (x >= w) {
+                    if (D2 && k == 0) continue;   // the center comes first, out of order
+                    break;
+                }
+                if (cur_color(st[x]) == c) {
+                    lost = true;
+                    break;
+                }
+            }
+        }
+        if (lost) lose[w] = 1;
     }
 }
 

@@ -40,10 +40,13 @@ def test_binding_struct_layouts_match_header(tmp_path):
 #include "bgpc.h"
 int main(void) {
   printf("csr %zu %zu %zu\n", sizeof(bgpc_csr), offsetof(bgpc_csr, nnz), offsetof(bgpc_csr, indices));
-  printf("log %zu %zu\n", sizeof(bgpc_round_log), offsetof(bgpc_round_log, max_color));
+  printf("log %zu %zu %zu\n", sizeof(bgpc_round_log), offsetof(bgpc_round_log, max_color),
+         offsetof(bgpc_round_log, round_ms));
   printf("prof %zu %zu %zu\n", sizeof(bgpc_profile), offsetof(bgpc_profile, bytes), offsetof(bgpc_profile, bytes_scanned));
-  printf("opts %zu %zu %zu %zu\n", sizeof(bgpc_opts), offsetof(bgpc_opts, stream), offsetof(bgpc_opts, log),
-         offsetof(bgpc_opts, prof));
+  printf("opts %zu %zu %zu %zu %zu %zu\n", sizeof(bgpc_opts), offsetof(bgpc_opts, stream), offsetof(bgpc_opts, log),
+         offsetof(bgpc_opts, prof), offsetof(bgpc_opts, net_conflict_mask), offsetof(bgpc_opts, net_alg));
+  printf("item %zu %zu %zu %zu\n", sizeof(bgpc_batch_item), offsetof(bgpc_batch_item, order),
+         offsetof(bgpc_batch_item, d2gc), offsetof(bgpc_batch_item, route));
   printf("stats %zu %zu\n", sizeof(bgpc_stats), offsetof(bgpc_stats, card_std));
   return 0;
 }
@@ -55,10 +58,13 @@ int main(void) {
         k, *vals = line.split()
         got[k] = [int(v) for v in vals]
     assert got["csr"] == [ctypes.sizeof(bgpc.Csr), bgpc.Csr.nnz.offset, bgpc.Csr.indices.offset]
-    assert got["log"] == [ctypes.sizeof(bgpc.RoundLog), bgpc.RoundLog.max_color.offset]
+    assert got["log"] == [ctypes.sizeof(bgpc.RoundLog), bgpc.RoundLog.max_color.offset,
+                          bgpc.RoundLog.round_ms.offset]
     assert got["prof"] == [ctypes.sizeof(bgpc.Profile), bgpc.Profile.bytes.offset, bgpc.Profile.bytes_scanned.offset]
     assert got["opts"] == [ctypes.sizeof(bgpc.Opts), bgpc.Opts.stream.offset, bgpc.Opts.log.offset,
-                           bgpc.Opts.prof.offset]
+                           bgpc.Opts.prof.offset, bgpc.Opts.net_conflict_mask.offset, bgpc.Opts.net_alg.offset]
+    assert got["item"] == [ctypes.sizeof(bgpc.BatchItem), bgpc.BatchItem.order.offset, bgpc.BatchItem.d2gc.offset,
+                           bgpc.BatchItem.route.offset]
     assert got["stats"] == [ctypes.sizeof(bgpc.Stats), bgpc.Stats.card_std.offset]
 
 
@@ -69,3 +75,4 @@ def test_status_strings_and_defaults():
     o = bgpc.Opts()
     lib.bgpc_opts_default(ctypes.byref(o))
     assert o.policy == 0 and o.chunk == 64 and o.net_color_mask == 0 and o.flags == 0
+    assert o.net_conflict_mask == 2 ** 64 - 1 and o.net_alg == 0

@@ -9,12 +9,19 @@ from paper_1701_02628_amd import bgpc, synth
 pytestmark = pytest.mark.gpu
 
 
-def _batch(cuda, graphs, **kw):
+def _batch(cuda, graphs, routes=None, **kw):
+    """Batch over host graphs (bipartite, or Adjacency for distance-2 items);
+    `routes`, when a list, receives the route the library reports per item."""
     import torch
-    dev = [bgpc.upload_bipartite(g) for g in graphs]
-    outs = [torch.full((g.n_a,), -7, dtype=torch.int32, device=cuda) for g in graphs]
-    st, statuses, rounds = bgpc.bgpc_color_batch(dev, outs, **kw)
+    dev = [bgpc.upload_adjacency(g) if hasattr(g, "off") else bgpc.upload_bipartite(g) for g in graphs]
+    outs = [torch.full((g.n if hasattr(g, "off") else g.n_a,), -7, dtype=torch.int32, device=cuda) for g in graphs]
+    orders = kw.pop("orders", None)
+    if orders is not None:
+        orders = [None if o is None else torch.from_numpy(np.asarray(o, np.int32)).to(cuda) for o in orders]
+    st, statuses, rounds, rts = bgpc.bgpc_color_batch(dev, outs, orders=orders, with_routes=True, **kw)
     torch.cuda.synchronize()
+    if routes is not None:
+        routes.extend(rts)
     return st, statuses, rounds, [o.cpu().numpy() for o in outs]
 
 
@@ -32,29 +39,6 @@ def test_batch_matches_oracle(cuda):
         assert np.array_equal(c, ref.colors) and r == ref.rounds
 
 
-def _shape(g):
-    """(walk, walk_max): sum of squared net sizes, largest summed net size of a vertex."""
-    sizes = np.diff(np.asarray(g.b_off, dtype=np.int64))
-    per_member = np.repeat(np.arange(g.n_a), np.diff(np.asarray(g.a_off, dtype=np.int64)))
-    wsum = np.bincount(per_member, weights=sizes[np.asarray(g.a_idx)], minlength=g.n_a) if g.n_a else np.zeros(0)
-    return float((sizes ** 2).sum()), int(wsum.max()) if wsum.size else 0
-
-
-def _route(g):
-    """The per-graph route of bgpc_color_batch restated from its rule:
-    'dense' (conflict matrix), 'forb' (forbidden bitmaps), 'masks', or
-    'device' (the whole-device path of bgpc_color)."""
-    walk, wmax = _shape(g)
-    heavy = walk > 128.0 * g.n_a or walk > 4.0 * g.n_a ** 2
-    if g.n_a > 0 and heavy and g.n_a <= 16384:
-        return "dense"
-    cap = min(wmax + 2, g.n_a + 1)
-    mode = "forb" if g.n_a > 0 and heavy and g.n_a * ((cap + 31) // 32) * 4 <= (64 << 20) else "masks"
-    if (mode == "forb" and g.nnz > 50000) or g.nnz > 1000000:
-        return "device"
-    return mode
-
-
 def test_batch_every_mode_matches_oracle(cuda):
     """Graphs on every route of the per-graph rule: few vertices with heavily
     overlapping nets and many colors (conflict matrix; buckets both below and
@@ -65,9 +49,9 @@ def test_batch_every_mode_matches_oracle(cuda):
               (4097, 9000, 3, 30, 39), (9000, 3000, 30, 60, 37), (1004, 1992, 3, 30, 40),
               (17000, 380, 100, 150, 44), (20000, 8000, 10, 30, 35), (3000, 3000, 3, 6, 38)]
     graphs = [synth.random_uniform(*sh) for sh in shapes]
-    routes = [_route(g) for g in graphs]
-    assert routes == ["dense"] * 6 + ["forb", "device", "masks"]
-    st, statuses, rounds, colors = _batch(cuda, graphs)
+    routes = []
+    st, statuses, rounds, colors = _batch(cuda, graphs, routes)
+    assert routes == [bgpc.ROUTE_DENSE] * 6 + [bgpc.ROUTE_BITMAPS, bgpc.ROUTE_WHOLE_DEVICE, bgpc.ROUTE_NET_MASKS]
     assert st == 0 and all(s == 0 for s in statuses)
     for g, c, r in zip(graphs, colors, rounds):
         ref = oracle.bgpc(g)
@@ -126,14 +110,31 @@ def test_batch_not_converged(cuda):
         assert np.array_equal(c, ref.colors)
 
 
-def test_batch_rejects_other_schedules(cuda):
-    import ctypes
-    lib = bgpc.load()
-    o = bgpc.Opts()
-    lib.bgpc_opts_default(ctypes.byref(o))
-    o.net_color_mask = 1
-    items = (bgpc.BatchItem * 1)()
-    assert lib.bgpc_color_batch(items, 0, ctypes.byref(o)) == bgpc.E_UNSUPPORTED
+def test_batch_other_schedules_orders_and_distance2(cuda):
+    """Items the persistent launch does not run -- a caller order, a
+    distance-2 item, or any other schedule for the whole batch -- take the
+    whole-device route and equal the oracle."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    g1 = synth.random_uniform(3000, 2500, 2, 9, 51)
+    g2 = synth.random_uniform(1200, 1500, 3, 30, 52)
+    adj = synth.rmat(10, 8, 0.57, 0.19, 0.19, seed=4)
+    perm = rng.permutation(g2.n_a).astype(np.int32)
+    graphs, orders = [g1, g2, adj], [None, perm, None]
+    routes = []
+    st, statuses, rounds, colors = _batch(cuda, graphs, routes, orders=orders)
+    assert st == 0 and routes == [bgpc.ROUTE_NET_MASKS, bgpc.ROUTE_WHOLE_DEVICE, bgpc.ROUTE_WHOLE_DEVICE]
+    refs = [oracle.bgpc(g1), oracle.bgpc(g2, order=perm), oracle.d2gc(adj)]
+    for c, r, ref in zip(colors, rounds, refs):
+        assert np.array_equal(c, ref.colors) and r == ref.rounds
+    for kw, okw in ((dict(net_color_mask=1), dict(net_color_mask=1)),
+                    (dict(policy=2, chunk=9), dict(policy=2, chunk=9)),
+                    (dict(net_color_mask=1, net_alg=1), dict(net_color_mask=1, net_alg=1))):
+        routes = []
+        st, statuses, rounds, colors = _batch(cuda, graphs, routes, orders=orders, **kw)
+        assert st == 0 and routes == [bgpc.ROUTE_WHOLE_DEVICE] * 3
+        refs = [oracle.bgpc(g1, **okw), oracle.bgpc(g2, order=perm, **okw), oracle.d2gc(adj, **okw)]
+        for c, r, ref in zip(colors, rounds, refs):
+            assert np.array_equal(c, ref.colors) and r == ref.rounds
 
 
 def _serve(graphs, rate, seed, budget=2 << 30, max_slots=64, max_group=16):
@@ -174,6 +175,10 @@ def test_serving_same_as_alone(cuda):
     for i, g in enumerate(graphs * 2):
         tag, st, rounds, t_sub, t_adm, t_done, colors = res[i]
         assert st == 0 and t_sub <= t_adm <= t_done
+    # continuous batching, not a queue: some request was admitted while an
+    # earlier-admitted one was still running
+    spans = sorted((c[4], c[5]) for c in res.values())
+    assert any(spans[j][0] < spans[i][1] for i in range(len(spans)) for j in range(i + 1, len(spans)))
     for i, g in enumerate(graphs):
         ref = oracle.bgpc(g)
         for j in (i, i + len(graphs)):
@@ -203,6 +208,8 @@ def test_serving_batched_workload_graphs(cuda):
 def test_serving_rejects_oversized(cuda):
     s = bgpc.Session(1 << 20, max_slots=4, max_group=4)
     g = synth.random_uniform(300000, 100000, 2, 4, 43)   # sparse (batched route), ~4 MB of arrays
-    assert _route(g) == "masks"
+    routes = []
+    _batch(cuda, [g], routes)
+    assert routes == [bgpc.ROUTE_NET_MASKS]
     assert s.submit(0, g.n_a, g.n_b, g.a_off, g.a_idx, g.b_off, g.b_idx) == bgpc.E_OOM
     s.close()

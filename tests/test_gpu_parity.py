@@ -73,9 +73,13 @@ def test_worked_examples_round_by_round(cuda, case):
         dev = bgpc.upload_adjacency(g)
         run = lambda **kw: _gpu_d2(cuda, g, dev, **kw)
     states = case["states"]
+    extra = dict(net_alg=case.get("net_alg", 0), flags=bgpc.NET_BALANCE if case.get("net_balance") else 0)
+    if "init_colors" in case:
+        extra["init_colors"] = case["init_colors"]
+        extra["flags"] |= bgpc.RESUME
     for k, expect in enumerate(states, start=1):
         res, colors = run(net_color_mask=case["net_color_mask"], policy=case["policy"], chunk=case["chunk"],
-                          max_rounds=k)
+                          max_rounds=k, **extra)
         assert colors.tolist() == expect, (k, colors.tolist(), expect)
         assert res.status == (bgpc.OK if k == len(states) else bgpc.E_NOT_CONVERGED)
         assert res.rounds == k
@@ -472,3 +476,87 @@ def test_b1_global_resume(cuda):
     res, colors = _gpu_bgpc(cuda, g, policy=3, init_colors=part.colors, start_round=3, flags=bgpc.RESUME)
     _compare_full(res, colors, ref)
     assert np.array_equal(colors, oracle.bgpc(g, policy=3).colors)
+
+
+# ---------------------------------------------------------------------------
+# net-based variants (Algorithm 6, net-based balancing), removal forms, hashes
+
+
+def _oracle_kw(kw):
+    """bgpc_color keyword arguments -> the oracle's."""
+    out = {k: v for k, v in kw.items() if k in ("net_color_mask", "policy", "chunk", "net_alg", "max_rounds")}
+    if kw.get("flags", 0) & bgpc.NET_BALANCE:
+        out["net_balance"] = True
+    return out
+
+
+NET_VARIANTS = [
+    ("alg6-N1", dict(net_color_mask=1, net_alg=1)),
+    ("alg6r-N1", dict(net_color_mask=1, net_alg=2)),
+    ("alg6-N2", dict(net_color_mask=0b11, net_alg=1)),
+    ("alg6-V-then-N", dict(net_color_mask=0b10, net_alg=1)),
+    ("alg6r-every-3rd", dict(net_color_mask=0b1001001, net_alg=2)),
+    ("netB1-N1", dict(net_color_mask=1, policy=1, flags=8)),
+    ("netB2-N2", dict(net_color_mask=0b11, policy=2, flags=8)),
+    ("netB1G-N1", dict(net_color_mask=1, policy=3, flags=8)),
+    ("netB2-T5", dict(net_color_mask=0b101, policy=2, chunk=5, flags=8)),
+    ("netFF-N1", dict(net_color_mask=1, policy=0, flags=8)),
+]
+
+
+@pytest.mark.parametrize("shape", GRAPHS[:2] + [(2000, 1500, 60, 140, 15)], ids=lambda s: f"{s[0]}x{s[1]}k{s[2]}-{s[3]}")
+@pytest.mark.parametrize("var", NET_VARIANTS, ids=lambda v: v[0])
+def test_net_variants(cuda, shape, var):
+    n_a, n_b, kmin, kmax, seed = shape
+    g = synth.random_uniform(n_a, n_b, kmin, kmax, seed)
+    ref = oracle.bgpc(g, **_oracle_kw(var[1]))
+    res, colors = _gpu_bgpc(cuda, g, **var[1])
+    _compare_full(res, colors, ref)
+
+
+@pytest.mark.parametrize("var", NET_VARIANTS, ids=lambda v: v[0])
+def test_net_variants_skewed_and_d2(cuda, var):
+    g = synth.skewed(30000, 30000, seed=5, kmax=3000, name="skewed30k")
+    ref = oracle.bgpc(g, **_oracle_kw(var[1]))
+    res, colors = _gpu_bgpc(cuda, g, **var[1])
+    _compare_full(res, colors, ref)
+    adj = synth.rmat(11, 8, 0.57, 0.19, 0.19, seed=4)
+    ref = oracle.d2gc(adj, **_oracle_kw(var[1]))
+    res, colors = _gpu_d2(cuda, adj, **var[1])
+    _compare_full(res, colors, ref)
+
+
+@pytest.mark.parametrize("sched", [("V-V", dict()), ("N1", dict(net_color_mask=1)), ("B2", dict(policy=2)),
+                                   ("V-then-N", dict(net_color_mask=0b10)), ("alg6-N1", dict(net_color_mask=1, net_alg=1))],
+                         ids=lambda s: s[0])
+def test_vertex_form_removal(cuda, sched):
+    """net_conflict_mask = 0: the vertex form (Algorithm 5) wherever it is
+    exact, the net form elsewhere; same rounds and colors as the oracle."""
+    for g in (synth.random_uniform(5003, 4001, 2, 8, 11), synth.stencil27(24)):
+        ref = oracle.bgpc(g, **sched[1])
+        res, colors = _gpu_bgpc(cuda, g, net_conflict_mask=0, **sched[1])
+        _compare_full(res, colors, ref)
+        # every other round in the vertex form
+        res, colors = _gpu_bgpc(cuda, g, net_conflict_mask=0x5555555555555555, **sched[1])
+        _compare_full(res, colors, ref)
+    adj = synth.rmat(11, 8, 0.57, 0.19, 0.19, seed=4)
+    ref = oracle.d2gc(adj, net_color_mask=1)
+    res, colors = _gpu_d2(cuda, adj, net_color_mask=1, net_conflict_mask=0)
+    _compare_full(res, colors, ref)
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(net_color_mask=0b101), dict(policy=2, chunk=9),
+                                dict(net_color_mask=1, flags=8, policy=1)], ids=str)
+def test_round_hashes_and_times(cuda, kw):
+    """FNV-1a-64 of the tentative colors after each round's coloring step and
+    of the colors after each round, against the oracle's; per-round event
+    times are positive and sum to at most the call."""
+    g = synth.random_uniform(5003, 4001, 2, 8, 11)
+    ref = oracle.bgpc(g, **_oracle_kw(kw))
+    res, colors = _gpu_bgpc(cuda, g, log_hashes=True, **kw)
+    _compare_full(res, colors, ref)
+    assert np.array_equal(res.log["hash_t"], ref.log["hash_t"])
+    assert np.array_equal(res.log["hash_c"], ref.log["hash_c"])
+    big = synth.stencil27(40)
+    res, _ = _gpu_bgpc(cuda, big)
+    assert (res.log["round_ms"] > 0).all() and len(res.log["round_ms"]) == res.rounds
