@@ -526,7 +526,7 @@ def summarize_counters(fetch_dir, write_dir, workload):
     kernels = {}
     round0, in_r0, seen_color = 0.0, False, False
     for i, ((name, fv), (_, wv)) in enumerate(zip(fetch, write)):
-        if i in cal:
+        if i in cal or "bgpc::" not in name:   # the library's kernels only
             continue
         k = _short(name)
         b = 1024.0 * (fv * f_read + wv * f_write)

@@ -57,6 +57,8 @@ def _load():
         lib.oracle_color_stats.argtypes = [P, i64, P, P]
         lib.oracle_color_stats.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_order_smallest_last.argtypes = [i32, i32, P, P, P, P, i32, i32, i32, P]
+        lib.oracle_order_smallest_last.restype = ctypes.c_int64
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_set_threads.restype = None
         _lib = lib
@@ -288,3 +290,32 @@ def d2gc_order_largest_first(adj) -> np.ndarray:
     owner = np.repeat(np.arange(n), deg)
     np.add.at(key, owner, deg[np.asarray(adj.idx, dtype=np.int64)])
     return np.lexsort((np.arange(n), -key)).astype(np.int32)
+
+
+def _smallest_last(n, a_off, a_idx, b_off, b_idx, n_b, d2, batched, slack_shift=63):
+    lib = _load()
+    a_off, b_off, a_idx, b_idx = _c64(a_off), _c64(b_off), _c32(a_idx), _c32(b_idx)
+    out = np.empty(max(n, 1), dtype=np.int32)
+    steps = lib.oracle_order_smallest_last(int(n), int(n_b), _ptr(a_off), _ptr(a_idx), _ptr(b_off), _ptr(b_idx),
+                                           int(d2), int(bool(batched)), int(slack_shift), _ptr(out))
+    if steps < 0:
+        raise RuntimeError("oracle_order_smallest_last failed")
+    return out[:n], int(steps)
+
+
+def order_smallest_last(g, batched: bool = True, with_steps: bool = False):
+    """Smallest-last order of a bipartite graph (Section VI's other order):
+    vertices are removed smallest key first -- key(u) = sum over the nets of u
+    of (members still present - 1) -- and ranked in reverse removal order.
+    batched: every vertex at the current minimum key leaves in one step (ranks
+    of a step ascending by id); else one vertex per step, ties to the lowest
+    id (quadratic: small graphs only).  Returns order[k] = vertex of rank k
+    (and the number of steps with with_steps)."""
+    o, st = _smallest_last(g.n_a, g.a_off, g.a_idx, g.b_off, g.b_idx, g.n_b, 0, batched)
+    return (o, st) if with_steps else o
+
+
+def d2gc_order_smallest_last(adj, batched: bool = True, with_steps: bool = False):
+    """The same order for distance-2 coloring (nets = closed neighbourhoods)."""
+    o, st = _smallest_last(adj.n, adj.off, adj.idx, adj.off, adj.idx, adj.n, 1, batched)
+    return (o, st) if with_steps else o

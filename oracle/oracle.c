@@ -860,6 +860,94 @@ int oracle_color_stats(const int32_t *colors, int64_t n, int64_t *out_i, double 
     return OR_OK;
 }
 
+/*
+ * Smallest-last processing orders (Section VI compares the natural order with
+ * ColPack's smallest-last order).  The degree of a vertex u is counted as in
+ * the largest-first order: key(u) = the number of (net, other member) pairs
+ * of u among the vertices not yet removed, sum over v in nets(u) of
+ * (|vtxs(v) still present| - 1), an upper bound of its distance-2 degree
+ * (distance-2: the nets are the closed neighbourhoods).  Vertices are removed
+ * smallest key first; the processing order is the reverse of the removal
+ * sequence (the last vertex removed gets rank 0).
+ *   batched = 0  one vertex per step: the smallest key, ties to the lowest id
+ *                (ColPack's peeling with a fixed tie rule; cost quadratic in
+ *                |V_A|, for small graphs)
+ *   batched = 1  every vertex whose key equals the current minimum is removed
+ *                in the same step; a step's vertices take consecutive ranks in
+ *                ascending id, steps in reverse order of removal (the form
+ *                the device computes in parallel)
+ * order_out[k] = the vertex of rank k.  Returns the number of steps.
+ */
+int64_t oracle_order_smallest_last(int32_t n_a, int32_t n_b, const int64_t *a_off, const int32_t *a_idx,
+                                   const int64_t *b_off, const int32_t *b_idx, int32_t d2, int32_t batched,
+                                   int32_t slack_shift, int32_t *order_out)
+{
+    graph_t g = {n_a, n_b, d2, a_off, a_idx, b_off, b_idx};
+    int64_t *key = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n_a + 1));
+    uint8_t *gone = (uint8_t *)calloc((size_t)n_a + 1, 1);
+    int32_t *seq = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n_a + 1));   /* removal sequence */
+    int64_t *step_end = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n_a + 1));
+    int32_t *batch = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n_a + 1));
+    if (!key || !gone || !seq || !step_end || !batch) {
+        free(key); free(gone); free(seq); free(step_end); free(batch);
+        return -1;
+    }
+    #pragma omp parallel for schedule(dynamic, 1024)
+    for (int32_t u = 0; u < n_a; u++) {
+        int64_t k = 0, kn = nets_count(&g, u);
+        for (int64_t a = 0; a < kn; a++) k += vtxs_count(&g, net_at(&g, u, a)) - 1;
+        key[u] = k;
+    }
+    int64_t removed = 0, steps = 0;
+    while (removed < n_a) {
+        int64_t d = INT64_MAX;
+        int32_t first = -1;
+        for (int32_t u = 0; u < n_a; u++)
+            if (!gone[u] && key[u] < d) { d = key[u]; first = u; }
+        int64_t nb = 0;
+        if (batched) {
+            const int64_t thr = slack_shift >= 63 ? d : d + (d >> slack_shift);
+            for (int32_t u = 0; u < n_a; u++)
+                if (!gone[u] && key[u] <= thr) batch[nb++] = u;
+        } else {
+            batch[nb++] = first;
+        }
+        for (int64_t i = 0; i < nb; i++) {
+            gone[batch[i]] = 1;
+            seq[removed + i] = batch[i];
+        }
+        /* every (net, removed member) pair leaves the keys of the members
+         * still present */
+        #pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t i = 0; i < nb; i++) {
+            int32_t u = batch[i];
+            int64_t kn = nets_count(&g, u);
+            for (int64_t a = 0; a < kn; a++) {
+                int32_t v = net_at(&g, u, a);
+                int64_t kv = vtxs_count(&g, v);
+                for (int64_t b = 0; b < kv; b++) {
+                    int32_t x = vtx_at(&g, v, b);
+                    if (!gone[x]) {
+                        #pragma omp atomic
+                        key[x] -= 1;
+                    }
+                }
+            }
+        }
+        removed += nb;
+        step_end[steps++] = removed;
+    }
+    /* ranks: steps in reverse, each step's vertices in ascending id (a step's
+     * vertices were collected in ascending id) */
+    int64_t k = 0;
+    for (int64_t st = steps - 1; st >= 0; st--) {
+        int64_t lo = st ? step_end[st - 1] : 0, hi = step_end[st];
+        for (int64_t i = lo; i < hi; i++) order_out[k++] = seq[i];
+    }
+    free(key); free(gone); free(seq); free(step_end); free(batch);
+    return steps;
+}
+
 int oracle_num_threads(void) { return omp_get_max_threads(); }
 
 /* threads of the parallel loops from now on (the CPU-baseline timings) */

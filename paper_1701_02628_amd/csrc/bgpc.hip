@@ -1356,7 +1356,11 @@ BGPC_API int color_stats(const int32_t *colors, int64_t n, void *stream, bgpc_st
     d_i = (long long *)(blk + aligned(ncol, 4));
     d_d = (double *)(blk + aligned(ncol, 4) + aligned(5, 8));
     k_fill_i32<<<grid_for(ncol, 256, di.cus * 8), 256, 0, s>>>(d_count, 0, ncol);
-    k_hist<<<grid_for(n, 256, di.cus * 8), 256, 0, s>>>(colors, n, d_count, ncol);
+    // with LDS histograms, few enough blocks that each one's flush (ncol
+    // atomics at most) stays below the atomics it saves
+    const int g_hist = ncol <= HIST_LDS ? (int)std::max<long>(1, std::min<long>(di.cus * 8, n / (8L * ncol)))
+                                        : grid_for(n, 256, di.cus * 8);
+    k_hist<<<g_hist, 256, 0, s>>>(colors, n, d_count, ncol);
     k_hist_reduce<<<1, 1024, 0, s>>>(d_count, ncol, d_i, d_d);
     long long hi[5];
     double hd[2];

@@ -2452,11 +2452,27 @@ __global__ void k_drop_proposals(int *st, int n)
 // ---------------------------------------------------------------------------
 // color-set statistics
 
+// Set cardinalities.  Up to HIST_LDS colors each block counts into its own
+// LDS histogram and adds it to the global one once (many vertices share a
+// few colors: per-vertex atomics on one global counter would serialize);
+// beyond that, global atomics per vertex.
+constexpr int HIST_LDS = 12288;
 __global__ void k_hist(const int *colors, long n, int *count, int ncolors)
 {
+    __shared__ int s_cnt[HIST_LDS];
+    const bool local = ncolors <= HIST_LDS;
+    if (local) {
+        for (int c = threadIdx.x; c < ncolors; c += blockDim.x) s_cnt[c] = 0;
+        __syncthreads();
+    }
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         int c = colors[i];
-        if (c >= 0 && c < ncolors) atomicAdd(&count[c], 1);
+        if (c >= 0 && c < ncolors) atomicAdd(local ? &s_cnt[c] : &count[c], 1);
+    }
+    if (local) {
+        __syncthreads();
+        for (int c = threadIdx.x; c < ncolors; c += blockDim.x)
+            if (s_cnt[c]) atomicAdd(&count[c], s_cnt[c]);
     }
 }
 
