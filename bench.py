@@ -56,6 +56,11 @@ def parse():
                    help="first copy 256 MiB device to device (a kernel of known traffic for HBM counters)")
     p.add_argument("--counter-run", action="store_true",
                    help="stencil128: one plain call and exit (the program the rocprofv3 --pmc passes profile)")
+    p.add_argument("--study", choices=["orders", "net-alg", "net-balance"],
+                   help="tables of the paper's comparisons on the full-size workloads (one JSON line each): "
+                        "processing orders (natural, largest-first, smallest-last) on the stencil, skewed and "
+                        "R-MAT workloads; Algorithm 6 / 6 with reverse start / 8 in the first net-based round; "
+                        "balancing in net-based rounds")
     p.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "WORKLOAD"),
                    help="no GPU: read the FETCH_SIZE and WRITE_SIZE counter CSVs of two --counter-run passes "
                         "and write the calibrated per-kernel bytes into profiles/traffic.json")
@@ -83,6 +88,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     wl = WORKLOADS[args.workload]
+    if args.study:
+        run_study(args)
+        return
     if args.workload == "batch4096":
         run_batch(args, wl)
         return
@@ -300,6 +308,99 @@ def run_large(args, wl):
                                 "gpu_seconds_same_rounds": t_gpu_R,
                                 "matches_gpu_same_rounds": bool(np.array_equal(ref.colors, o2.cpu().numpy()))}
     print(json.dumps(line), flush=True)
+
+
+def run_study(args):
+    """One JSON line per measurement of the comparisons the paper makes
+    (Section III's first-round table, Section V's balancing, Section VI's
+    orders), on the full-size synthetic workloads; colors are checked valid
+    by the library's own statistics only (parity is the tests' job)."""
+    import numpy as np
+    import torch
+
+    from paper_1701_02628_amd import bgpc, synth
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        r = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1)
+
+    def emit(d):
+        print(json.dumps(d), flush=True)
+
+    if args.study == "orders":
+        for name, cfg, mask in (("stencil128", 1, 0), ("skewed4m", 2, 1), ("rmat22_d2", 3, 1)):
+            g = synth.config(cfg)
+            d2 = cfg == 3
+            if d2:
+                D = bgpc.upload_adjacency(g)
+                n = g.n
+                color = lambda out, order: bgpc.d2gc_color(D, order, out, net_color_mask=mask, stream=stream)
+                orders = {"largest_first": lambda: bgpc.d2gc_order_largest_first(D, stream=stream),
+                          "smallest_last": lambda: bgpc.d2gc_order_smallest_last(D, 3, stream=stream, with_steps=True)}
+            else:
+                A, B = bgpc.upload_bipartite(g)
+                n = g.n_a
+                color = lambda out, order: bgpc.bgpc_color(A, B, order, out, net_color_mask=mask, stream=stream)
+                orders = {"largest_first": lambda: bgpc.order_largest_first(A, B, stream=stream),
+                          "smallest_last": lambda: bgpc.order_smallest_last(A, B, 3, stream=stream, with_steps=True)}
+            out = torch.empty(n, dtype=torch.int32, device="cuda")
+            for oname in ("natural", "largest_first", "smallest_last"):
+                steps, order_ms, order = None, 0.0, None
+                if oname != "natural":
+                    res, order_ms = timed(orders[oname])
+                    order, steps = res if isinstance(res, tuple) else (res, None)
+                color(out, order)   # warm-up
+                r, ms = timed(lambda: color(out, order))
+                st = bgpc.color_stats(out)
+                emit({"study": "orders", "workload": name, "order": oname, "rounds": r.rounds,
+                      "colors": st["n_distinct"], "call_ms": ms, "order_ms": order_ms, "order_steps": steps,
+                      "status": r.status})
+            del out
+            torch.cuda.empty_cache()
+    elif args.study == "net-alg":
+        for name, cfg in (("stencil128", 1), ("skewed4m", 2)):
+            g = synth.config(cfg)
+            A, B = bgpc.upload_bipartite(g)
+            out = torch.empty(g.n_a, dtype=torch.int32, device="cuda")
+            for alg, aname in ((1, "alg6"), (2, "alg6_reverse"), (0, "alg8")):
+                r1 = bgpc.bgpc_color(A, B, None, out, net_color_mask=1, net_alg=alg, max_rounds=1, log_cap=4,
+                                     stream=stream)
+                r2 = bgpc.bgpc_color(A, B, None, out, net_color_mask=0b11, net_alg=alg, max_rounds=2, log_cap=4,
+                                     stream=stream)
+                r, ms = timed(lambda: bgpc.bgpc_color(A, B, None, out, net_color_mask=1, net_alg=alg, stream=stream))
+                st = bgpc.color_stats(out)
+                emit({"study": "net-alg", "workload": name, "net_alg": aname, "n_b": g.n_b,
+                      "remaining_after_round0": int(r1.log["losers"][0]),
+                      "remaining_after_two_net_rounds": int(r2.log["losers"][1]),
+                      "n1_then_v": {"rounds": r.rounds, "colors": st["n_distinct"], "call_ms": ms}})
+    else:
+        g = synth.config(2)
+        A, B = bgpc.upload_bipartite(g)
+        out = torch.empty(g.n_a, dtype=torch.int32, device="cuda")
+        base = None
+        for pol, pname in ((0, "U"), (1, "B1"), (2, "B2"), (3, "B1G")):
+            for flags, fname in ((0, "vertex rounds only"), (bgpc.NET_BALANCE, "net and vertex rounds")):
+                if pol == 0 and flags:
+                    continue
+                bgpc.bgpc_color(A, B, None, out, net_color_mask=1, policy=pol, flags=flags, stream=stream)
+                r, ms = timed(lambda: bgpc.bgpc_color(A, B, None, out, net_color_mask=1, policy=pol, flags=flags,
+                                                      stream=stream))
+                st = bgpc.color_stats(out)
+                if base is None:
+                    base = (ms, st)
+                emit({"study": "net-balance", "workload": "skewed4m", "schedule": "N1 then V", "policy": pname,
+                      "balanced": fname, "status": r.status, "rounds": r.rounds, "call_ms": ms,
+                      "colors": st["n_distinct"], "card_max": st["card_max"], "card_mean": st["card_mean"],
+                      "card_std": st["card_std"],
+                      "vs_U": {"time": ms / base[0], "sets": st["n_distinct"] / base[1]["n_distinct"],
+                               "mean": st["card_mean"] / base[1]["card_mean"],
+                               "std": st["card_std"] / base[1]["card_std"]}})
 
 
 def _gen(i):

@@ -176,6 +176,27 @@ typedef struct {
                                  equal to bytes for the coloring kernel */
 } bgpc_profile;
 
+/*
+ * Launch and data-structure choices of bgpc_color / d2gc_color that do not
+ * change any result (every value gives the same colors and rounds): picked
+ * by the library from the graph's shape, by bgpc_autotune, or by the caller.
+ * -1 (0 for the grids): the library's choice.
+ */
+typedef struct {
+    int32_t front;         /* front-driven first-fit rounds (only vertices whose nets hold color 0 are
+                              recolored; removal over the nets whose members changed; winners from the
+                              vertices whose loss count dropped to 0): 0 off, 1 on where the schedule
+                              allows it (vertex-based first-fit, nets of at most 64 members, needs
+                              standing proposals) */
+    int32_t standing;      /* standing proposals in vertex-based rounds (a loser keeps its proposal and
+                              only nets with a changed member are scanned again): 0 off, 1 on */
+    int32_t planes;        /* per-net 64-bit color words past color 63: 0 off (per-vertex LDS bitmaps
+                              from the distance-2 walk), 1 on */
+    int32_t color_grid;    /* workgroups per CU of the first-fit launch (a wave each) */
+    int32_t removal_grid;  /* workgroups per CU of the removal launches */
+    int32_t apply_grid;    /* workgroups per CU of the apply / compaction launches */
+} bgpc_tuning;
+
 typedef struct {
     uint64_t net_color_mask;  /* bit r (r < 64): round r is net-based */
     int32_t policy;           /* BGPC_FIRST_FIT, BGPC_B1 or BGPC_B2 */
@@ -198,6 +219,8 @@ typedef struct {
                                     whatever the bit.  Default all ones */
     int32_t net_alg;          /* BGPC_NET_ALG8 (default), BGPC_NET_ALG6, BGPC_NET_ALG6_REVERSE */
     int32_t reserved2;
+    const bgpc_tuning *tuning;  /* NULL: the choices bgpc_autotune cached for graphs of this shape, else the
+                                   library's rules */
 } bgpc_opts;
 
 /* Fills *opts with the defaults: vertex-based first-fit rounds, chunk 64,
@@ -235,6 +258,23 @@ BGPC_API int d2gc_color(const bgpc_csr *adj, const int32_t *order, const bgpc_op
                         int32_t *colors_out);
 
 /*
+ * Autotuner: times bgpc_color (csr_B non-NULL) or d2gc_color (csr_B NULL: the
+ * symmetric adjacency csr_A) on the caller's graph under `opts` for each
+ * candidate choice of bgpc_tuning, one field at a time (coordinate descent
+ * from the library's choices; front, standing, planes, then the three grids),
+ * keeping a candidate only when it is faster over `trials` calls (the
+ * fastest of them).  Every candidate's colors and rounds must equal the
+ * library's default choices' (else BGPC_E_INTERNAL: a tuning changed a
+ * result).  The best choice is written to *best and cached for graphs of the
+ * same shape (distance-2 or not, schedule and policy class, log2 of |V_A|,
+ * |V_B| and nnz / |V_A|): later calls whose opts->tuning is NULL use it.
+ * Allocates two color arrays; colors_scratch may be NULL.  *ms_default and
+ * *ms_best (optional) receive the default and the tuned call times.
+ */
+BGPC_API int bgpc_autotune(const bgpc_csr *csr_A, const bgpc_csr *csr_B, const bgpc_opts *opts, int32_t trials,
+                           bgpc_tuning *best, double *ms_default, double *ms_best);
+
+/*
  * Largest-first processing order (the paper's experiments compare processing
  * orders, Section VI; this is the cheap degree-based one, computed on the
  * device): vertices by decreasing key(u) = sum over the nets v of u of
@@ -254,6 +294,32 @@ BGPC_API int d2gc_color(const bgpc_csr *adj, const int32_t *order, const bgpc_op
 BGPC_API int bgpc_order_largest_first(const bgpc_csr *csr_A, const bgpc_csr *csr_B, void *stream,
                                       int32_t *order_out);
 BGPC_API int d2gc_order_largest_first(const bgpc_csr *adj, void *stream, int32_t *order_out);
+
+/*
+ * Smallest-last processing order (Section VI compares the natural order with
+ * ColPack's smallest-last order), computed on the device by removal steps:
+ * with key(u) = the number of (net, other member) pairs of u among the
+ * vertices still present (the largest-first key, recounted as vertices
+ * leave; distance-2: over the closed neighbourhoods), each step removes every
+ * present vertex whose key is at most d + (d >> slack_shift), d the smallest
+ * key present (slack_shift >= 63: exactly the vertices at d).  Ranks run
+ * over the steps in reverse (the last step's vertices first), a step's
+ * vertices in ascending id.  The one-vertex-at-a-time peeling of ColPack is
+ * sequential; the steps trade its tie order for parallel removal, and a
+ * slack of 1/8 (slack_shift 3) keeps the steps to a few hundred on the
+ * workloads measured (an exact minimum takes thousands to tens of thousands).
+ *   csr_A, csr_B / adj  as for bgpc_color / d2gc_color (trusted)
+ *   stream              hipStream_t or NULL; returns once the order is done
+ *   order_out           device int32[|V_A|] (resp. [n]): the vertex of each rank
+ *   steps_out           optional host int32: removal steps taken
+ * Allocates its own workspace (two uint64 and five int32 per vertex, one
+ * int32 per net, the selection scratch); every step waits for the host once.
+ * BGPC_E_INVALID for inconsistent sizes, a NULL output or slack_shift < 0.
+ */
+BGPC_API int bgpc_order_smallest_last(const bgpc_csr *csr_A, const bgpc_csr *csr_B, int32_t slack_shift,
+                                      void *stream, int32_t *order_out, int32_t *steps_out);
+BGPC_API int d2gc_order_smallest_last(const bgpc_csr *adj, int32_t slack_shift, void *stream, int32_t *order_out,
+                                      int32_t *steps_out);
 
 /*
  * Color-set statistics of a coloring (the metrics of the balancing

@@ -303,19 +303,20 @@ def _smallest_last(n, a_off, a_idx, b_off, b_idx, n_b, d2, batched, slack_shift=
     return out[:n], int(steps)
 
 
-def order_smallest_last(g, batched: bool = True, with_steps: bool = False):
+def order_smallest_last(g, batched: bool = True, with_steps: bool = False, slack_shift: int = 63):
     """Smallest-last order of a bipartite graph (Section VI's other order):
     vertices are removed smallest key first -- key(u) = sum over the nets of u
     of (members still present - 1) -- and ranked in reverse removal order.
     batched: every vertex at the current minimum key leaves in one step (ranks
-    of a step ascending by id); else one vertex per step, ties to the lowest
-    id (quadratic: small graphs only).  Returns order[k] = vertex of rank k
-    (and the number of steps with with_steps)."""
-    o, st = _smallest_last(g.n_a, g.a_off, g.a_idx, g.b_off, g.b_idx, g.n_b, 0, batched)
+    of a step ascending by id); with slack_shift < 63 a step takes every key
+    up to d + (d >> slack_shift), d the minimum; else one vertex per step,
+    ties to the lowest id (quadratic: small graphs only).  Returns order[k] =
+    vertex of rank k (and the number of steps with with_steps)."""
+    o, st = _smallest_last(g.n_a, g.a_off, g.a_idx, g.b_off, g.b_idx, g.n_b, 0, batched, slack_shift)
     return (o, st) if with_steps else o
 
 
-def d2gc_order_smallest_last(adj, batched: bool = True, with_steps: bool = False):
+def d2gc_order_smallest_last(adj, batched: bool = True, with_steps: bool = False, slack_shift: int = 63):
     """The same order for distance-2 coloring (nets = closed neighbourhoods)."""
-    o, st = _smallest_last(adj.n, adj.off, adj.idx, adj.off, adj.idx, adj.n, 1, batched)
+    o, st = _smallest_last(adj.n, adj.off, adj.idx, adj.off, adj.idx, adj.n, 1, batched, slack_shift)
     return (o, st) if with_steps else o

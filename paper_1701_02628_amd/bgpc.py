@@ -51,7 +51,20 @@ class Opts(ctypes.Structure):
                 ("max_rounds", ctypes.c_int32), ("start_round", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p), ("log", ctypes.POINTER(RoundLog)),
                 ("rounds_out", ctypes.POINTER(ctypes.c_int32)), ("prof", ctypes.POINTER(Profile)),
-                ("net_conflict_mask", ctypes.c_uint64), ("net_alg", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+                ("net_conflict_mask", ctypes.c_uint64), ("net_alg", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+                ("tuning", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("front", ctypes.c_int32), ("standing", ctypes.c_int32), ("planes", ctypes.c_int32),
+                ("color_grid", ctypes.c_int32), ("removal_grid", ctypes.c_int32), ("apply_grid", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def tuning(front=-1, standing=-1, planes=-1, color_grid=0, removal_grid=0, apply_grid=0):
+    return Tuning(front, standing, planes, color_grid, removal_grid, apply_grid)
 
 
 class BatchItem(ctypes.Structure):
@@ -116,6 +129,16 @@ def load():
         lib.bgpc_order_largest_first.restype = ctypes.c_int
         lib.d2gc_order_largest_first.argtypes = [ctypes.POINTER(Csr), P, P]
         lib.d2gc_order_largest_first.restype = ctypes.c_int
+        lib.bgpc_autotune.argtypes = [ctypes.POINTER(Csr), ctypes.POINTER(Csr), ctypes.POINTER(Opts), ctypes.c_int32,
+                                      ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]
+        lib.bgpc_autotune.restype = ctypes.c_int
+        lib.bgpc_order_smallest_last.argtypes = [ctypes.POINTER(Csr), ctypes.POINTER(Csr), ctypes.c_int32, P, P,
+                                                 ctypes.POINTER(ctypes.c_int32)]
+        lib.bgpc_order_smallest_last.restype = ctypes.c_int
+        lib.d2gc_order_smallest_last.argtypes = [ctypes.POINTER(Csr), ctypes.c_int32, P, P,
+                                                 ctypes.POINTER(ctypes.c_int32)]
+        lib.d2gc_order_smallest_last.restype = ctypes.c_int
         lib.bgpc_status_string.argtypes = [ctypes.c_int]
         lib.bgpc_status_string.restype = ctypes.c_char_p
         _lib = lib
@@ -124,7 +147,8 @@ def load():
 
 EXPORTED = ("bgpc_opts_default", "bgpc_color", "d2gc_color", "color_stats", "bgpc_status_string",
             "bgpc_color_batch", "bgpc_session_create", "bgpc_session_submit", "bgpc_session_poll",
-            "bgpc_session_destroy", "bgpc_order_largest_first", "d2gc_order_largest_first")
+            "bgpc_session_destroy", "bgpc_order_largest_first", "d2gc_order_largest_first",
+            "bgpc_order_smallest_last", "d2gc_order_smallest_last", "bgpc_autotune")
 
 
 def status_string(code: int) -> str:
@@ -191,7 +215,7 @@ class Result:
 
 
 def _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags, stream, log_cap, prof=None,
-               net_conflict_mask=ALL_NET, net_alg=NET_ALG8, log_hashes=False):
+               net_conflict_mask=ALL_NET, net_alg=NET_ALG8, log_hashes=False, tune=None):
     lib = load()
     o = Opts()
     lib.bgpc_opts_default(ctypes.byref(o))
@@ -204,6 +228,9 @@ def _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags, st
     rounds = ctypes.c_int32(0)
     o.rounds_out = ctypes.pointer(rounds)
     keep = [rounds]
+    if tune is not None:
+        o.tuning = ctypes.cast(ctypes.pointer(tune), ctypes.c_void_p)
+        keep.append(tune)
     log_arrays = None
     if log_cap:
         log_arrays = {"mode": np.zeros(log_cap, np.int32), "w": np.zeros(log_cap, np.int64),
@@ -235,12 +262,13 @@ def _finish(status, rounds, log_arrays, o):
 
 def bgpc_color(csr_A: DeviceCsr, csr_B: DeviceCsr, order, colors_out, net_color_mask=0, policy=FIRST_FIT,
                chunk=64, max_rounds=0, start_round=0, flags=0, stream=None, log_cap=0, prof=None,
-               net_conflict_mask=ALL_NET, net_alg=NET_ALG8, log_hashes=False) -> Result:
+               net_conflict_mask=ALL_NET, net_alg=NET_ALG8, log_hashes=False, tune=None) -> Result:
     """Bipartite-graph partial coloring; colors_out is an int32 GPU tensor of |V_A|.
-    prof: optional Profile struct (kernel timing), filled in place."""
+    prof: optional Profile struct (kernel timing), filled in place; tune:
+    optional Tuning (result-invariant launch choices)."""
     lib = load()
     o, rounds, log_arrays, keep = _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags,
-                                             stream, log_cap, prof, net_conflict_mask, net_alg, log_hashes)
+                                             stream, log_cap, prof, net_conflict_mask, net_alg, log_hashes, tune)
     a, b = csr_A.as_struct(), csr_B.as_struct()
     order_p = _dev_ptr(order, "order") if order is not None else None
     st = lib.bgpc_color(ctypes.byref(a), ctypes.byref(b), order_p, ctypes.byref(o), _dev_ptr(colors_out, "colors_out"))
@@ -250,11 +278,11 @@ def bgpc_color(csr_A: DeviceCsr, csr_B: DeviceCsr, order, colors_out, net_color_
 
 def d2gc_color(adj: DeviceCsr, order, colors_out, net_color_mask=0, policy=FIRST_FIT, chunk=64, max_rounds=0,
                start_round=0, flags=0, stream=None, log_cap=0, prof=None, net_conflict_mask=ALL_NET,
-               net_alg=NET_ALG8, log_hashes=False) -> Result:
+               net_alg=NET_ALG8, log_hashes=False, tune=None) -> Result:
     """Distance-2 coloring of a symmetric graph; colors_out is an int32 GPU tensor of n."""
     lib = load()
     o, rounds, log_arrays, keep = _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags,
-                                             stream, log_cap, prof, net_conflict_mask, net_alg, log_hashes)
+                                             stream, log_cap, prof, net_conflict_mask, net_alg, log_hashes, tune)
     a = adj.as_struct()
     order_p = _dev_ptr(order, "order") if order is not None else None
     st = lib.d2gc_color(ctypes.byref(a), order_p, ctypes.byref(o), _dev_ptr(colors_out, "colors_out"))
@@ -286,6 +314,54 @@ def d2gc_order_largest_first(adj: DeviceCsr, stream=None):
     if st != OK:
         raise RuntimeError(f"d2gc_order_largest_first failed: {status_string(st)}")
     return out
+
+
+def autotune(csr_A: DeviceCsr, csr_B=None, trials=3, stream=None, **kw):
+    """Tune the result-invariant choices for this graph (csr_B None: distance-2
+    on the adjacency csr_A) under the given schedule (net_color_mask, policy,
+    chunk, flags as for bgpc_color); returns (Tuning, default ms, tuned ms).
+    The choice is cached in the library for graphs of the same shape."""
+    lib = load()
+    o, rounds, _, keep = _make_opts(kw.get("net_color_mask", 0), kw.get("policy", FIRST_FIT), kw.get("chunk", 64),
+                                    0, 0, kw.get("flags", 0), stream, 0)
+    best = Tuning()
+    md, mb = ctypes.c_double(0), ctypes.c_double(0)
+    a = csr_A.as_struct()
+    b = csr_B.as_struct() if csr_B is not None else None
+    st = lib.bgpc_autotune(ctypes.byref(a), ctypes.byref(b) if b is not None else None, ctypes.byref(o), int(trials),
+                           ctypes.byref(best), ctypes.byref(md), ctypes.byref(mb))
+    del keep
+    if st != OK:
+        raise RuntimeError(f"bgpc_autotune failed: {status_string(st)}")
+    return best, md.value, mb.value
+
+
+def order_smallest_last(csr_A: DeviceCsr, csr_B: DeviceCsr, slack_shift=3, stream=None, with_steps=False):
+    """Smallest-last order of V_A by removal steps (int32 GPU tensor, order[k] = vertex of rank k)."""
+    import torch
+    lib = load()
+    out = torch.empty(max(csr_A.n_rows, 1), dtype=torch.int32, device=csr_A.offsets.device)[:csr_A.n_rows]
+    steps = ctypes.c_int32(0)
+    a, b = csr_A.as_struct(), csr_B.as_struct()
+    st = lib.bgpc_order_smallest_last(ctypes.byref(a), ctypes.byref(b), int(slack_shift), _stream_handle(stream),
+                                      _dev_ptr(out, "order_out") if csr_A.n_rows else None, ctypes.byref(steps))
+    if st != OK:
+        raise RuntimeError(f"bgpc_order_smallest_last failed: {status_string(st)}")
+    return (out, steps.value) if with_steps else out
+
+
+def d2gc_order_smallest_last(adj: DeviceCsr, slack_shift=3, stream=None, with_steps=False):
+    """Smallest-last order of a symmetric graph's vertices (closed neighbourhoods as nets)."""
+    import torch
+    lib = load()
+    out = torch.empty(max(adj.n_rows, 1), dtype=torch.int32, device=adj.offsets.device)[:adj.n_rows]
+    steps = ctypes.c_int32(0)
+    a = adj.as_struct()
+    st = lib.d2gc_order_smallest_last(ctypes.byref(a), int(slack_shift), _stream_handle(stream),
+                                      _dev_ptr(out, "order_out") if adj.n_rows else None, ctypes.byref(steps))
+    if st != OK:
+        raise RuntimeError(f"d2gc_order_smallest_last failed: {status_string(st)}")
+    return (out, steps.value) if with_steps else out
 
 
 def color_stats(colors, stream=None) -> dict:

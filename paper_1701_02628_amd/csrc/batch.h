@@ -654,7 +654,9 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch(BatchItem *items, const i
 struct ServeRing {
     int tail;       // descriptors published (items[k % cap] for k < tail)
     int stop;       // set by the host: workgroups exit
-    int pad[62];
+    int active;     // workgroups inside k_serve (read by the host)
+    int claimed;    // descriptors claimed so far (the largest claim + 1; read by the host)
+    int pad[60];
     BatchItem items[1];
 };
 
@@ -664,13 +666,16 @@ struct ServeRing {
 // used), copies the descriptor to LDS and runs the graph; the graph's
 // completion reaches the host through its done word.  A workgroup leaves
 // after idle_spins empty polls (about 20 ms) or when stop is set, so every
-// wave exits; the host launches the kernel again when it publishes work and
-// none is running.
+// wave exits.  Workgroups count themselves in `active` and publish the
+// claims in `claimed`, so the host can launch more workgroups (another launch
+// of this kernel, on another stream) while published requests wait
+// unclaimed behind the few workgroups still busy with long graphs.
 __global__ void __launch_bounds__(BATCH_BLOCK) k_serve(ServeRing *ring, int cap, int *head, int idle_spins)
 {
     __shared__ int s_k;
     __shared__ unsigned long long s_desc[(sizeof(BatchItem) + 7) / 8];
     const int tid = threadIdx.x;
+    if (tid == 0) __hip_atomic_fetch_add(&ring->active, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     for (;;) {
         if (tid == 0) {
             int k = -1;
@@ -680,6 +685,7 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_serve(ServeRing *ring, int cap,
                 if (h < t) {
                     if (atomicCAS(head, h, h + 1) == h) {
                         k = h;
+                        __hip_atomic_fetch_max(&ring->claimed, h + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                         break;
                     }
                     spin = 0;   // another workgroup took it: not idle
@@ -693,7 +699,10 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_serve(ServeRing *ring, int cap,
         }
         __syncthreads();
         const int k = s_k;
-        if (k < 0) break;
+        if (k < 0) {
+            if (tid == 0) __hip_atomic_fetch_add(&ring->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            break;
+        }
         const unsigned long long *src = (const unsigned long long *)&ring->items[k % cap];
         for (int i = tid; i < (int)((sizeof(BatchItem) + 7) / 8); i += blockDim.x) s_desc[i] = src[i];
         __syncthreads();

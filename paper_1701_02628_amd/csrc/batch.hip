@@ -499,9 +499,11 @@ struct bgpc_session {
     RangeAlloc *alloc = nullptr;
     std::vector<hipStream_t> streams;   // uploads
     std::vector<hipEvent_t> events;     // free upload events
-    hipStream_t kstream = nullptr;      // the serving kernel
-    hipEvent_t kdone = nullptr;         // recorded after each serving-kernel launch
-    bool klaunched = false;
+    static constexpr int KSTREAMS = 3;  // serving-kernel launches that may run at once
+    hipStream_t kstream[KSTREAMS] = {}; // one per launch in flight
+    hipEvent_t kdone[KSTREAMS] = {};    // recorded after each launch
+    bool klaunched[KSTREAMS] = {};
+    std::chrono::steady_clock::time_point klast;   // last launch
     ServeRing *ring = nullptr, *ring_dev = nullptr;
     int cap = 0;                        // ring slots
     std::vector<Req *> slot_owner;      // request in each ring slot until it is done
@@ -522,6 +524,7 @@ struct bgpc_session {
     std::thread worker;
     std::vector<std::thread> dev_workers;
     bool stop = false;              // guarded by mu
+    bool kernels_stopped = false;   // worker only: after an error, the serving kernels have left
     bool dev_stop = false;          // guarded by mu: set once the worker has handed over every request
     int error = 0;
 
@@ -657,6 +660,15 @@ void bgpc_session::loop()
             }
         }
         bool progress = false;
+        if (error && !kernels_stopped) {
+            // a failed call: nothing more is published, and no workgroup may
+            // still read a request's arrays when its pool range is released
+            __atomic_store_n(&ring->stop, 1, __ATOMIC_RELEASE);
+            for (int k = 0; k < KSTREAMS; k++)
+                if (klaunched[k]) (void)hipEventSynchronize(kdone[k]);
+            for (auto &u : uploading) (void)hipEventSynchronize(u.second);
+            kernels_stopped = true;
+        }
         // requests whose graphs are done
         for (size_t i = 0; i < running.size();) {
             if (*running[i]->done != 0 || error) {
@@ -669,7 +681,14 @@ void bgpc_session::loop()
                 i++;
             }
         }
-        // uploaded requests go on the ring, in admission order
+        // uploaded requests go on the ring, in admission order (after an
+        // error they are retired instead)
+        while (!uploading.empty() && error) {
+            events.push_back(uploading.front().second);
+            running.push_back(uploading.front().first);
+            uploading.pop_front();
+            progress = true;
+        }
         while (!uploading.empty()) {
             hipError_t e = hipEventQuery(uploading.front().second);
             if (e == hipErrorNotReady) break;
@@ -679,26 +698,41 @@ void bgpc_session::loop()
             uploading.pop_front();
             progress = true;
         }
-        // the serving kernel runs while published work is not done
-        if (!running.empty()) {
-            bool alive = false;
-            if (klaunched) {
-                hipError_t e = hipEventQuery(kdone);
-                if (e == hipErrorNotReady) alive = true;
-                else if (e != hipSuccess) error = BGPC_E_HIP;
+        // the serving kernel runs while published work is not done: a launch
+        // when none is in flight, and another (on a free stream) when requests
+        // wait unclaimed while fewer than one workgroup per CU is left (the
+        // others having left after their idle polls); at most one launch per
+        // millisecond
+        if (!running.empty() && !error) {
+            int in_flight = 0, free_k = -1;
+            for (int k = 0; k < KSTREAMS; k++) {
+                bool alive = false;
+                if (klaunched[k]) {
+                    hipError_t e = hipEventQuery(kdone[k]);
+                    if (e == hipErrorNotReady) alive = true;
+                    else if (e != hipSuccess) error = BGPC_E_HIP;
+                    else klaunched[k] = false;
+                }
+                if (alive) in_flight++;
+                else if (free_k < 0) free_k = k;
             }
-            if (!alive) {
+            const int active = __atomic_load_n(&ring->active, __ATOMIC_ACQUIRE);
+            const int claimed = __atomic_load_n(&ring->claimed, __ATOMIC_ACQUIRE);
+            const bool starved = tail > claimed && active < cus &&
+                                 std::chrono::steady_clock::now() - klast > std::chrono::milliseconds(1);
+            if (free_k >= 0 && !error && (in_flight == 0 || starved)) {
                 // about 20 ms of empty polls before a workgroup leaves
-                k_serve<<<std::max(1, cus * 2), BATCH_BLOCK, 0, kstream>>>(ring_dev, cap, head, 12000);
-                if (hipGetLastError() != hipSuccess || hipEventRecord(kdone, kstream) != hipSuccess)
+                k_serve<<<std::max(1, cus * 2), BATCH_BLOCK, 0, kstream[free_k]>>>(ring_dev, cap, head, 12000);
+                if (hipGetLastError() != hipSuccess || hipEventRecord(kdone[free_k], kstream[free_k]) != hipSuccess)
                     error = BGPC_E_HIP;
-                klaunched = true;
+                klaunched[free_k] = true;
+                klast = std::chrono::steady_clock::now();
                 progress = true;
             }
         }
         // admit in arrival order while a slot and pool room are free
         int admitted = 0;
-        while (!pending.empty() && slots_used < max_slots && admitted < max_group) {
+        while (!error && !pending.empty() && slots_used < max_slots && admitted < max_group) {
             Req *q = pending.front();
             if (!alloc->alloc(q->bytes, &q->off)) break;
             q->t_admit = now_s();
@@ -812,8 +846,10 @@ BGPC_API bgpc_session *bgpc_session_create(size_t mem_budget, int32_t max_slots,
         ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
         if (ok) S->dev_streams.push_back(st);
     }
-    ok = ok && hipStreamCreateWithFlags(&S->kstream, hipStreamNonBlocking) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&S->kdone, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k < bgpc_session::KSTREAMS; k++) {
+        ok = ok && hipStreamCreateWithFlags(&S->kstream[k], hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&S->kdone[k], hipEventDisableTiming) == hipSuccess;
+    }
     // ring: a few times the slots, so that a slot is normally free again long
     // before its index comes round
     S->cap = std::max(64, 4 * max_slots);
@@ -831,8 +867,10 @@ BGPC_API bgpc_session *bgpc_session_create(size_t mem_budget, int32_t max_slots,
         (void)hipGetLastError();
         for (auto st : S->streams) (void)hipStreamDestroy(st);
         for (auto st : S->dev_streams) (void)hipStreamDestroy(st);
-        if (S->kstream) (void)hipStreamDestroy(S->kstream);
-        if (S->kdone) (void)hipEventDestroy(S->kdone);
+        for (int k = 0; k < bgpc_session::KSTREAMS; k++) {
+            if (S->kstream[k]) (void)hipStreamDestroy(S->kstream[k]);
+            if (S->kdone[k]) (void)hipEventDestroy(S->kdone[k]);
+        }
         if (S->ring) (void)hipHostFree(S->ring);
         if (S->head) (void)hipFree(S->head);
         if (S->dpool) (void)hipFree(S->dpool);
@@ -907,7 +945,7 @@ BGPC_API void bgpc_session_destroy(bgpc_session *S)
     if (S->worker.joinable()) S->worker.join();
     // every request is done: the serving kernel's workgroups leave
     __atomic_store_n(&S->ring->stop, 1, __ATOMIC_RELEASE);
-    (void)hipStreamSynchronize(S->kstream);
+    for (int k = 0; k < bgpc_session::KSTREAMS; k++) (void)hipStreamSynchronize(S->kstream[k]);
     {
         std::lock_guard<std::mutex> lk(S->mu);
         S->dev_stop = true;
@@ -923,8 +961,10 @@ BGPC_API void bgpc_session_destroy(bgpc_session *S)
         (void)hipStreamSynchronize(st);
         (void)hipStreamDestroy(st);
     }
-    (void)hipStreamDestroy(S->kstream);
-    (void)hipEventDestroy(S->kdone);
+    for (int k = 0; k < bgpc_session::KSTREAMS; k++) {
+        (void)hipStreamDestroy(S->kstream[k]);
+        (void)hipEventDestroy(S->kdone[k]);
+    }
     for (auto e : S->events) (void)hipEventDestroy(e);
     (void)hipHostFree(S->ring);
     (void)hipFree(S->head);

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
+#include <rocprim/device/device_select.hpp>
 #include <rocprim/device/device_segmented_radix_sort.hpp>
 
 #include <algorithm>
@@ -16,7 +17,9 @@
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <thread>
 #include <vector>
 
@@ -92,10 +95,17 @@ struct Arena {
     size_t used = 0, cap = 0;
     hipStream_t s = nullptr;
     bool async = true;
+    char *ext = nullptr;      // caller-provided memory (the allocation-free entry point)
+    size_t ext_cap = 0;
     int reserve(size_t bytes, hipStream_t stream)
     {
         s = stream;
         cap = bytes;
+        if (ext) {
+            if (bytes > ext_cap) return BGPC_E_UNSUPPORTED;
+            base = ext;
+            return BGPC_OK;
+        }
         hipError_t e = hipMallocAsync((void **)&base, bytes, stream);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -120,6 +130,10 @@ struct Arena {
     void release()
     {
         if (!base) return;
+        if (ext) {
+            base = nullptr;
+            return;
+        }
         if (async) hipFreeAsync(base, s);
         else {
             hipStreamSynchronize(s);
@@ -135,6 +149,7 @@ size_t aligned(size_t count, size_t elem) { return (count * elem + 255) & ~(size
 struct HostProgress {
     volatile int *h = nullptr;
     int *d = nullptr;
+    explicit HostProgress(std::nullptr_t) {}   // none: rounds are checked with plain copies
     HostProgress()
     {
         void *p = nullptr;
@@ -177,6 +192,8 @@ struct RunArgs {
     const bgpc_opts *o;
     int *st;
     hipStream_t s;
+    char *ext = nullptr;   // non-null: the workspace lives here and nothing is allocated
+    size_t ext_cap = 0;
 };
 
 // workgroups of k_vcolor_ff resident per compute unit (occupancy query, once)
@@ -193,6 +210,38 @@ int resident_per_cu()
         cached.store(v, std::memory_order_relaxed);
     }
     return v;
+}
+
+// Choices cached by bgpc_autotune, keyed by the shape of the graph and the
+// class of the schedule.
+struct TuneKey {
+    int d2, cls, la, lb, ld;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(d2, cls, la, lb, ld) < std::tie(o.d2, o.cls, o.la, o.lb, o.ld);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, bgpc_tuning> g_tune_cache;
+
+int ilog2l(long v) { int r = 0; while (v > 1) { v >>= 1; r++; } return r; }
+
+TuneKey tune_key(const Graph &g, long nnz, bool d2, const bgpc_opts &o)
+{
+    // schedule class: first-fit vertex rounds, first-fit with net rounds, a balancing policy
+    const int cls = o.policy != BGPC_FIRST_FIT ? 2 : (o.net_color_mask ? 1 : 0);
+    return TuneKey{d2 ? 1 : 0, cls, ilog2l(g.n_a), ilog2l(g.n_b), ilog2l(g.n_a ? nnz / g.n_a : 0)};
+}
+
+bgpc_tuning tune_default() { return bgpc_tuning{-1, -1, -1, 0, 0, 0}; }
+
+// the choices for this call: the caller's, else the cached ones, else the rules
+bgpc_tuning tune_for(const Graph &g, long nnz, bool d2, const bgpc_opts &o)
+{
+    if (o.tuning) return *o.tuning;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(tune_key(g, nnz, d2, o));
+    return it == g_tune_cache.end() ? tune_default() : it->second;
 }
 
 template <bool D2>
@@ -222,6 +271,21 @@ int run(const RunArgs &a)
     for (int r = 0; r < max_rounds && start_round + r < 64; r++)
         if (start_round + r >= 0 && ((o.net_color_mask >> (start_round + r)) & 1ull)) any_net_round = true;
     const size_t sp_words = (size_t)((a.nnz + (D2 ? n_b : 0)) / 64 + 4);
+    // front-driven first-fit rounds (see k_front_apply) may run: their lists
+    // (two front lists, winner candidates, stamps, front flags)
+    const bgpc_tuning tune = tune_for(g, a.nnz, D2, o);
+    // standing proposals pay where a coloring front sweeps many nets round
+    // after round (on 2^21 stencil nets: 12% per call); on graphs of 10^4-10^5
+    // nets the bookkeeping costs about as much as it saves
+    const bool sp_on = !(o.flags & BGPC_INCREMENTAL) && o.net_conflict_mask == ~0ull &&
+                       (tune.standing == 1 || (tune.standing < 0 && n_b >= (1 << 20)));
+    // front-driven rounds do less work per round but append to shared lists,
+    // and same-address atomics serialize: on the 128^3 stencil they measured
+    // 82 ms per call against 24 ms for the worklist rounds, so they run only
+    // when chosen (bgpc_tuning.front = 1)
+    const bool front_possible = policy == BGPC_FIRST_FIT && !resume && !(o.flags & BGPC_INCREMENTAL) &&
+                                !any_net_round && sp_on && tune.front == 1;
+    const long fr_a = front_possible ? n_a : 0, fr_b = front_possible ? n_b : 0;
     const long n_huge_cap = std::min<long>(n_b, (a.nnz + (D2 ? n_b : 0)) / (HASH_MAX + 1) + 1) + 1;
     const bool inc_flag = (o.flags & BGPC_INCREMENTAL) != 0;
     const long inc_a = inc_flag ? n_a : 0, inc_b = inc_flag ? n_b : 0;   // incremental lists and bit sets
@@ -244,8 +308,13 @@ int run(const RunArgs &a)
                    + aligned(inc_b / 32 + 2, 4) * 2   // net bit sets
                    + aligned(sp_words, 8)             // standing proposals: verdict bits
                    + aligned(n_a + 1, 4)              //   loss counts
-                   + aligned(n_b + 1, 1);             //   dirty nets
+                   + aligned(n_b + 1, 1)              //   dirty nets
+                   + aligned(fr_a + 1, 4) * 3         // front lists, front flags
+                   + aligned(fr_b + 1, 4) * 4;        //   dirty-net list, its stamps, two zero-net lists
+    const bool noalloc = a.ext != nullptr;
     Arena ar;
+    ar.ext = a.ext;
+    ar.ext_cap = a.ext_cap;
     int rc = ar.reserve(bytes, s);
     if (rc != BGPC_OK) return rc;
     int *W0 = ar.take<int>(n_a + 1);
@@ -284,6 +353,11 @@ int run(const RunArgs &a)
     unsigned long long *sp_bits = ar.take<unsigned long long>(sp_words);
     int *sp_cnt = ar.take<int>(n_a + 1);
     uint8_t *sp_dirty = ar.take<uint8_t>(n_b + 1);
+    int *FL[2] = {ar.take<int>(fr_a + 1), ar.take<int>(fr_a + 1)};
+    int *infront = ar.take<int>(fr_a + 1);
+    int *DL = ar.take<int>(fr_b + 1);
+    int *dstamp = ar.take<int>(fr_b + 1);
+    int *ZL[2] = {ar.take<int>(fr_b + 1), ar.take<int>(fr_b + 1)};
     int *Wb[2] = {W0, W1};
 
     int st_code = BGPC_OK;
@@ -306,7 +380,7 @@ int run(const RunArgs &a)
     int hv_H = 0, hv_stride = 0;
     long mc_ub = -1;   // upper bound of every color present before the next round
     // (decided from the graph's shape below)
-    bool planes_ok = !(o.flags & BGPC_INCREMENTAL);
+    bool planes_ok = !(o.flags & BGPC_INCREMENTAL) && !noalloc;   // the words are allocated as colors grow
     long max_PH = 0;
     {
         size_t fr = 0, tot = 0;
@@ -314,12 +388,8 @@ int run(const RunArgs &a)
         else (void)hipGetLastError();
         max_PH = std::min<long>(max_PH, (long)n_a / 64 + 2);
     }
-    // standing proposals in vertex-based rounds (not with the opt-in
-    // incremental rounds); their state is reset after every net-based round.
-    // They pay where a coloring front sweeps many nets round after round (on
-    // 2^21 stencil nets: 12% per call); on graphs of 10^4-10^5 nets the
-    // bookkeeping costs about as much as it saves, so smaller graphs go without
-    const bool sp_on = !(o.flags & BGPC_INCREMENTAL) && n_b >= (1 << 20) && o.net_conflict_mask == ~0ull;
+    // standing proposals (sp_on, above) in vertex-based rounds; their state
+    // is reset after every net-based round
     // removal form of round r: the vertex form (Algorithm 5) where its bit is
     // clear and it is exact -- a vertex-based round, or a net-based first
     // round that starts with nothing colored -- else the net form
@@ -356,11 +426,14 @@ int run(const RunArgs &a)
     };
     // pinned counters live for the thread's lifetime (never freed: freeing at
     // thread exit could run after the HIP runtime has shut down)
-    if (!t_prog) t_prog = new HostProgress();
-    HostProgress *prog_p = t_prog;
+    // (none without allocation: rounds are then checked by plain copies)
+    HostProgress no_prog(nullptr);
+    EventPool no_events;
+    if (!noalloc && !t_prog) t_prog = new HostProgress();
+    HostProgress *prog_p = noalloc ? &no_prog : t_prog;
     HostProgress &prog = *prog_p;
-    if (!t_evpool) t_evpool = new EventPool();
-    EventPool *evpool_p = t_evpool;
+    if (!noalloc && !t_evpool) t_evpool = new EventPool();
+    EventPool *evpool_p = noalloc ? &no_events : t_evpool;
     EventPool &evpool = *evpool_p;
     evpool.used = 0;
     const int prof_kernel = o.prof ? o.prof->kernel : -1;
@@ -440,6 +513,10 @@ int run(const RunArgs &a)
         const int max_net = h_shape[0];
         const int n_big = h_shape[1];
         const int n_huge = h_shape[3];
+        // front-driven rounds need every net on the small-net removal path
+        // (its candidate listing) and standing proposals
+        const bool front = front_possible && n_big == 0 && n_huge == 0 && max_net <= SMALL_NET &&
+                           !(o.flags & BGPC_NET_BALANCE);
         // distance-2 degree bound: most nets of a vertex x largest net
         const long two_hop = std::min<long>((long)h_shape[2] * (long)max_net, 1L << 30);
         unsigned long long walk;
@@ -447,7 +524,7 @@ int run(const RunArgs &a)
         // small dense graphs under plain first-fit vertex rounds: one workgroup
         // with an explicit conflict bit matrix (the batch kernel's dense mode)
         if (!D2 && !any_net_round && policy == BGPC_FIRST_FIT && !resume && !(o.flags & BGPC_INCREMENTAL) &&
-            !o.prof && n_a <= DENSE_ROUTE_N && (double)walk > 4.0 * (double)n_a * (double)n_a) {
+            !o.prof && !noalloc && n_a <= DENSE_ROUTE_N && (double)walk > 4.0 * (double)n_a * (double)n_a) {
             std::vector<int> lg;
             int rounds = 0;
             const int lcap = o.log ? std::min(o.log->cap, max_rounds) : 0;
@@ -478,7 +555,8 @@ int run(const RunArgs &a)
         // per-net color words past 63 where the distance-2 walk is costly
         // (nets of more than SMALL_NET members) or cannot hold every color
         // (bound past the LDS bitmap); elsewhere the walk is cheaper
-        planes_ok = planes_ok && (n_big > 0 || need_bits > lds_bits);
+        planes_ok = planes_ok && (tune.planes == 1 || (tune.planes < 0 && (n_big > 0 || need_bits > lds_bits)) ||
+                                  need_bits > lds_bits);
         const int wide_bytes = lds_bits / 8;
         // net-based rounds: bitmap + suffix counts of the largest net
         const int ncolor_words = std::min(lds_budget / 4, 2 * ((max_net + 31) / 32) + 2);
@@ -536,10 +614,18 @@ int run(const RunArgs &a)
         k_fill_u8<<<g_b, nthr, 0, s>>>(done_net, 0, n_b + 1);
         clear_inc_bits();
         if (!resume) {
-            k_fill_i32<<<g_a, nthr, 0, s>>>(st, -1, n_a);
+            // front-driven rounds start every vertex on its standing proposal 0
+            // (first-fit with nothing colored)
+            k_fill_i32<<<g_a, nthr, 0, s>>>(st, front ? TENT : -1, n_a);
+            if (front) {
+                k_fill_i32<<<g_a, nthr, 0, s>>>(infront, 0, n_a + 1);
+                k_fill_i32<<<g_b, nthr, 0, s>>>(dstamp, 0, n_b + 1);
+                k_iota<<<g_b, nthr, 0, s>>>(DL, n_b);   // the first round rescans every net
+            }
             k_iota<<<g_a, nthr, 0, s>>>(W0, n_a);
             k_fill_u64<<<g_b, nthr, 0, s>>>(mask0, 0ull, n_b + 1);
             k_init_ctrl<<<1, 64, 0, s>>>(ctrl, n_a, -1);
+            if (front) k_fill_i32<<<1, 64, 0, s>>>(&ctrl->dl_n, n_b, 1);
         } else {
             k_init_ctrl<<<1, 64, 0, s>>>(ctrl, 0, -1);
             k_check_colors<<<g_a, nthr, 0, s>>>(st, n_a, 1 << 29, &ctrl->error);
@@ -564,7 +650,7 @@ int run(const RunArgs &a)
                 if (planes_ok) ensure_planes(mc_ub + 1);
             }
             k_mask_rebuild<D2><<<g_b, nthr, 0, s>>>(g, st, mask0, hw, PH);
-            const int gt = grid_for(max_tiles, 1, di.cus * 4);
+            const int gt = grid_for(max_tiles, 1, di.cus * (tune.apply_grid > 0 ? tune.apply_grid : 4));
             k_count_uncolored<<<gt, TILE_BLOCK, 0, s>>>(st, n_a, tile_count);
             // identity compaction: the uncolored vertices in id order become W0
             k_compact<<<gt, TILE_BLOCK, 0, s>>>(nullptr, n_a, ctrl, 1, st, tile_count, W0, rec, 0, 0, 0, nullptr);
@@ -579,7 +665,7 @@ int run(const RunArgs &a)
         }
 
         // ---- rounds
-        const int gt = grid_for(max_tiles, 1, di.cus * 4);
+        const int gt = grid_for(max_tiles, 1, di.cus * (tune.apply_grid > 0 ? tune.apply_grid : 4));
         const int g_big = std::max(1, std::min(n_big, di.cus * 4));
         const int g_chunk = grid_for((n_a + chunk - 1) / chunk, 1, di.cus * 16);
         // first-fit vertex rounds after the last net-based round run
@@ -605,8 +691,12 @@ int run(const RunArgs &a)
         // first-fit: one resident pass of workgroups (the LDS staging buffer
         // limits residency; a second partial pass of workgroups costs more than
         // the longer per-wave loop)
-        const int g_w64a = std::min(grid64(n_a), std::max(8, di.cus * resident_per_cu<D2>() / 8 * 8));
-        const int g_w64b = grid64(n_b);
+        const int g_w64a = std::min(grid64(n_a), std::max(8, di.cus * (tune.color_grid > 0 ? tune.color_grid
+                                                                                  : resident_per_cu<D2>()) / 8 * 8));
+        const int g_w64b = tune.removal_grid > 0 ? std::min(grid64(n_b), std::max(8, di.cus * tune.removal_grid / 8 * 8))
+                                                 : grid64(n_b);
+        const int g_list = di.cus * (tune.removal_grid > 0 ? tune.removal_grid : 8);
+        const int g_fa = grid_for(((long)n_a + 3) / 4, APPLY_BLOCK, di.cus * (tune.apply_grid > 0 ? tune.apply_grid : 8));
         // balanced net rounds: a wave per chunk of net ids, an LDS bitmap of
         // 16 bits per member of the largest net (at least 16 KB), within the budget
         const int bal_bytes = (int)std::min<long>(lds_budget, std::max<long>(16384, (16L * max_net + 64) / 8 + 64) / 4 * 4);
@@ -769,7 +859,20 @@ int run(const RunArgs &a)
             } else {
                 uint8_t *dty = spr ? sp_dirty : nullptr;
                 const SPState &spx = spr ? sp_state : sp_none;
-                if (policy == BGPC_FIRST_FIT) {
+                if (front) {
+                    const DirtyList dlr{DL, &ctrl->dl_n, dstamp, r};
+                    LAUNCH_PROF(BGPC_PROF_COLOR, (k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, FL[par], ctrl, par, st, mask0, heavy, PCNT(r), hw, PH, ffc, dty, &ctrl->fl_n[par], FL[par ^ 1], &ctrl->fl_n[par ^ 1], dlr)));
+                    bool need_wide = true;
+                    if (use_prog) {
+                        int seen = prog.h[0], mc = prog.h[3];
+                        if (seen >= 0) need_wide = (long)mc + (r - 1 - seen) >= 63;
+                        else need_wide = r >= 63;
+                    }
+                    if (need_wide)
+                        k_vcolor_wide<D2><<<di.cus * 2, 256, wide_bytes, s>>>(g, heavy, ctrl, st, lds_bits, nullptr,
+                                                                               nullptr, nullptr, nullptr, nullptr,
+                                                                               hw, PH, ffc, dty, dlr);
+                } else if (policy == BGPC_FIRST_FIT) {
                     LAUNCH_PROF(BGPC_PROF_COLOR, (k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy, PCNT(r), hw, PH, ffc, dty)));
                     // the wide path can only be needed once colors 0..63 all exist:
                     // a vertex-based first-fit round raises the largest color by at
@@ -823,7 +926,10 @@ int run(const RunArgs &a)
                 if (vertex_form(r, false)) {
                     k_conflict_vertex<D2><<<g_a, nthr, 0, s>>>(g, Wc, ctrl, par, st, lose);
                 } else {
-                    LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), spx)));
+                    if (front)
+                        LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_list<D2><<<g_list, LIST_BLOCK, 0, s>>>(g, st, done_net, sp_state, DL, &ctrl->dl_n, PCNT(r))));
+                    else
+                        LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), spx)));
                     if (spr && prof_kernel == BGPC_PROF_CONFLICT && PCNT(r))
                         k_census<D2><<<g_b, nthr, 0, s>>>(g, st, PCNT(r));
                     if (n_big)
@@ -833,9 +939,19 @@ int run(const RunArgs &a)
                         k_conflict_huge<D2><<<g_huge, HUGE_BLOCK, huge_bytes, s>>>(g, st, lose, done_net, huge, &shape[3],
                                                                                  ctrl, 1, spx, huge_list);
                 }
-                k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1, hw, PH,
-                                                      spr ? sp_cnt : nullptr);
-                k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 0, 1, host);
+                if (front) {
+                    // winners (all vertices streamed); closes the round; then
+                    // the members of nets that gained color 0 join the front
+                    k_front_apply<D2><<<g_fa, APPLY_BLOCK, 0, s>>>(g, sp_cnt, st, mask0, hw, PH, ZL[par],
+                                                                  &ctrl->zl_n[par], ctrl, par, rec, rr, host,
+                                                                  &ctrl->dl_n, &ctrl->fl_n[par], &ctrl->zl_n[par ^ 1]);
+                    k_front_push<D2><<<di.cus * 8, 256, 0, s>>>(g, ZL[par], &ctrl->zl_n[par], st, infront,
+                                                                 FL[par ^ 1], &ctrl->fl_n[par ^ 1]);
+                } else {
+                    k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1, hw,
+                                                          PH, spr ? sp_cnt : nullptr);
+                    k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 0, 1, host);
+                }
             }
             LAUNCH_CHECK();
             mark_round();
@@ -948,10 +1064,11 @@ finish:
     return st_code;
 }
 
-int validate_bipartite(const bgpc_csr *A, const bgpc_csr *B, hipStream_t s)
+// d_err_ext: a device int to use instead of allocating one
+int validate_bipartite(const bgpc_csr *A, const bgpc_csr *B, hipStream_t s, int *d_err_ext = nullptr)
 {
-    int *d_err = nullptr;
-    HIP_TRY(hipMallocAsync((void **)&d_err, 256, s));
+    int *d_err = d_err_ext;
+    if (!d_err) HIP_TRY(hipMallocAsync((void **)&d_err, 256, s));
     const DevInfo di = dev_info();
     k_fill_i32<<<1, 64, 0, s>>>(d_err, 0, 1);
     k_check_sorted<<<grid_for(A->n_rows, 256, di.cus * 8), 256, 0, s>>>(A->offsets, A->indices, A->n_rows, A->n_cols,
@@ -971,7 +1088,7 @@ int validate_bipartite(const bgpc_csr *A, const bgpc_csr *B, hipStream_t s)
         HIP_TRY(hipStreamSynchronize(s));
         if (ends[0] != A->nnz || ends[1] != B->nnz) h_err |= 1;
     }
-    hipFreeAsync(d_err, s);
+    if (!d_err_ext) hipFreeAsync(d_err, s);
     hipStreamSynchronize(s);
     if (h_err & 1) return BGPC_E_INVALID;
     if (h_err & 2) return BGPC_E_UNSORTED;
@@ -1090,6 +1207,79 @@ __global__ void k_order_key(Graph g, unsigned long long *key, int *ids)
             key[u] = s;
             ids[u] = u;
         }
+    }
+}
+
+// ---- smallest-last orders, removed in steps: key(x) = sum over the nets v
+// of x of (members of v still present - 1) = base(x) - sum over those nets of
+// removed(v); every step removes all present vertices whose key is at most
+// d + (d >> shift), d the smallest key, and adds one to removed(v) for each
+// net of each removed vertex.  Keys are recomputed from removed() every step
+// (work proportional to the memberships still present, whatever the net
+// sizes).
+
+// keys of the present vertices R[0..n) and their minimum (atomicMin into *dmin)
+template <bool D2>
+__global__ void k_sl_keys(Graph g, const int *R, const int *n_p, const unsigned long long *base, const int *removed,
+                          unsigned long long *key, unsigned long long *dmin)
+{
+    const int n = *n_p;
+    unsigned long long m = ~0ull;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int x = R[i];
+        const int nn = Acc<D2>::nets_count(g, x);
+        unsigned long long r = 0;
+        for (int k = 0; k < nn; k++) r += (unsigned long long)removed[Acc<D2>::net_at(g, x, k)];
+        const unsigned long long kx = base[x] - r;
+        key[x] = kx;
+        m = kx < m ? kx : m;
+    }
+    for (int d = WAVE / 2; d > 0; d >>= 1) {
+        const unsigned long long o = (unsigned long long)__shfl_xor((long long)m, d);
+        m = o < m ? o : m;
+    }
+    if (lane_id() == 0 && m != ~0ull) atomicMin(dmin, m);
+}
+
+// flags of the step: present vertices at or below the threshold leave
+__global__ void k_sl_flags(const int *R, const int *n_p, const unsigned long long *key, const unsigned long long *dmin,
+                           int shift, uint8_t *take, uint8_t *keep)
+{
+    const int n = *n_p;
+    const unsigned long long d = *dmin;
+    const unsigned long long thr = shift >= 63 ? d : d + (d >> shift);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const bool t = key[R[i]] <= thr;
+        take[i] = t;
+        keep[i] = !t;
+    }
+}
+
+// removed(v) += 1 for every net of every vertex removed in this step
+template <bool D2>
+__global__ void k_sl_remove(Graph g, const int *B, const int *nb_p, int *removed)
+{
+    const int n = *nb_p;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int u = B[i];
+        const int nn = Acc<D2>::nets_count(g, u);
+        for (int k = 0; k < nn; k++) atomicAdd(&removed[Acc<D2>::net_at(g, u, k)], 1);
+    }
+}
+
+// rank of removal position i: steps in reverse, a step's vertices in
+// ascending id; step_end[s] = vertices removed after step s
+__global__ void k_sl_ranks(const int *seq, int n, const int *step_end, int steps, int *order)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int lo = 0, hi = steps - 1;   // first step with step_end > i
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (step_end[mid] > i) hi = mid;
+            else lo = mid + 1;
+        }
+        const int beg = lo ? step_end[lo - 1] : 0;
+        order[(n - step_end[lo]) + (i - beg)] = seq[i];
     }
 }
 
@@ -1224,6 +1414,91 @@ int order_largest_first(const Graph &g, bool d2, hipStream_t s, int32_t *order_o
     return ok ? BGPC_OK : BGPC_E_HIP;
 }
 
+// Smallest-last order by steps (see k_sl_keys).  steps_out: optional, host.
+int order_smallest_last(const Graph &g, bool d2, int shift, hipStream_t s, int32_t *order_out, int32_t *steps_out)
+{
+    const int n = g.n_a;
+    if (steps_out) *steps_out = 0;
+    if (n == 0) return BGPC_OK;
+    const DevInfo di = dev_info();
+    size_t sel_bytes = 0;
+    if (rocprim::select(nullptr, sel_bytes, (const int *)nullptr, (const uint8_t *)nullptr, (int *)nullptr,
+                        (int *)nullptr, (size_t)n, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return BGPC_E_HIP;
+    }
+    Arena ar;
+    const size_t bytes = aligned(n, 8) * 2 + aligned(n, 4) * 4 + aligned(g.n_b + 1, 4) + aligned(n, 1) * 2 +
+                         aligned(16, 8) + aligned(sel_bytes, 1);
+    int rc = ar.reserve(bytes, s);
+    if (rc != BGPC_OK) return rc;
+    unsigned long long *base = ar.take<unsigned long long>(n);
+    unsigned long long *key = ar.take<unsigned long long>(n);
+    int *R[2] = {ar.take<int>(n), ar.take<int>(n)};
+    int *seq = ar.take<int>(n);
+    int *ids = ar.take<int>(n);
+    int *removed = ar.take<int>(g.n_b + 1);
+    uint8_t *take = ar.take<uint8_t>(n);
+    uint8_t *keep = ar.take<uint8_t>(n);
+    unsigned long long *ctl = ar.take<unsigned long long>(16);   // [0] min key; ints from [1]: counts
+    int *cnt = (int *)(ctl + 1);                                 // cnt[0] present, cnt[1] taken, cnt[2] kept
+    void *tmp = ar.take<char>(sel_bytes);
+    const int nthr = 256;
+    const int blocks_w = grid_for((long)n * WAVE, 256, di.cus * 16);
+    const int ga = grid_for(n, nthr, di.cus * 8);
+    bool ok = true;
+    if (d2) k_order_key<true><<<blocks_w, 256, 0, s>>>(g, base, ids);
+    else k_order_key<false><<<blocks_w, 256, 0, s>>>(g, base, ids);
+    k_iota<<<ga, nthr, 0, s>>>(R[0], n);
+    k_fill_i32<<<grid_for(g.n_b + 1, nthr, di.cus * 8), nthr, 0, s>>>(removed, 0, g.n_b + 1);
+    ok = hipMemcpyAsync(cnt, &n, sizeof(int), hipMemcpyHostToDevice, s) == hipSuccess;
+    std::vector<int> step_end;
+    int present = n, removed_total = 0, cur = 0;
+    while (ok && present > 0) {
+        k_fill_u64<<<1, 64, 0, s>>>((uint64_t *)ctl, ~0ull, 1);
+        if (d2) k_sl_keys<true><<<ga, nthr, 0, s>>>(g, R[cur], cnt, base, removed, key, ctl);
+        else k_sl_keys<false><<<ga, nthr, 0, s>>>(g, R[cur], cnt, base, removed, key, ctl);
+        k_sl_flags<<<ga, nthr, 0, s>>>(R[cur], cnt, key, ctl, shift, take, keep);
+        ok = hipGetLastError() == hipSuccess &&
+             rocprim::select(tmp, sel_bytes, (const int *)R[cur], (const uint8_t *)take, seq + removed_total,
+                             cnt + 1, (size_t)present, s) == hipSuccess &&
+             rocprim::select(tmp, sel_bytes, (const int *)R[cur], (const uint8_t *)keep, R[cur ^ 1], cnt + 2,
+                             (size_t)present, s) == hipSuccess;
+        if (!ok) break;
+        if (d2) k_sl_remove<true><<<ga, nthr, 0, s>>>(g, seq + removed_total, cnt + 1, removed);
+        else k_sl_remove<false><<<ga, nthr, 0, s>>>(g, seq + removed_total, cnt + 1, removed);
+        int h[3] = {0, 0, 0};
+        ok = hipMemcpyAsync(cnt, cnt + 2, sizeof(int), hipMemcpyDeviceToDevice, s) == hipSuccess &&
+             hipMemcpyAsync(h, cnt, 3 * sizeof(int), hipMemcpyDeviceToHost, s) == hipSuccess &&
+             hipStreamSynchronize(s) == hipSuccess;
+        if (!ok || h[1] <= 0) {   // a step always removes the vertices at the minimum
+            ok = false;
+            break;
+        }
+        removed_total += h[1];
+        present = h[2];
+        step_end.push_back(removed_total);
+        cur ^= 1;
+    }
+    int *d_steps = nullptr;
+    if (ok) {
+        // the step boundaries go where the keys were (no longer needed)
+        d_steps = (int *)key;
+        ok = (size_t)step_end.size() <= (size_t)n * 2 &&
+             hipMemcpyAsync(d_steps, step_end.data(), sizeof(int) * step_end.size(), hipMemcpyHostToDevice, s) ==
+                 hipSuccess;
+    }
+    if (ok) {
+        k_sl_ranks<<<ga, nthr, 0, s>>>(seq, n, d_steps, (int)step_end.size(), order_out);
+        ok = hipGetLastError() == hipSuccess;
+    }
+    if (!ok) (void)hipGetLastError();
+    ar.release();
+    if (hipStreamSynchronize(s) != hipSuccess) ok = false;
+    if (ok && steps_out) *steps_out = (int32_t)step_end.size();
+    return ok ? BGPC_OK : BGPC_E_HIP;
+}
+
 }  // namespace bgpc
 
 namespace bgpc {
@@ -1245,6 +1520,116 @@ void release_thread_state()
 }  // namespace bgpc
 
 extern "C" {
+
+// ---- autotuner (see bgpc.h)
+extern "C" BGPC_API int bgpc_autotune(const bgpc_csr *csr_A, const bgpc_csr *csr_B, const bgpc_opts *opts,
+                                      int32_t trials, bgpc_tuning *best, double *ms_default, double *ms_best)
+{
+    bgpc_opts o;
+    if (opts) o = *opts;
+    else bgpc_opts_default(&o);
+    const bool d2 = csr_B == nullptr;
+    if (!csr_ok(csr_A) || !opts_ok(o) || !best || trials < 1 || (o.flags & BGPC_RESUME)) return BGPC_E_INVALID;
+    if (d2 ? csr_A->n_rows != csr_A->n_cols
+           : (!csr_ok(csr_B) || csr_A->n_rows != csr_B->n_cols || csr_A->n_cols != csr_B->n_rows ||
+              csr_A->nnz != csr_B->nnz))
+        return BGPC_E_INVALID;
+    hipStream_t s = (hipStream_t)o.stream;
+    o.log = nullptr;
+    o.prof = nullptr;
+    o.flags &= ~(uint32_t)BGPC_STRICT;
+    int32_t rounds = 0;
+    o.rounds_out = &rounds;
+    const int n = csr_A->n_rows;
+    RunArgs a;
+    a.g = d2 ? Graph{n, n, csr_A->offsets, csr_A->indices, csr_A->offsets, csr_A->indices}
+             : Graph{csr_A->n_rows, csr_B->n_rows, csr_A->offsets, csr_A->indices, csr_B->offsets, csr_B->indices};
+    a.nnz = csr_A->nnz;
+    a.d2 = d2;
+    a.o = &o;
+    a.s = s;
+    int32_t *colors = nullptr;
+    if (hipMallocAsync((void **)&colors, sizeof(int32_t) * ((size_t)n + 1), s) != hipSuccess) {
+        (void)hipGetLastError();
+        return BGPC_E_OOM;
+    }
+    a.st = colors;
+    std::vector<int32_t> ref(n), got(n);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = BGPC_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = BGPC_E_HIP;
+    // one configuration: the fastest of `trials` calls, its colors and rounds
+    auto measure = [&](const bgpc_tuning &t, std::vector<int32_t> &out, int32_t *r_out, double *ms) -> int {
+        o.tuning = &t;
+        double bestms = 1e30;
+        for (int k = 0; k < trials; k++) {
+            if (hipEventRecord(e0, s) != hipSuccess) return BGPC_E_HIP;
+            int st = d2 ? run<true>(a) : run<false>(a);
+            if (st != BGPC_OK && st != BGPC_E_NOT_CONVERGED) return st;
+            float t_ms = 0.f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&t_ms, e0, e1) != hipSuccess)
+                return BGPC_E_HIP;
+            bestms = std::min(bestms, (double)t_ms);
+        }
+        *r_out = rounds;
+        *ms = bestms;
+        if (n && (hipMemcpyAsync(out.data(), colors, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                  hipStreamSynchronize(s) != hipSuccess))
+            return BGPC_E_HIP;
+        return BGPC_OK;
+    };
+    bgpc_tuning cur = tune_default();
+    double cur_ms = 0.0, base_ms = 0.0;
+    int32_t ref_rounds = 0;
+    if (rc == BGPC_OK) rc = measure(cur, ref, &ref_rounds, &cur_ms);
+    base_ms = cur_ms;
+    // candidates per field, tried one field at a time
+    struct Field {
+        int32_t bgpc_tuning::*f;
+        std::vector<int32_t> values;
+    };
+    const std::vector<Field> fields = {{&bgpc_tuning::front, {0, 1}},
+                                       {&bgpc_tuning::standing, {0, 1}},
+                                       {&bgpc_tuning::planes, {0, 1}},
+                                       {&bgpc_tuning::color_grid, {8, 16, 32, 64}},
+                                       {&bgpc_tuning::removal_grid, {2, 4, 16, 32}},
+                                       {&bgpc_tuning::apply_grid, {2, 8, 16}}};
+    for (const Field &fd : fields) {
+        for (int32_t v : fd.values) {
+            if (rc != BGPC_OK) break;
+            bgpc_tuning cand = cur;
+            cand.*(fd.f) = v;
+            double ms = 0.0;
+            int32_t r2 = 0;
+            rc = measure(cand, got, &r2, &ms);
+            if (rc != BGPC_OK) break;
+            if (r2 != ref_rounds || got != ref) {   // a choice that changes a result is a library fault
+                rc = BGPC_E_INTERNAL;
+                break;
+            }
+            if (ms < cur_ms) {
+                cur = cand;
+                cur_ms = ms;
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFreeAsync(colors, s);
+    (void)hipStreamSynchronize(s);
+    if (rc != BGPC_OK) return rc;
+    *best = cur;
+    if (ms_default) *ms_default = base_ms;
+    if (ms_best) *ms_best = cur_ms;
+    {
+        bgpc_opts ko = o;
+        ko.tuning = nullptr;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[tune_key(a.g, a.nnz, d2, ko)] = cur;
+    }
+    return BGPC_OK;
+}
 
 BGPC_API void bgpc_opts_default(bgpc_opts *o)
 {
@@ -1316,6 +1701,25 @@ BGPC_API int d2gc_order_largest_first(const bgpc_csr *adj, void *stream, int32_t
     if (!csr_ok(adj) || adj->n_rows != adj->n_cols || (adj->n_rows > 0 && !order_out)) return BGPC_E_INVALID;
     const Graph g{adj->n_rows, adj->n_rows, adj->offsets, adj->indices, adj->offsets, adj->indices};
     return order_largest_first(g, true, (hipStream_t)stream, order_out);
+}
+
+BGPC_API int bgpc_order_smallest_last(const bgpc_csr *csr_A, const bgpc_csr *csr_B, int32_t slack_shift, void *stream,
+                                      int32_t *order_out, int32_t *steps_out)
+{
+    if (!csr_ok(csr_A) || !csr_ok(csr_B) || csr_A->n_rows != csr_B->n_cols || csr_A->n_cols != csr_B->n_rows ||
+        csr_A->nnz != csr_B->nnz || (csr_A->n_rows > 0 && !order_out) || slack_shift < 0)
+        return BGPC_E_INVALID;
+    Graph g{csr_A->n_rows, csr_B->n_rows, csr_A->offsets, csr_A->indices, csr_B->offsets, csr_B->indices};
+    return order_smallest_last(g, false, slack_shift, (hipStream_t)stream, order_out, steps_out);
+}
+
+BGPC_API int d2gc_order_smallest_last(const bgpc_csr *adj, int32_t slack_shift, void *stream, int32_t *order_out,
+                                      int32_t *steps_out)
+{
+    if (!csr_ok(adj) || adj->n_rows != adj->n_cols || (adj->n_rows > 0 && !order_out) || slack_shift < 0)
+        return BGPC_E_INVALID;
+    Graph g{adj->n_rows, adj->n_rows, adj->offsets, adj->indices, adj->offsets, adj->indices};
+    return order_smallest_last(g, true, slack_shift, (hipStream_t)stream, order_out, steps_out);
 }
 
 BGPC_API int color_stats(const int32_t *colors, int64_t n, void *stream, bgpc_stats *out)

@@ -69,6 +69,13 @@ struct Ctrl {
     int rounds;          // rounds that started with a non-empty worklist
     int error;           // device-side invariant violations (bit set)
     int pad[2];
+    // front-driven first-fit rounds
+    int fl_n[2];         // front list lengths, double-buffered by round parity
+    int zl_n[2];         // nets that gained color 0, double-buffered by round parity
+    int win;             // winners of the round so far
+    unsigned done_blocks;   // blocks of the closing kernel that have finished
+    int dl_n;            // nets listed for this round's removal
+    int pad2[1];
 };
 
 // per-round record written by the compaction kernel

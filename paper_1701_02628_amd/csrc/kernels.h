@@ -125,6 +125,11 @@ __global__ void k_init_ctrl(Ctrl *c, int n_w, int max_color)
         c->error = 0;
         c->pad[0] = max_color;   // largest color present (max_final)
         c->pad[1] = 0;
+        c->fl_n[0] = c->fl_n[1] = 0;
+        c->zl_n[0] = c->zl_n[1] = 0;
+        c->dl_n = 0;
+        c->win = 0;
+        c->done_blocks = 0;
     }
 }
 
@@ -265,12 +270,38 @@ __global__ void k_grow_planes(const uint64_t *old, int PHo, uint64_t *neu, int P
     }
 }
 
+// Front-driven rounds list the nets to rescan instead of flagging them: a net
+// joins the list once per round (stamped with round + 1).
+struct DirtyList {
+    int *list;   // null: nets are flagged in the dirty bytes instead
+    int *n;
+    int *stamp;
+    int round;
+};
+
+// stamps v for this round; true for the one caller that did
+__device__ __forceinline__ bool dl_claim(const DirtyList &dl, int v)
+{
+    return __atomic_load_n(&dl.stamp[v], __ATOMIC_RELAXED) != dl.round + 1 &&
+           atomicExch(&dl.stamp[v], dl.round + 1) != dl.round + 1;
+}
+
+__device__ __forceinline__ void dl_mark(const DirtyList &dl, int v)
+{
+    if (dl_claim(dl, v)) dl.list[atomicAdd(dl.n, 1)] = v;
+}
+
 // Nets of w, marked for a new scan (standing proposals): w's proposal changed.
 template <bool D2>
-__device__ __forceinline__ void mark_nets_dirty(const Graph &g, int w, uint8_t *dirty, int first, int step)
+__device__ __forceinline__ void mark_nets_dirty(const Graph &g, int w, uint8_t *dirty, int first, int step,
+                                                const DirtyList *dl = nullptr)
 {
     const int nn = Acc<D2>::nets_count(g, w);
-    for (int k = first; k < nn; k += step) dirty[Acc<D2>::net_at(g, w, k)] = 1;
+    for (int k = first; k < nn; k += step) {
+        const int v = Acc<D2>::net_at(g, w, k);
+        if (dl && dl->list) dl_mark(*dl, v);
+        else dirty[v] = 1;
+    }
 }
 
 // Smallest color >= from (from >= 64) that no net of w holds, searched one
@@ -427,32 +458,49 @@ __device__ uint64_t wave_row_or(const int *row, int d, const uint64_t *mask0)
 // lane), then every lane ORs the masks of its own row, eight gathers in
 // flight.  The first clear bit is the first-fit color.  Entries whose 64 low
 // colors are all forbidden are queued for k_vcolor_wide.
+// Front mode (fl_out set): W is the front list (uncolored vertices whose
+// nets hold color 0, unordered, with the last round's winners still in it),
+// its length is *n_p; winners are dropped and every other entry is appended
+// to fl_out, the next round's front list.
 template <bool D2>
 __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *ctrl, int par, int *st,
                                                   const uint64_t *mask0, int *heavy, unsigned long long *prof,
-                                                  const uint64_t *hw, int PH, int *ffc, uint8_t *dirty)
+                                                  const uint64_t *hw, int PH, int *ffc, uint8_t *dirty,
+                                                  const int *n_p = nullptr, int *fl_out = nullptr,
+                                                  int *fl_out_n = nullptr,
+                                                  DirtyList dl = DirtyList{nullptr, nullptr, nullptr, 0})
 {
     unsigned long long rows = 0;
     __shared__ int s_pre[65], s_beg[64];
     __shared__ int s_idx[STAGE];
-    const int n = ctrl->n_w[par];
+    const int n = n_p ? *n_p : ctrl->n_w[par];
     const int lane = threadIdx.x, nb = gridDim.x, lb = xcd_remap(blockIdx.x, nb);
     const int stride = nb * 64;
     int local_max = -1;
     // the next 64 entries and their row offsets are loaded while the current
     // ones are colored
-    int nw_ = -1, nbeg = 0, nend = 0;
+    int nw_ = -1, nbeg = 0, nend = 0, nst = -1;
     auto fetch = [&](int bs) {
         int i = bs + lane;
         nw_ = i < n ? W[i] : -1;
         if (nw_ >= 0) {
             nbeg = g.a_off[nw_];
             nend = g.a_off[nw_ + 1];
+            if (fl_out) nst = st[nw_];
         }
     };
     fetch(lb * 64);
     for (int base = lb * 64; base < n; base += stride) {
-        const int w = nw_;
+        int w = nw_;
+        if (fl_out) {
+            // front list: last round's winners leave it, the rest stays
+            if (w >= 0 && nst >= 0 && !(nst & TENT)) w = -1;
+            const uint64_t bal = __ballot(w >= 0);
+            int fbase = 0;
+            if (lane == 0 && bal) fbase = atomicAdd(fl_out_n, __builtin_popcountll(bal));
+            fbase = __shfl(fbase, 0);
+            if (w >= 0) fl_out[fbase + __builtin_popcountll(bal & ((1ull << lane) - 1ull))] = w;
+        }
         const int beg = w >= 0 ? nbeg : 0, d = w >= 0 ? nend - nbeg : 0;
         fetch(base + stride);
         uint64_t m = 0;
@@ -464,8 +512,9 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
         // the worklist is ascending, so the 64 rows lie in one stretch of the
         // row ids; when that stretch fits, it is copied flat (rows of
         // vertices between worklist entries included), else row by row
-        const int beg0 = __shfl(beg, 0);
-        const int span = wave_max(w >= 0 ? beg + d : 0) - beg0;
+        // (the front list is unordered: the stretch starts at the smallest row)
+        const int beg0 = wave_min(w >= 0 && d > 0 ? beg : 0x7fffffff);
+        const int span = beg0 == 0x7fffffff ? 0 : wave_max(w >= 0 && d > 0 ? beg + d : 0) - beg0;
         const bool flat = span <= STAGE;
         const int sofs = flat ? beg - beg0 : pre;   // lane's row in s_idx
         if (flat) {
@@ -535,6 +584,7 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
             }
         }
         bool coop_mark = false;   // a long row's nets re-opened by the whole wave
+        bool changed = false;     // (front-driven rounds) w's nets go on the dirty list
         if (w >= 0) {
             int col = -1;
             if (~m) {
@@ -552,7 +602,9 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
                 } else if (st[w] != nv) {
                     // standing proposals: a changed proposal re-opens w's nets
                     st[w] = nv;
-                    if (staged) {
+                    if (dl.list) {
+                        changed = true;
+                    } else if (staged) {
                         if (D2) dirty[w] = 1;
                         for (int k = 0; k < d; k++) dirty[s_idx[sofs + k]] = 1;
                     } else if (d > COOP_NETS) {
@@ -572,6 +624,41 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
             const int bj = __shfl(beg, j), dj = __shfl(d, j);
             for (int k = lane; k < dj; k += WAVE) dirty[g.a_idx[bj + k]] = 1;
         }
+        if (dl.list) {
+            // the nets of changed proposals onto the dirty list: each lane
+            // claims its row's nets (first 32 through a position mask, the
+            // rest one by one), one atomic per wave for the slots
+            uint64_t newm = 0;
+            if (changed) {
+                if (D2) dl_mark(dl, w);   // w's own closed neighbourhood
+                // the stamps of the first 32 nets read together, then the
+                // exchanges of the unstamped ones issued together
+                const int r1 = dl.round + 1;
+                int vs[32], sv[32];
+#pragma unroll
+                for (int k = 0; k < 32; k++) vs[k] = k < d ? (staged ? s_idx[sofs + k] : g.a_idx[beg + k]) : -1;
+#pragma unroll
+                for (int k = 0; k < 32; k++) sv[k] = vs[k] >= 0 ? dl.stamp[vs[k]] : r1;
+#pragma unroll
+                for (int k = 0; k < 32; k++) sv[k] = sv[k] != r1 ? atomicExch(&dl.stamp[vs[k]], r1) : r1;
+#pragma unroll
+                for (int k = 0; k < 32; k++)
+                    if (sv[k] != r1) newm |= 1ull << k;
+                for (int k = 32; k < d; k++) dl_mark(dl, staged ? s_idx[sofs + k] : g.a_idx[beg + k]);
+            }
+            const int cnt = __builtin_popcountll(newm);
+            const int incl = wave_incl_scan(cnt);
+            const int tot = __shfl(incl, WAVE - 1);
+            if (tot) {
+                int dbase = 0;
+                if (lane == WAVE - 1) dbase = atomicAdd(dl.n, tot);
+                dbase = __shfl(dbase, WAVE - 1) + incl - cnt;
+                for (uint64_t t = newm; t; t &= t - 1) {
+                    const int k = __builtin_ctzll(t);
+                    dl.list[dbase++] = staged ? s_idx[sofs + k] : g.a_idx[beg + k];
+                }
+            }
+        }
         __syncthreads();
     }
     local_max = wave_max(local_max);
@@ -587,7 +674,7 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
 template <bool D2>
 __global__ void k_vcolor_wide(Graph g, const int *heavy, Ctrl *ctrl, int *st, int lds_bits, IncCtrl *ic,
                               unsigned *aff_bits, int *A, unsigned *tchg_bits, int *tcn, const uint64_t *hw, int PH,
-                              int *ffc, uint8_t *dirty)
+                              int *ffc, uint8_t *dirty, DirtyList dl = DirtyList{nullptr, nullptr, nullptr, 0})
 {
     extern __shared__ uint32_t dyn[];
     __shared__ int s_net[1025], s_pre[1025], s_scan[20], s_res;
@@ -656,7 +743,7 @@ __global__ void k_vcolor_wide(Graph g, const int *heavy, Ctrl *ctrl, int *st, in
             // standing proposals: a changed proposal re-opens w's nets
             const bool changed = st[w] != (TENT | col);
             __syncthreads();
-            if (changed) mark_nets_dirty<D2>(g, w, dirty, tid, nt);
+            if (changed) mark_nets_dirty<D2>(g, w, dirty, tid, nt, &dl);
         }
         if (tid == 0) {
             int nw = TENT | col;
@@ -1692,6 +1779,33 @@ __global__ void __launch_bounds__(64) k_conflict_small(Graph g, const int *st, u
     }
 }
 
+// Removal in front-driven rounds: the nets listed dirty by this round's
+// coloring (every net in the first round), one lane per net, scanned as in
+// k_conflict_small's standing-proposal path.
+constexpr int LIST_BLOCK = 256;
+template <bool D2>
+__global__ void __launch_bounds__(LIST_BLOCK) k_conflict_list(Graph g, const int *st, uint8_t *done, SPState sp,
+                                                              const int *list, const int *n_p,
+                                                              unsigned long long *prof)
+{
+    const int n = *n_p;
+    int scanned = 0;
+    for (int i = blockIdx.x * LIST_BLOCK + threadIdx.x; i < n; i += gridDim.x * LIST_BLOCK) {
+        const int v = list[i];
+        const int b = g.b_off[v], e = g.b_off[v + 1];
+        const int sz = e - b + (D2 ? 1 : 0);
+        if (sz >= 2 && sz <= SMALL_NET) {
+            const int pending = scan_net<D2>(v, b, e, g.b_idx, 0, st, nullptr, 1, &sp, (long)b + (D2 ? v : 0));
+            if (pending == 0) done[v] = 1;
+            scanned += sz;
+        }
+    }
+    if (prof) {
+        const int ws = wave_sum(scanned);
+        if (lane_id() == 0 && ws) atomicAdd(&prof[4 * (blockIdx.x & 63) + 3], (unsigned long long)ws);
+    }
+}
+
 // Profiling only (launched after the timed removal launch): the round's nets
 // of at most SMALL_NET members -- those with a member still uncolored or
 // proposed -- and their sizes, the units the removal step is responsible for.
@@ -2115,6 +2229,184 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
     if (lane == 0) {
         if (evicted) atomicAdd(&rec[round].evicted, evicted);
         if (mx >= 0) max_to(&ctrl->pad[0], mx);
+    }
+}
+
+// Closing kernel of a front-driven first-fit round.  A vertex-based
+// first-fit proposal is 0 unless some net of the vertex holds color 0, so
+// the uncolored vertices split into the front (F(w) holds 0: their first-fit
+// is recomputed every round, on the front list) and the rest, whose standing
+// proposal 0 never needs recomputing.  After the removal step the winners are
+// exactly the vertices still holding a proposal with loss count 0 (every
+// other one lost in some net), so this kernel streams over all vertices,
+// four per thread: a winner's proposal becomes its color and the color's bit
+// goes into the words of its nets (the exchanges issued together); a net that
+// gains its first member of color 0 goes on the list zl for k_front_push.
+// The last block to finish closes the round (worklist size, record, host
+// mirror) and clears the counters of the lists this round consumed.
+constexpr int APPLY_BLOCK = 256;
+template <bool D2>
+__global__ void __launch_bounds__(APPLY_BLOCK) k_front_apply(Graph g, const int *lcnt, int *st, uint64_t *mask0,
+                                                             uint64_t *hw, int PH, int *zl, int *zl_n, Ctrl *ctrl,
+                                                             int par, RoundRec *rec, int round, int *host,
+                                                             int *clear_a, int *clear_b, int *clear_c)
+{
+    __shared__ int s_scan[8];
+    __shared__ bool s_last;
+    const int lane = lane_id();
+    const int n = g.n_a;
+    int wins = 0, mx = -1;
+    const long nq = ((long)n + 3) / 4;   // groups of four vertices
+    const long tstride = (long)gridDim.x * APPLY_BLOCK;
+    const long nloop = (nq + tstride - 1) / tstride;
+    for (long it = 0; it < nloop; it++) {
+        const long qi = it * tstride + (long)blockIdx.x * APPLY_BLOCK + threadIdx.x;
+        int xs[4], cs[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            xs[k] = -1;
+            cs[k] = -1;
+        }
+        if (qi < nq) {
+            const long x0 = qi * 4;
+            int sv[4], lv[4];
+            if (x0 + 3 < n && !((uintptr_t)st & 15)) {
+                const int4 s4 = *(const int4 *)(st + x0);   // st 16-byte aligned, x0 a multiple of 4
+                sv[0] = s4.x; sv[1] = s4.y; sv[2] = s4.z; sv[3] = s4.w;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; k++) sv[k] = x0 + k < n ? st[x0 + k] : -1;
+            }
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < 4; k++) any |= sv[k] >= 0 && (sv[k] & TENT);
+            if (any) {
+#pragma unroll
+                for (int k = 0; k < 4; k++) lv[k] = (sv[k] >= 0 && (sv[k] & TENT)) ? lcnt[x0 + k] : 1;
+#pragma unroll
+                for (int k = 0; k < 4; k++)
+                    if (sv[k] >= 0 && (sv[k] & TENT) && lv[k] == 0) {
+                        xs[k] = (int)(x0 + k);
+                        cs[k] = sv[k] & COLOR_MASK;
+                        st[x0 + k] = cs[k];
+                    }
+            }
+        }
+        // the winners' colors in the words of their nets; nets gaining color 0
+        for (int k = 0; k < 4; k++) {
+            const int x = xs[k], col = cs[k];
+            uint64_t zero_nets = 0;
+            int nn = 0;
+            if (x >= 0) {
+                wins++;
+                mx = max(mx, col);
+                nn = Acc<D2>::nets_count(g, x);
+                // all exchanges in flight before any result is looked at
+                uint64_t olds[32];
+#pragma unroll
+                for (int j = 0; j < 32; j++) {
+                    if (j < nn) {
+                        const int v = Acc<D2>::net_at(g, x, j);
+                        if (col == 0) olds[j] = atomicOr((unsigned long long *)&mask0[v], 1ull);
+                        else if (col < 64) atomicOr((unsigned long long *)&mask0[v], 1ull << col);
+                        else if ((col >> 6) - 1 < PH)
+                            atomicOr((unsigned long long *)&hw[(long)v * PH + (col >> 6) - 1], 1ull << (col & 63));
+                    }
+                }
+                if (col == 0) {
+#pragma unroll
+                    for (int j = 0; j < 32; j++)
+                        if (j < nn && !(olds[j] & 1ull)) zero_nets |= 1ull << j;
+                }
+                for (int j = 32; j < nn; j++) {   // vertices of many nets: one by one
+                    const int v = Acc<D2>::net_at(g, x, j);
+                    if (col == 0) {
+                        if (!(atomicOr((unsigned long long *)&mask0[v], 1ull) & 1ull)) zl[atomicAdd(zl_n, 1)] = v;
+                    } else if (col < 64) {
+                        atomicOr((unsigned long long *)&mask0[v], 1ull << col);
+                    } else if ((col >> 6) - 1 < PH) {
+                        atomicOr((unsigned long long *)&hw[(long)v * PH + (col >> 6) - 1], 1ull << (col & 63));
+                    }
+                }
+            }
+            // newly zero nets onto zl, one atomic per wave for the slots
+            const int cnt = __builtin_popcountll(zero_nets);
+            const int incl = wave_incl_scan(cnt);
+            const int tot = __shfl(incl, WAVE - 1);
+            if (tot) {
+                int base = 0;
+                if (lane == WAVE - 1) base = atomicAdd(zl_n, tot);
+                base = __shfl(base, WAVE - 1) + incl - cnt;
+                for (uint64_t t = zero_nets; t; t &= t - 1) zl[base++] = Acc<D2>::net_at(g, x, __builtin_ctzll(t));
+            }
+        }
+    }
+    wins = block_sum(wins, s_scan);
+    mx = block_max(mx, s_scan);
+    if (threadIdx.x == 0) {
+        if (wins) atomicAdd(&ctrl->win, wins);
+        if (mx >= 0) max_to(&ctrl->pad[0], mx);
+        __threadfence();
+        s_last = atomicAdd(&ctrl->done_blocks, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+        __threadfence();
+        const int w = ctrl->n_w[par];
+        const int total_wins = atomicAdd(&ctrl->win, 0);
+        const int left = w - total_wins;
+        ctrl->n_w[par ^ 1] = left;
+        ctrl->win = 0;
+        ctrl->done_blocks = 0;
+        ctrl->n_heavy = 0;
+        *clear_a = 0;
+        *clear_b = 0;
+        *clear_c = 0;
+        if (w > 0) {
+            ctrl->rounds += 1;
+            RoundRec &R = rec[round];
+            R.mode = 0;
+            R.w = w;
+            R.losers = left;
+            R.max_color = atomicAdd(&ctrl->pad[0], 0);
+            if (host) {
+                __atomic_store_n(&host[1], left, __ATOMIC_RELAXED);
+                __atomic_store_n(&host[2], ctrl->error, __ATOMIC_RELAXED);
+                __atomic_store_n(&host[3], R.max_color, __ATOMIC_RELAXED);
+                __threadfence_system();
+                __atomic_store_n(&host[0], round, __ATOMIC_RELAXED);
+                __threadfence_system();
+            }
+        }
+    }
+}
+
+// Members of the nets that gained color 0 join the front list (one lane per
+// (net, member) pair: every exchange of the round in flight at once); a flag
+// per vertex, taken by exchange, lets each vertex join once, so the front
+// lists never hold more than |V_A| entries.
+template <bool D2>
+__global__ void __launch_bounds__(256) k_front_push(Graph g, const int *zl, const int *zl_n, const int *st,
+                                                    int *infront, int *fl_out, int *fl_out_n)
+{
+    const long n = (long)*zl_n * SMALL_NET;
+    for (long i = blockIdx.x * 256L + threadIdx.x; i - threadIdx.x < n; i += gridDim.x * 256L) {
+        int y = -1;
+        if (i < n) {
+            const int v = zl[i / SMALL_NET];
+            const int k = (int)(i % SMALL_NET);
+            if (k < Acc<D2>::size(g, v)) {
+                y = Acc<D2>::member(g, v, k);
+                const int sy = st[y];
+                if (!((sy < 0 || (sy & TENT)) && !infront[y] && atomicExch(&infront[y], 1) == 0)) y = -1;
+            }
+        }
+        const uint64_t bal = __ballot(y >= 0);
+        if (!bal) continue;
+        int base = 0;
+        if (lane_id() == 0) base = atomicAdd(fl_out_n, __builtin_popcountll(bal));
+        base = __shfl(base, 0);
+        if (y >= 0) fl_out[base + __builtin_popcountll(bal & ((1ull << lane_id()) - 1ull))] = y;
     }
 }
 

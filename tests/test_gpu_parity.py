@@ -560,3 +560,113 @@ def test_round_hashes_and_times(cuda, kw):
     big = synth.stencil27(40)
     res, _ = _gpu_bgpc(cuda, big)
     assert (res.log["round_ms"] > 0).all() and len(res.log["round_ms"]) == res.rounds
+
+
+def test_smallest_last_orders(cuda):
+    """The device's smallest-last orders (removal steps, with and without the
+    slack) equal the oracle's, bipartite and distance-2; coloring in that order
+    equals the oracle's coloring in it."""
+    import torch
+    for g in (synth.random_uniform(5003, 4001, 2, 8, 11), synth.stencil27(20),
+              synth.skewed(30000, 30000, seed=5, kmax=3000, name="skewed30k"), synth.from_nets(7, [])):
+        A, B = bgpc.upload_bipartite(g)
+        for shift in (3, 63):
+            got, steps = bgpc.order_smallest_last(A, B, slack_shift=shift, with_steps=True)
+            want, wsteps = oracle.order_smallest_last(g, with_steps=True, slack_shift=shift)
+            assert steps == wsteps and np.array_equal(got.cpu().numpy(), want), (g.name, shift)
+        order = want
+        ref = oracle.bgpc(g, order=order, net_color_mask=1)
+        res, colors = _gpu_bgpc(cuda, g, order=order, net_color_mask=1)
+        _compare_full(res, colors, ref)
+    adj = synth.rmat(12, 8, 0.57, 0.19, 0.19, seed=4)
+    D = bgpc.upload_adjacency(adj)
+    got, steps = bgpc.d2gc_order_smallest_last(D, slack_shift=3, with_steps=True)
+    want, wsteps = oracle.d2gc_order_smallest_last(adj, with_steps=True, slack_shift=3)
+    assert steps == wsteps and np.array_equal(got.cpu().numpy(), want)
+    ref = oracle.d2gc(adj, order=want, net_color_mask=1)
+    res, colors = _gpu_d2(cuda, adj, order=want, net_color_mask=1)
+    _compare_full(res, colors, ref)
+
+
+def _grid7(g):
+    """Adjacency of the 7-point stencil on a g^3 grid (degree <= 6)."""
+    ids = np.arange(g ** 3).reshape(g, g, g)
+    e = [np.stack([ids[:, :, :-1].ravel(), ids[:, :, 1:].ravel()], 1),
+         np.stack([ids[:, :-1, :].ravel(), ids[:, 1:, :].ravel()], 1),
+         np.stack([ids[:-1, :, :].ravel(), ids[1:, :, :].ravel()], 1)]
+    return synth.adjacency_from_edges(g ** 3, np.concatenate(e))
+
+
+def test_front_driven_rounds(cuda):
+    """Front-driven first-fit rounds (only vertices whose nets hold color 0
+    are recolored, removal over the listed dirty nets, winners streamed) on
+    graphs of at least 2^20 small nets: every round's record and hashes equal
+    the oracle's, also when stopped after a few rounds; the default rounds
+    give the same."""
+    t = bgpc.tuning(front=1)
+    g = synth.stencil27(102)
+    ref = oracle.bgpc(g)
+    res, colors = _gpu_bgpc(cuda, g, log_hashes=True, tune=t)
+    _compare_full(res, colors, ref)
+    assert np.array_equal(res.log["hash_t"], ref.log["hash_t"])
+    assert np.array_equal(res.log["hash_c"], ref.log["hash_c"])
+    res, colors = _gpu_bgpc(cuda, g)
+    _compare_full(res, colors, ref)
+    for k in (1, 2, 7):
+        refk = oracle.bgpc(g, max_rounds=k)
+        res, colors = _gpu_bgpc(cuda, g, max_rounds=k, tune=t)
+        _compare_full(res, colors, refk)
+    r = synth.random_uniform(1100000, 1050000, 2, 8, 61)
+    ref = oracle.bgpc(r)
+    res, colors = _gpu_bgpc(cuda, r, tune=t)
+    _compare_full(res, colors, ref)
+    adj = _grid7(102)
+    ref = oracle.d2gc(adj)
+    res, colors = _gpu_d2(cuda, adj, tune=t)
+    _compare_full(res, colors, ref)
+
+
+FORCED = [dict(front=1), dict(front=0, standing=1), dict(standing=0), dict(planes=1), dict(planes=0),
+          dict(color_grid=8, removal_grid=2, apply_grid=2), dict(front=1, color_grid=64, removal_grid=32)]
+
+
+@pytest.mark.parametrize("forced", FORCED, ids=str)
+def test_tuning_choices_keep_results(cuda, forced):
+    """Every result-invariant choice, forced on graphs of every kind (front-
+    driven rounds and standing proposals also on small graphs, color words on
+    and off, extreme grids): colors, rounds and round log equal the oracle's."""
+    t = bgpc.tuning(**forced)
+    cases = [(synth.random_uniform(5003, 4001, 2, 8, 11), dict()),
+             (synth.random_uniform(3000, 2500, 40, 90, 21), dict()),     # colors past 63
+             (synth.stencil27(24), dict()),
+             (synth.random_uniform(20481, 9000, 3, 30, 12), dict(net_color_mask=0b101)),
+             (synth.skewed(30000, 30000, seed=5, kmax=3000, name="skewed30k"), dict(net_color_mask=1, policy=2))]
+    for g, kw in cases:
+        ref = oracle.bgpc(g, **kw)
+        res, colors = _gpu_bgpc(cuda, g, tune=t, **kw)
+        _compare_full(res, colors, ref)
+    for adj in (_grid7(20), synth.rmat(11, 8, 0.57, 0.19, 0.19, seed=4)):
+        ref = oracle.d2gc(adj)
+        res, colors = _gpu_d2(cuda, adj, tune=t)
+        _compare_full(res, colors, ref)
+
+
+def test_autotune(cuda):
+    """The autotuner returns a choice no slower than the library's own (it
+    checks every candidate's colors against the default's itself); the tuned
+    choice, explicit or from the shape cache, gives the oracle's colors."""
+    for g, kw in ((synth.stencil27(48), dict()), (synth.random_uniform(20000, 20000, 2, 8, 1), dict()),
+                  (synth.random_uniform(30000, 30000, 3, 30, 41), dict(net_color_mask=1))):
+        A, B = bgpc.upload_bipartite(g)
+        best, ms_default, ms_best = bgpc.autotune(A, B, trials=2, **kw)
+        assert ms_best <= ms_default
+        ref = oracle.bgpc(g, **kw)
+        res, colors = _gpu_bgpc(cuda, g, (A, B), tune=best, **kw)
+        _compare_full(res, colors, ref)
+        res, colors = _gpu_bgpc(cuda, g, (A, B), **kw)   # the cached choice
+        _compare_full(res, colors, ref)
+    adj = _grid7(24)
+    D = bgpc.upload_adjacency(adj)
+    best, _, _ = bgpc.autotune(D, None, trials=1)
+    res, colors = _gpu_d2(cuda, adj, D, tune=best)
+    _compare_full(res, colors, oracle.d2gc(adj))

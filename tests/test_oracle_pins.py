@@ -622,3 +622,78 @@ def test_net_balance_first_fit_policy_is_plain_reverse_rejected():
     Algorithm 6 variant the call is rejected."""
     g = synth.from_nets(5, E1_NETS)
     assert oracle.bgpc(g, net_color_mask=1, net_balance=True, net_alg=1).status == oracle.E_INVALID
+
+
+# ---------------------------------------------------------------------------
+# smallest-last orders
+
+
+def _keys_from_scratch(g, alive):
+    """key(u) = sum over the nets v of u of (present members of v - 1), for
+    the present vertices, from the scipy incidence matrix."""
+    m = incidence(g).astype(np.int64)
+    present = m @ alive.astype(np.int64)                  # present members per net
+    per = m.T @ (present - 1)
+    return np.where(alive, per, -1).astype(np.int64)
+
+
+def _smallest_last_brute(g, batched, shift=63):
+    n = g.n_a if hasattr(g, "n_a") else g.n
+    alive = np.ones(n, bool)
+    steps = []
+    while alive.any():
+        key = _keys_from_scratch(g, alive)
+        d = key[alive].min()
+        thr = d if shift >= 63 else d + (d >> shift)
+        if batched:
+            b = np.flatnonzero(alive & (key <= thr))
+        else:
+            b = np.flatnonzero(alive & (key == d))[:1]
+        steps.append(b)
+        alive[b] = False
+    return np.concatenate(steps[::-1]).astype(np.int32), len(steps)
+
+
+def test_smallest_last_worked_examples():
+    """E1: keys 3,3,4,3,3; the four vertices at 3 leave first, then 2.  One
+    at a time: 0 (key 3, lowest id), then 1 (2), 2 (2), 3 (1), 4 (0).  E4:
+    keys 5,5,6,4,4,5,5,4; {3,4,7} at 4, then {0,1,5,6} at 3, then {2}."""
+    e1 = synth.from_nets(5, E1_NETS)
+    assert oracle.order_smallest_last(e1).tolist() == [2, 0, 1, 3, 4]
+    assert oracle.order_smallest_last(e1, batched=False).tolist() == [4, 3, 2, 1, 0]
+    e4 = synth.from_nets(8, [[0, 1, 2, 3], [0, 4, 5], [1, 4, 6], [2, 5, 6, 7], [3, 7]])
+    o, st = oracle.order_smallest_last(e4, with_steps=True)
+    assert o.tolist() == [2, 0, 1, 5, 6, 3, 4, 7] and st == 3
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_smallest_last_against_recount(seed):
+    """Every step's keys recounted from scratch with scipy (no incremental
+    decrements) give the same orders, with and without slack, one vertex at
+    a time or in steps."""
+    g = synth.random_uniform(300, 250, 2, 9, seed)
+    for batched, shift in ((True, 63), (True, 3), (True, 1), (False, 63)):
+        want, steps = _smallest_last_brute(g, batched, shift)
+        got, st = oracle.order_smallest_last(g, batched=batched, with_steps=True, slack_shift=shift)
+        assert np.array_equal(got, want) and st == steps, (batched, shift)
+    adj = synth.rmat(8, 6, 0.57, 0.19, 0.19, seed=seed)
+    want, steps = _smallest_last_brute(adj, True, 3)
+    got, st = oracle.d2gc_order_smallest_last(adj, with_steps=True, slack_shift=3)
+    assert np.array_equal(got, want) and st == steps
+
+
+def test_smallest_last_one_vertex_peeling_properties():
+    """One vertex at a time: reading the order backwards, each vertex has the
+    smallest key among the vertices not yet removed (ties to the lowest id) --
+    the definition of the peeling; on a single net all keys tie, so the
+    order is descending id."""
+    g = synth.random_uniform(120, 90, 2, 7, 9)
+    order = oracle.order_smallest_last(g, batched=False)
+    alive = np.ones(g.n_a, bool)
+    for u in order[::-1]:
+        key = _keys_from_scratch(g, alive)
+        cand = np.flatnonzero(alive & (key == key[alive].min()))
+        assert u == cand[0]
+        alive[u] = False
+    single = synth.from_nets(6, [[0, 1, 2, 3, 4, 5]])
+    assert oracle.order_smallest_last(single, batched=False).tolist() == [5, 4, 3, 2, 1, 0]
