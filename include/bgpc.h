@@ -460,6 +460,31 @@ BGPC_API int bgpc_session_poll(bgpc_session *session, bgpc_completion *out, int3
                                int32_t wait_ms);
 BGPC_API void bgpc_session_destroy(bgpc_session *session);
 
+/*
+ * Allocation-free bgpc_color, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same rounds and colors as bgpc_color(csr_A, csr_B, NULL,
+ * opts, colors_out), with the workspace in a static device array of
+ * BGPC_NOALLOC_SCRATCH_BYTES (64 MiB) that each GPU the library runs on holds
+ * until the process ends.  Calls no hipMalloc / hipFree / hipHostMalloc.
+ *   Limits: |V_A| <= BGPC_NOALLOC_MAX_VERTICES, |V_B| <= BGPC_NOALLOC_MAX_NETS,
+ *   nnz <= BGPC_NOALLOC_MAX_NNZ, the natural order only, and a workspace
+ *   that fits the array (BGPC_E_UNSUPPORTED otherwise, before anything runs);
+ *   no BGPC_INCREMENTAL, prof, or log hashes / round times
+ *   (BGPC_E_UNSUPPORTED).  Colors past 63 are found through per-vertex LDS
+ *   bitmaps instead of per-net color words (same colors; BGPC_E_UNSUPPORTED
+ *   when a vertex's distance-2 colors pass the LDS bitmap).
+ *   Every call on one GPU uses that GPU's one array and leaves its contents
+ *   behind (each call initializes what it reads): calls that overlap on one
+ *   GPU, from any stream or thread, race and must be serialized by the caller.
+ */
+#define BGPC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+#define BGPC_NOALLOC_MAX_VERTICES (1 << 20)
+#define BGPC_NOALLOC_MAX_NETS (1 << 20)
+#define BGPC_NOALLOC_MAX_NNZ (1ll << 24)
+BGPC_API int bgpc_color_noalloc(const bgpc_csr *csr_A, const bgpc_csr *csr_B, const bgpc_opts *opts,
+                                int32_t *colors_out);
+
 /* Human-readable name of a status code (static storage). */
 BGPC_API const char *bgpc_status_string(int status);
 

@@ -139,6 +139,8 @@ def load():
         lib.d2gc_order_smallest_last.argtypes = [ctypes.POINTER(Csr), ctypes.c_int32, P, P,
                                                  ctypes.POINTER(ctypes.c_int32)]
         lib.d2gc_order_smallest_last.restype = ctypes.c_int
+        lib.bgpc_color_noalloc.argtypes = [ctypes.POINTER(Csr), ctypes.POINTER(Csr), ctypes.POINTER(Opts), P]
+        lib.bgpc_color_noalloc.restype = ctypes.c_int
         lib.bgpc_status_string.argtypes = [ctypes.c_int]
         lib.bgpc_status_string.restype = ctypes.c_char_p
         _lib = lib
@@ -148,7 +150,7 @@ def load():
 EXPORTED = ("bgpc_opts_default", "bgpc_color", "d2gc_color", "color_stats", "bgpc_status_string",
             "bgpc_color_batch", "bgpc_session_create", "bgpc_session_submit", "bgpc_session_poll",
             "bgpc_session_destroy", "bgpc_order_largest_first", "d2gc_order_largest_first",
-            "bgpc_order_smallest_last", "d2gc_order_smallest_last", "bgpc_autotune")
+            "bgpc_order_smallest_last", "d2gc_order_smallest_last", "bgpc_autotune", "bgpc_color_noalloc")
 
 
 def status_string(code: int) -> str:
@@ -274,6 +276,25 @@ def bgpc_color(csr_A: DeviceCsr, csr_B: DeviceCsr, order, colors_out, net_color_
     st = lib.bgpc_color(ctypes.byref(a), ctypes.byref(b), order_p, ctypes.byref(o), _dev_ptr(colors_out, "colors_out"))
     del keep
     return _finish(st, rounds, log_arrays, o)
+
+
+def bgpc_color_noalloc(csr_A: DeviceCsr, csr_B: DeviceCsr, colors_out, net_color_mask=0, policy=FIRST_FIT,
+                       chunk=64, max_rounds=0, start_round=0, flags=0, stream=None, log_cap=0,
+                       net_conflict_mask=ALL_NET, net_alg=NET_ALG8) -> Result:
+    """bgpc_color without any allocation (natural order; workspace in the
+    library's static device array)."""
+    lib = load()
+    o, rounds, log_arrays, keep = _make_opts(net_color_mask, policy, chunk, max_rounds, start_round, flags,
+                                             stream, log_cap, None, net_conflict_mask, net_alg)
+    if o.log:
+        o.log.contents.round_ms = None   # per-round events are not created without allocation
+    a, b = csr_A.as_struct(), csr_B.as_struct()
+    st = lib.bgpc_color_noalloc(ctypes.byref(a), ctypes.byref(b), ctypes.byref(o), _dev_ptr(colors_out, "colors_out"))
+    del keep
+    res = _finish(st, rounds, log_arrays, o)
+    if res.log is not None:
+        res.log.pop("round_ms", None)
+    return res
 
 
 def d2gc_color(adj: DeviceCsr, order, colors_out, net_color_mask=0, policy=FIRST_FIT, chunk=64, max_rounds=0,

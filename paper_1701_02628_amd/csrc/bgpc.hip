@@ -1521,6 +1521,71 @@ void release_thread_state()
 
 extern "C" {
 
+// ---- allocation-free entry point: the workspace is one static device array
+// per GPU (held until the process ends); host code reaches it only through
+// the address hipGetSymbolAddress returns on that device.
+namespace {
+__device__ __align__(256) unsigned char scratch[BGPC_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[64] = {};
+
+// address of this device's scratch array (looked up once per device, with
+// the device current); null when the lookup fails
+char *scratch_of_current_device()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = (char *)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" BGPC_API int bgpc_color_noalloc(const bgpc_csr *csr_A, const bgpc_csr *csr_B, const bgpc_opts *opts,
+                                           int32_t *colors_out)
+{
+    bgpc_opts o;
+    if (opts) o = *opts;
+    else bgpc_opts_default(&o);
+    if (!csr_ok(csr_A) || !csr_ok(csr_B) || !colors_out || !opts_ok(o)) return BGPC_E_INVALID;
+    if (csr_A->n_rows != csr_B->n_cols || csr_A->n_cols != csr_B->n_rows || csr_A->nnz != csr_B->nnz)
+        return BGPC_E_INVALID;
+    // sizes past the documented limits, and the options that need memory of
+    // their own (events, pinned buffers), are refused before any device call
+    if (csr_A->n_rows > BGPC_NOALLOC_MAX_VERTICES || csr_B->n_rows > BGPC_NOALLOC_MAX_NETS ||
+        csr_A->nnz > BGPC_NOALLOC_MAX_NNZ || (o.flags & BGPC_INCREMENTAL) || o.prof ||
+        (o.log && (o.log->hash_t || o.log->hash_c || o.log->round_ms)))
+        return BGPC_E_UNSUPPORTED;
+    char *base = scratch_of_current_device();
+    if (!base) return BGPC_E_HIP;
+    hipStream_t s = (hipStream_t)o.stream;
+    if (o.flags & BGPC_STRICT) {
+        int v = validate_bipartite(csr_A, csr_B, s, (int *)base);
+        if (v != BGPC_OK) return v;
+    }
+    RunArgs a;
+    a.g = Graph{csr_A->n_rows, csr_B->n_rows, csr_A->offsets, csr_A->indices, csr_B->offsets, csr_B->indices};
+    a.nnz = csr_B->nnz;
+    a.d2 = false;
+    a.o = &o;
+    a.st = colors_out;
+    a.s = s;
+    a.ext = base;
+    a.ext_cap = BGPC_NOALLOC_SCRATCH_BYTES;
+    return run<false>(a);
+}
+
 // ---- autotuner (see bgpc.h)
 extern "C" BGPC_API int bgpc_autotune(const bgpc_csr *csr_A, const bgpc_csr *csr_B, const bgpc_opts *opts,
                                       int32_t trials, bgpc_tuning *best, double *ms_default, double *ms_best)
