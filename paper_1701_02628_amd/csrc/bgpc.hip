@@ -212,6 +212,22 @@ int resident_per_cu()
     return v;
 }
 
+// workgroups of the standing-proposal removal kernel resident per compute unit
+template <bool D2>
+int resident_sp_per_cu()
+{
+    static std::atomic<int> cached{0};
+    int v = cached.load(std::memory_order_relaxed);
+    if (v == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_conflict_small<D2, true>, 64, 0) != hipSuccess || v <= 0) {
+            (void)hipGetLastError();
+            v = 32;
+        }
+        cached.store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
 // Choices cached by bgpc_autotune, keyed by the shape of the graph and the
 // class of the schedule.
 struct TuneKey {
@@ -309,6 +325,7 @@ int run(const RunArgs &a)
                    + aligned(sp_words, 8)             // standing proposals: verdict bits
                    + aligned(n_a + 1, 4)              //   loss counts
                    + aligned(n_b + 1, 1)              //   dirty nets
+                   + aligned(n_a + 1, 1)              //   vertices with a net holding color 0
                    + aligned(fr_a + 1, 4) * 3         // front lists, front flags
                    + aligned(fr_b + 1, 4) * 4;        //   dirty-net list, its stamps, two zero-net lists
     const bool noalloc = a.ext != nullptr;
@@ -353,6 +370,7 @@ int run(const RunArgs &a)
     unsigned long long *sp_bits = ar.take<unsigned long long>(sp_words);
     int *sp_cnt = ar.take<int>(n_a + 1);
     uint8_t *sp_dirty = ar.take<uint8_t>(n_b + 1);
+    uint8_t *zf = ar.take<uint8_t>(n_a + 1);
     int *FL[2] = {ar.take<int>(fr_a + 1), ar.take<int>(fr_a + 1)};
     int *infront = ar.take<int>(fr_a + 1);
     int *DL = ar.take<int>(fr_b + 1);
@@ -378,6 +396,11 @@ int run(const RunArgs &a)
     HeavySlice *hv_slices = nullptr;
     uint64_t *hv_F = nullptr;
     int hv_H = 0, hv_stride = 0;
+    // column-major copy of the nets' first members for the standing-proposal
+    // removal scan (distance-1 graphs; skipped without room, or without
+    // allocation)
+    int *ell = nullptr;
+    int ell_w = 0;
     long mc_ub = -1;   // upper bound of every color present before the next round
     // (decided from the graph's shape below)
     bool planes_ok = !(o.flags & BGPC_INCREMENTAL) && !noalloc;   // the words are allocated as colors grow
@@ -517,6 +540,16 @@ int run(const RunArgs &a)
         // (its candidate listing) and standing proposals
         const bool front = front_possible && n_big == 0 && n_huge == 0 && max_net <= SMALL_NET &&
                            !(o.flags & BGPC_NET_BALANCE);
+        if (!D2 && sp_on && !noalloc && max_net >= 2 && (long)std::min(max_net, ELL_W) * n_b < (1L << 31)) {
+            ell_w = std::min(max_net, ELL_W);
+            if (hipMallocAsync((void **)&ell, (size_t)ell_w * (size_t)n_b * 4, s) != hipSuccess) {
+                (void)hipGetLastError();
+                ell = nullptr;
+                ell_w = 0;
+            } else {
+                k_build_ell<<<grid_for((long)ell_w * n_b, nthr, di.cus * 16), nthr, 0, s>>>(g, ell_w, ell);
+            }
+        }
         // distance-2 degree bound: most nets of a vertex x largest net
         const long two_hop = std::min<long>((long)h_shape[2] * (long)max_net, 1L << 30);
         unsigned long long walk;
@@ -681,6 +714,7 @@ int run(const RunArgs &a)
         bool use_prog = prog.h && prog.d;
         bool inc_used = false;
         int net_round_issued = -1;   // last net-based round queued
+        bool zf_valid = false;       // zf matches the masks (kept by the rounds that pass it)
         // one wave per 64 items, grids a multiple of 8 (XCD-aware remap)
         auto grid64 = [&](long items) {
             long gsz = (items + 63) / 64;
@@ -695,6 +729,9 @@ int run(const RunArgs &a)
                                                                                   : resident_per_cu<D2>()) / 8 * 8));
         const int g_w64b = tune.removal_grid > 0 ? std::min(grid64(n_b), std::max(8, di.cus * tune.removal_grid / 8 * 8))
                                                  : grid64(n_b);
+        // standing-proposal removal: one resident pass of workgroups
+        const int g_sp = std::min(grid64(n_b), std::max(8, di.cus * (tune.removal_grid > 0 ? tune.removal_grid
+                                                                           : resident_sp_per_cu<D2>()) / 8 * 8));
         const int g_list = di.cus * (tune.removal_grid > 0 ? tune.removal_grid : 8);
         const int g_fa = grid_for(((long)n_a + 3) / 4, APPLY_BLOCK, di.cus * (tune.apply_grid > 0 ? tune.apply_grid : 8));
         // balanced net rounds: a wave per chunk of net ids, an LDS bitmap of
@@ -815,7 +852,9 @@ int run(const RunArgs &a)
                     k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 1, 1, host);
                 }
                 net_round_issued = r;
+                zf_valid = false;
             } else if (r >= inc_start) {
+                zf_valid = false;
                 // the wide path can only be needed once colors 0..63 all exist
                 bool need_wide = true;
                 if (use_prog) {
@@ -859,9 +898,12 @@ int run(const RunArgs &a)
             } else {
                 uint8_t *dty = spr ? sp_dirty : nullptr;
                 const SPState &spx = spr ? sp_state : sp_none;
+                // first-fit skips standing proposals 0 of vertices without a
+                // net holding color 0 (zf, kept up to date by k_apply)
+                const bool zfr = spr && policy == BGPC_FIRST_FIT && !front;
                 if (front) {
                     const DirtyList dlr{DL, &ctrl->dl_n, dstamp, r};
-                    LAUNCH_PROF(BGPC_PROF_COLOR, (k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, FL[par], ctrl, par, st, mask0, heavy, PCNT(r), hw, PH, ffc, dty, &ctrl->fl_n[par], FL[par ^ 1], &ctrl->fl_n[par ^ 1], dlr)));
+                    LAUNCH_PROF(BGPC_PROF_COLOR, (k_vcolor_ff<D2, true><<<g_w64a, 64, 0, s>>>(g, FL[par], ctrl, par, st, mask0, heavy, PCNT(r), hw, PH, ffc, dty, &ctrl->fl_n[par], FL[par ^ 1], &ctrl->fl_n[par ^ 1], dlr)));
                     bool need_wide = true;
                     if (use_prog) {
                         int seen = prog.h[0], mc = prog.h[3];
@@ -873,7 +915,13 @@ int run(const RunArgs &a)
                                                                                nullptr, nullptr, nullptr, nullptr,
                                                                                hw, PH, ffc, dty, dlr);
                 } else if (policy == BGPC_FIRST_FIT) {
-                    LAUNCH_PROF(BGPC_PROF_COLOR, (k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy, PCNT(r), hw, PH, ffc, dty)));
+                    if (zfr && !zf_valid) {
+                        // before any color exists nothing holds color 0
+                        if (!resume && net_round_issued < 0) k_fill_u8<<<g_a, nthr, 0, s>>>(zf, 0, n_a + 1);
+                        else k_zero_front_init<D2><<<g_a, nthr, 0, s>>>(g, mask0, zf);
+                        zf_valid = true;
+                    }
+                    LAUNCH_PROF(BGPC_PROF_COLOR, (k_vcolor_ff<D2><<<g_w64a, 64, 0, s>>>(g, Wc, ctrl, par, st, mask0, heavy, PCNT(r), hw, PH, ffc, dty, nullptr, nullptr, nullptr, DirtyList{nullptr, nullptr, nullptr, 0}, zfr ? zf : nullptr)));
                     // the wide path can only be needed once colors 0..63 all exist:
                     // a vertex-based first-fit round raises the largest color by at
                     // most one, a net-based round keeps it below the largest net
@@ -928,8 +976,12 @@ int run(const RunArgs &a)
                 } else {
                     if (front)
                         LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_list<D2><<<g_list, LIST_BLOCK, 0, s>>>(g, st, done_net, sp_state, DL, &ctrl->dl_n, PCNT(r))));
+                    else if (spr && ell)
+                        LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2, true, true><<<g_sp, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), sp_state, ell, ell_w)));
+                    else if (spr)
+                        LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2, true><<<g_sp, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), sp_state)));
                     else
-                        LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), spx)));
+                        LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2><<<g_w64b, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), sp_none)));
                     if (spr && prof_kernel == BGPC_PROF_CONFLICT && PCNT(r))
                         k_census<D2><<<g_b, nthr, 0, s>>>(g, st, PCNT(r));
                     if (n_big)
@@ -949,8 +1001,9 @@ int run(const RunArgs &a)
                                                                  FL[par ^ 1], &ctrl->fl_n[par ^ 1]);
                 } else {
                     k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1, hw,
-                                                          PH, spr ? sp_cnt : nullptr);
+                                                          PH, spr ? sp_cnt : nullptr, zfr ? zf : nullptr);
                     k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 0, 1, host);
+                    if (!zfr) zf_valid = false;
                 }
             }
             LAUNCH_CHECK();
@@ -1056,7 +1109,7 @@ finish:
     for (hipEvent_t e : round_ev) (void)hipEventDestroy(e);
     if (h_states) (void)hipHostFree(h_states);
     if (hw) (void)hipFreeAsync(hw, s);
-    for (void *p : {(void *)hv_id, (void *)hv_list, (void *)hv_slices, (void *)hv_counts, (void *)hv_F})
+    for (void *p : {(void *)hv_id, (void *)hv_list, (void *)hv_slices, (void *)hv_counts, (void *)hv_F, (void *)ell})
         if (p) (void)hipFreeAsync(p, s);
     ar.release();
     if (!ar.async) (void)hipGetLastError();

@@ -431,6 +431,18 @@ constexpr int COOP_NETS = 256;   // rows longer than this are ORed by the whole 
 
 // OR of mask0 over the d nets in row[0..d), by the whole wave (eight loads in
 // flight per lane); every lane gets the result.
+// zf[w] = some net of w holds color 0, from the masks (after a net-based
+// round or a resumed start)
+template <bool D2>
+__global__ void k_zero_front_init(Graph g, const uint64_t *mask0, uint8_t *zf)
+{
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < g.n_a; w += gridDim.x * blockDim.x) {
+        uint64_t m = D2 ? mask0[w] : 0ull;
+        for (int k = g.a_off[w]; k < g.a_off[w + 1] && !(m & 1ull); k++) m |= mask0[g.a_idx[k]];
+        zf[w] = (uint8_t)(m & 1ull);
+    }
+}
+
 __device__ uint64_t wave_row_or(const int *row, int d, const uint64_t *mask0)
 {
     const int lane = lane_id();
@@ -458,17 +470,21 @@ __device__ uint64_t wave_row_or(const int *row, int d, const uint64_t *mask0)
 // lane), then every lane ORs the masks of its own row, eight gathers in
 // flight.  The first clear bit is the first-fit color.  Entries whose 64 low
 // colors are all forbidden are queued for k_vcolor_wide.
-// Front mode (fl_out set): W is the front list (uncolored vertices whose
+// zf (vertex rounds with standing proposals): zf[w] is set once some net of
+// w holds color 0; entries without it whose standing proposal is 0 are
+// skipped (first-fit would give 0 again).
+// Front mode (FRONT, fl_out set): W is the front list (uncolored vertices whose
 // nets hold color 0, unordered, with the last round's winners still in it),
 // its length is *n_p; winners are dropped and every other entry is appended
 // to fl_out, the next round's front list.
-template <bool D2>
+template <bool D2, bool FRONT = false>
 __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *ctrl, int par, int *st,
                                                   const uint64_t *mask0, int *heavy, unsigned long long *prof,
                                                   const uint64_t *hw, int PH, int *ffc, uint8_t *dirty,
                                                   const int *n_p = nullptr, int *fl_out = nullptr,
                                                   int *fl_out_n = nullptr,
-                                                  DirtyList dl = DirtyList{nullptr, nullptr, nullptr, 0})
+                                                  DirtyList dl = DirtyList{nullptr, nullptr, nullptr, 0},
+                                                  const uint8_t *zf = nullptr)
 {
     unsigned long long rows = 0;
     __shared__ int s_pre[65], s_beg[64];
@@ -480,19 +496,24 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
     // the next 64 entries and their row offsets are loaded while the current
     // ones are colored
     int nw_ = -1, nbeg = 0, nend = 0, nst = -1;
+    uint8_t nzf = 1;
     auto fetch = [&](int bs) {
         int i = bs + lane;
         nw_ = i < n ? W[i] : -1;
         if (nw_ >= 0) {
             nbeg = g.a_off[nw_];
             nend = g.a_off[nw_ + 1];
-            if (fl_out) nst = st[nw_];
+            if ((FRONT && fl_out) || (!FRONT && zf)) nst = st[nw_];
+            if (!FRONT && zf) nzf = zf[nw_];
         }
     };
     fetch(lb * 64);
     for (int base = lb * 64; base < n; base += stride) {
         int w = nw_;
-        if (fl_out) {
+        // (zf) no net of w holds color 0, so its first-fit answer is 0: a
+        // standing proposal 0 stays as it is
+        if (!FRONT && zf && w >= 0 && !nzf && nst == TENT) w = -1;
+        if (FRONT && fl_out) {
             // front list: last round's winners leave it, the rest stays
             if (w >= 0 && nst >= 0 && !(nst & TENT)) w = -1;
             const uint64_t bal = __ballot(w >= 0);
@@ -602,7 +623,7 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
                 } else if (st[w] != nv) {
                     // standing proposals: a changed proposal re-opens w's nets
                     st[w] = nv;
-                    if (dl.list) {
+                    if (FRONT && dl.list) {
                         changed = true;
                     } else if (staged) {
                         if (D2) dirty[w] = 1;
@@ -624,7 +645,7 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
             const int bj = __shfl(beg, j), dj = __shfl(d, j);
             for (int k = lane; k < dj; k += WAVE) dirty[g.a_idx[bj + k]] = 1;
         }
-        if (dl.list) {
+        if (FRONT && dl.list) {
             // the nets of changed proposals onto the dirty list: each lane
             // claims its row's nets (first 32 through a position mask, the
             // rest one by one), one atomic per wave for the slots
@@ -1550,6 +1571,32 @@ __device__ __forceinline__ void sp_set(const SPState &sp, long pos, int x, bool 
     }
 }
 
+// Column-major copy of the first ELL_W members of every net: member p of
+// net v at ell[p * n_b + v] (-1 past the net's size).  Lanes that scan
+// neighbouring nets then read neighbouring words at every position, where
+// the row-major lists put each lane on its own cache line.  Members past
+// ELL_W come from the row-major lists.
+constexpr int ELL_W = 32;
+struct EllSrc {
+    const int *ell, *idx;   // ell: this net's column (ell + v)
+    int n_b, b, w;          // w * n_b < 2^31
+    __device__ __forceinline__ int operator[](int k) const
+    {
+        const int p = k - b;
+        return p < w ? ell[p * n_b] : idx[k];
+    }
+};
+
+// thread per net: its row read in order, the column written across threads
+__global__ void k_build_ell(Graph g, int w, int *ell)
+{
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n_b; v += gridDim.x * blockDim.x) {
+        const int b = g.b_off[v], d = g.b_off[v + 1] - b;
+        int *col = ell + v;
+        for (int p = 0; p < w; p++) col[p * g.n_b] = p < d ? g.b_idx[b + p] : -1;
+    }
+}
+
 constexpr int SCAN_BATCH = 16;   // member states gathered per batch (all in flight)
 template <bool D2, class Src>
 __device__ __forceinline__ int scan_net(int v, int b, int e, Src src, int rel, const int *st, uint8_t *lose,
@@ -1572,6 +1619,15 @@ __device__ __forceinline__ int scan_net(int v, int b, int e, Src src, int rel, c
         if (p == cpos) return v;
         return (int)src[b + p - 1 - rel];
     };
+    // stored verdicts of this net's positions, loaded before the members
+    // (size <= 64: at most two words; only this thread changes these bits)
+    unsigned long long a0 = 0, a1 = 0;
+    const long w0 = lpos >> 6;
+    const int sh = (int)(lpos & 63);
+    if (sp) {
+        a0 = __atomic_load_n(&sp->lbits[w0], __ATOMIC_RELAXED);
+        if (sh + size > 64) a1 = __atomic_load_n(&sp->lbits[w0 + 1], __ATOMIC_RELAXED);
+    }
     uint64_t seen = 0, lm = 0;   // lm: positions that lose (standing proposals)
     bool wide = false;
     int pending = 0;
@@ -1624,12 +1680,7 @@ __device__ __forceinline__ int scan_net(int v, int b, int e, Src src, int rel, c
         }
     }
     if (sp) {
-        // changed verdicts against the stored bits of this net's positions
-        // (size <= 64: at most two words; only this thread changes them)
-        const long w0 = lpos >> 6;
-        const int sh = (int)(lpos & 63);
-        unsigned long long a0 = __atomic_load_n(&sp->lbits[w0], __ATOMIC_RELAXED);
-        unsigned long long a1 = sh + size > 64 ? __atomic_load_n(&sp->lbits[w0 + 1], __ATOMIC_RELAXED) : 0ull;
+        // changed verdicts against the stored bits
         unsigned long long old = (a0 >> sh) | (sh ? (a1 << (64 - sh)) : 0ull);
         if (size < 64) old &= (1ull << size) - 1ull;
         unsigned long long chg = old ^ lm;
@@ -1652,22 +1703,31 @@ __device__ __forceinline__ int scan_net(int v, int b, int e, Src src, int rel, c
 // until a net-based round evicts (the driver then clears the marks).  With
 // tent_only, only proposed colors take part (after a vertex-based round no
 // colored vertex can clash).
-// Standing proposals: only dirty nets are scanned.  The wave sweeps its
-// stretches' flags, queues the dirty nets in LDS and scans them 64 at a
-// time, one net per lane, members read straight from the net lists.
-template <bool D2>
+// Standing proposals (SP): only dirty nets are scanned.  The wave reads the
+// flags and row offsets of SP_PF of its stretches at once (coalesced, all in
+// flight), queues the dirty nets with their offsets in LDS and scans them 64
+// at a time, one net per lane, members read straight from the net lists.
+constexpr int SP_PF = 4;
+template <bool D2, bool ELLS>
 __device__ void conflict_dirty(const Graph &g, const int *st, uint8_t *done, const SPState &sp, int lb, int nb,
-                               int *q, int &walked_nets, int &walked_members, int &scanned_members, bool prof)
+                               int *qv, int *qb, int *qe, int &walked_nets, int &scanned_members, const int *ell,
+                               int ell_w)
 {
     const int lane = threadIdx.x, stride = nb * 64;
     int qn = 0;
     auto drain = [&](int cnt) {
-        int v = lane < cnt ? q[lane] : -1;
+        const int v = lane < cnt ? qv[lane] : -1;
         if (v >= 0) {
-            const int b = g.b_off[v], e = g.b_off[v + 1];
+            const int b = qb[lane], e = qe[lane];
             const int sz = e - b + (D2 ? 1 : 0);
             if (sz >= 2 && sz <= SMALL_NET) {
-                int pending = scan_net<D2>(v, b, e, g.b_idx, 0, st, nullptr, 1, &sp, (long)b + (D2 ? v : 0));
+                const long lpos = (long)b + (D2 ? v : 0);
+                int pending;
+                if constexpr (ELLS)
+                    pending = scan_net<D2>(v, b, e, EllSrc{ell + v, g.b_idx, g.n_b, b, ell_w}, 0, st, nullptr, 1, &sp,
+                                           lpos);
+                else
+                    pending = scan_net<D2>(v, b, e, g.b_idx, 0, st, nullptr, 1, &sp, lpos);
                 if (pending == 0) done[v] = 1;
                 scanned_members += sz;
                 walked_nets++;
@@ -1676,105 +1736,133 @@ __device__ void conflict_dirty(const Graph &g, const int *st, uint8_t *done, con
         }
         __syncthreads();
         // move the rest of the queue to its front
-        int rest = qn - cnt;
-        int keep = lane < rest ? q[cnt + lane] : 0;
+        const int rest = qn - cnt;
+        int kv = 0, kb = 0, ke = 0;
+        if (lane < rest) {
+            kv = qv[cnt + lane];
+            kb = qb[cnt + lane];
+            ke = qe[cnt + lane];
+        }
         __syncthreads();
-        if (lane < rest) q[lane] = keep;
+        if (lane < rest) {
+            qv[lane] = kv;
+            qb[lane] = kb;
+            qe[lane] = ke;
+        }
         qn = rest;
         __syncthreads();
     };
-    for (int base = lb * 64; base < g.n_b; base += stride) {
-        const int v = base + lane;
-        const bool d = v < g.n_b && sp.dirty[v] && !done[v];
-        const uint64_t bal = __ballot(d);
-        if (d) q[qn + __builtin_popcountll(bal & ((1ull << lane) - 1ull))] = v;
-        qn += __builtin_popcountll(bal);
-        __syncthreads();
-        if (qn >= 64) drain(64);
+    for (int base0 = lb * 64; base0 < g.n_b; base0 += SP_PF * stride) {
+        uint8_t fd[SP_PF], fn[SP_PF];
+        int ob[SP_PF], oe[SP_PF];
+#pragma unroll
+        for (int k = 0; k < SP_PF; k++) {
+            const int v = base0 + k * stride + lane;
+            const bool in = v < g.n_b;
+            fd[k] = in ? sp.dirty[v] : 0;
+            fn[k] = in ? done[v] : 1;
+            ob[k] = in ? g.b_off[v] : 0;
+            oe[k] = in ? g.b_off[v + 1] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < SP_PF; k++) {
+            const int v = base0 + k * stride + lane;
+            const bool d = fd[k] && !fn[k];
+            const uint64_t bal = __ballot(d);
+            if (d) {
+                const int r = qn + __builtin_popcountll(bal & ((1ull << lane) - 1ull));
+                qv[r] = v;
+                qb[r] = ob[k];
+                qe[r] = oe[k];
+            }
+            qn += __builtin_popcountll(bal);
+            __syncthreads();
+            if (qn >= 64) drain(64);
+        }
     }
     if (qn > 0) drain(qn);
 }
 
-template <bool D2>
+template <bool D2, bool SP = false, bool ELLS = false>
 __global__ void __launch_bounds__(64) k_conflict_small(Graph g, const int *st, uint8_t *lose, uint8_t *done,
-                                                       int tent_only, unsigned long long *prof, SPState sp)
+                                                       int tent_only, unsigned long long *prof, SPState sp,
+                                                       const int *ell = nullptr, int ell_w = 0)
 {
     int walked_nets = 0, walked_members = 0;
-    __shared__ int s_idx[STAGE];
     const int lane = threadIdx.x, nb = gridDim.x, lb = xcd_remap(blockIdx.x, nb);
     const int stride = nb * 64;
-    const bool spm = sp.lbits != nullptr;
-    if (spm) {
+    if constexpr (SP) {
         // the round's nets are counted by k_census (profiling only)
+        __shared__ int q[3][128];
         int scanned = 0;
-        conflict_dirty<D2>(g, st, done, sp, lb, nb, s_idx, walked_nets, walked_members, scanned, prof != nullptr);
+        conflict_dirty<D2, ELLS>(g, st, done, sp, lb, nb, q[0], q[1], q[2], walked_nets, scanned, ell, ell_w);
         if (prof) {
             int ws = wave_sum(scanned);
             if (lane == 0 && ws) atomicAdd(&prof[4 * (blockIdx.x & 63) + 3], (unsigned long long)ws);
         }
         return;
-    }
-    // the next stretch's offsets and flags are loaded while the current one
-    // is scanned
-    int nb_ = 0, ne_ = 0, noff0 = 0, noffe = 0;
-    uint8_t nskip = 1;
-    auto fetch = [&](int bs) {
-        if (bs >= g.n_b) return;
-        int v = bs + lane;
-        if (v < g.n_b) {
-            nb_ = g.b_off[v];
-            ne_ = g.b_off[v + 1];
-            nskip = done[v] | (spm ? (uint8_t)!sp.dirty[v] : (uint8_t)0);
-        }
-        noff0 = g.b_off[bs];
-        noffe = g.b_off[min(bs + 64, g.n_b)];
-    };
-    fetch(lb * 64);
-    for (int base = lb * 64; base < g.n_b; base += stride) {
-        const int v = base + lane;
-        const int b = nb_, e = ne_, off0 = noff0, seg = noffe - noff0;
-        const uint8_t skip = nskip;
-        fetch(base + stride);
-        bool act = false;
-        if (v < g.n_b) {
-            int sz = e - b + (D2 ? 1 : 0);
-            act = sz >= 2 && sz <= SMALL_NET && !skip;
-        }
-        if (!__ballot(act)) continue;
-        bool staged = seg <= STAGE;
-        if (staged) {
-            // every load of the stretch in flight before the first LDS store
-            int v32[STAGE / 64];
-#pragma unroll
-            for (int q = 0; q < STAGE / 64; q++) {
-                int f = q * 64 + lane;
-                v32[q] = f < seg ? g.b_idx[off0 + f] : 0;
+    } else {
+        __shared__ int s_idx[STAGE];
+        // the next stretch's offsets and flags are loaded while the current one
+        // is scanned
+        int nb_ = 0, ne_ = 0, noff0 = 0, noffe = 0;
+        uint8_t nskip = 1;
+        auto fetch = [&](int bs) {
+            if (bs >= g.n_b) return;
+            int v = bs + lane;
+            if (v < g.n_b) {
+                nb_ = g.b_off[v];
+                ne_ = g.b_off[v + 1];
+                nskip = done[v];
             }
-#pragma unroll
-            for (int q = 0; q < STAGE / 64; q++) {
-                int f = q * 64 + lane;
-                if (f < seg) s_idx[f] = v32[q];
+            noff0 = g.b_off[bs];
+            noffe = g.b_off[min(bs + 64, g.n_b)];
+        };
+        fetch(lb * 64);
+        for (int base = lb * 64; base < g.n_b; base += stride) {
+            const int v = base + lane;
+            const int b = nb_, e = ne_, off0 = noff0, seg = noffe - noff0;
+            const uint8_t skip = nskip;
+            fetch(base + stride);
+            bool act = false;
+            if (v < g.n_b) {
+                int sz = e - b + (D2 ? 1 : 0);
+                act = sz >= 2 && sz <= SMALL_NET && !skip;
             }
+            if (!__ballot(act)) continue;
+            bool staged = seg <= STAGE;
+            if (staged) {
+                // every load of the stretch in flight before the first LDS store
+                int v32[STAGE / 64];
+    #pragma unroll
+                for (int q = 0; q < STAGE / 64; q++) {
+                    int f = q * 64 + lane;
+                    v32[q] = f < seg ? g.b_idx[off0 + f] : 0;
+                }
+    #pragma unroll
+                for (int q = 0; q < STAGE / 64; q++) {
+                    int f = q * 64 + lane;
+                    if (f < seg) s_idx[f] = v32[q];
+                }
+            }
+            __syncthreads();
+            if (act) {
+                const long lpos = (long)b + (D2 ? v : 0);
+                int pending = staged ? scan_net<D2>(v, b, e, (const int *)s_idx, off0, st, lose, tent_only, nullptr, lpos)
+                                     : scan_net<D2>(v, b, e, g.b_idx, 0, st, lose, tent_only, nullptr, lpos);
+                if (pending == 0) done[v] = 1;
+            }
+            walked_nets += act ? 1 : 0;
+            walked_members += act ? e - b + (D2 ? 1 : 0) : 0;
+            __syncthreads();
         }
-        __syncthreads();
-        if (act) {
-            const SPState *spp = spm ? &sp : nullptr;
-            const long lpos = (long)b + (D2 ? v : 0);
-            int pending = staged ? scan_net<D2>(v, b, e, (const int *)s_idx, off0, st, lose, tent_only, spp, lpos)
-                                 : scan_net<D2>(v, b, e, g.b_idx, 0, st, lose, tent_only, spp, lpos);
-            if (pending == 0) done[v] = 1;
-            if (spm) sp.dirty[v] = 0;
-        }
-        walked_nets += act ? 1 : 0;
-        walked_members += act ? e - b + (D2 ? 1 : 0) : 0;
-        __syncthreads();
-    }
-    if (prof) {
-        int wn = wave_sum(walked_nets), wm = wave_sum(walked_members);
-        if (lane == 0 && wn) {
-            atomicAdd(&prof[4 * (blockIdx.x & 63) + 0], (unsigned long long)wn);
-            atomicAdd(&prof[4 * (blockIdx.x & 63) + 1], (unsigned long long)wm);
-            atomicAdd(&prof[4 * (blockIdx.x & 63) + 3], (unsigned long long)wm);
+        if (prof) {
+            int wn = wave_sum(walked_nets), wm = wave_sum(walked_members);
+            if (lane == 0 && wn) {
+                atomicAdd(&prof[4 * (blockIdx.x & 63) + 0], (unsigned long long)wn);
+                atomicAdd(&prof[4 * (blockIdx.x & 63) + 1], (unsigned long long)wm);
+                atomicAdd(&prof[4 * (blockIdx.x & 63) + 3], (unsigned long long)wm);
+            }
         }
     }
 }
@@ -2094,11 +2182,16 @@ __global__ void k_conflict_vertex(Graph g, const int *W, Ctrl *ctrl, int par, co
 // wave queues its winners of a tile in LDS and walks their rows 64 winners at
 // a time as one flat range, so the row offsets and the rows are each one
 // round of loads).  Writes the number of uncolored entries of each tile.
+// With zf (first-fit vertex rounds with standing proposals): a winner of
+// color 0 proposed it because none of its nets held color 0 (and a net that
+// gains color 0 makes every member that still proposes 0 lose and propose
+// again), so each of its nets gains color 0 here for the first time, and
+// their members are marked in zf.
 template <bool D2>
 __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, Ctrl *ctrl, int par, int *st,
                                                       uint8_t *lose, uint64_t *mask0, int *tile_count,
                                                       RoundRec *rec, int round, int update_masks, uint64_t *hw,
-                                                      int PH, const int *lcnt)
+                                                      int PH, const int *lcnt, uint8_t *zf = nullptr)
 {
     constexpr int NWV = TILE_BLOCK / WAVE;
     constexpr int WQ = 2 * WAVE;   // winners queued per wave before their rows are walked
@@ -2106,9 +2199,47 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
     __shared__ int s_u[NWV][WQ];
     __shared__ int s_col[NWV][WQ];
     __shared__ int s_pre[NWV][64], s_beg[NWV][64];
+    constexpr int ZQ = 512;   // nets that gained color 0, queued per wave (zf)
+    __shared__ int s_z[NWV][ZQ];
+    __shared__ int s_zpre[NWV][64], s_zbeg[NWV][64];
     const int n = list ? ctrl->n_w[par] : g.n_a;
     const int ntiles = (n + TILE - 1) / TILE;
     const int lane = lane_id(), wid = threadIdx.x / WAVE;
+    // the members of the queued nets into zf, as one flat range per 64 nets
+    // (distance-2: the center too), eight stores in flight per lane
+    auto zflush = [&](int zn) {
+        for (int c0 = 0; c0 < zn; c0 += 64) {
+            const int j = c0 + lane;
+            int beg = 0, d = 0;
+            if (j < zn) {
+                const int v = s_z[wid][j];
+                beg = g.b_off[v];
+                d = g.b_off[v + 1] - beg;
+                if (D2) zf[v] = 1;
+            }
+            const int incl = wave_incl_scan(d);
+            const int total = __shfl(incl, 63);
+            s_zpre[wid][lane] = incl - d;
+            s_zbeg[wid][lane] = beg;
+            wave_sync();
+            for (int f0 = 0; f0 < total; f0 += 8 * WAVE) {
+                int x[8];
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    const int f = f0 + q * WAVE + lane;
+                    x[q] = -1;
+                    if (f < total) {
+                        const int r = row_of(s_zpre[wid], f);
+                        x[q] = g.b_idx[s_zbeg[wid][r] + f - s_zpre[wid][r]];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 8; q++)
+                    if (x[q] >= 0) zf[x[q]] = 1;
+            }
+            wave_sync();
+        }
+    };
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctrl->n_w[par ^ 1] = 0;
         ctrl->n_heavy = 0;
@@ -2117,6 +2248,7 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
     // pass, then the rows as one flat range, one color word update per entry
     // (mask0 for colors below 64, else the color's higher word)
     auto walk = [&](int qn) {
+        int zn = 0;
         for (int c0 = 0; c0 < qn; c0 += 64) {
             const int j = c0 + lane;
             int beg = 0, d = 0;
@@ -2143,15 +2275,37 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
                         cq[q] = s_col[wid][c0 + r];
                     }
                 }
+                bool gained[4];
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
+                    gained[q] = false;
                     if (tgt[q] < 0) continue;
                     const int c = cq[q];
                     uint64_t *wd = c < 64 ? &mask0[tgt[q]] : &hw[(long)tgt[q] * PH + (c >> 6) - 1];
                     atomicOr((unsigned long long *)wd, 1ull << (c & 63));
+                    // a first-fit proposal 0 means no net of the winner held
+                    // color 0: each of its nets gains color 0 now, once
+                    gained[q] = zf && c == 0;
+                }
+                if (zf) {
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const uint64_t bal = __ballot(gained[q]);
+                        if (gained[q]) s_z[wid][zn + __builtin_popcountll(bal & ((1ull << lane) - 1ull))] = tgt[q];
+                        zn += __builtin_popcountll(bal);
+                    }
+                    if (zn > ZQ - 4 * WAVE) {
+                        wave_sync();
+                        zflush(zn);
+                        zn = 0;
+                    }
                 }
             }
             wave_sync();
+        }
+        if (zn > 0) {
+            wave_sync();
+            zflush(zn);
         }
     };
     constexpr int KS = TILE / TILE_BLOCK;
@@ -2173,6 +2327,7 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
         for (int k = 0; k < KS; k++) {
             bool q64 = false;
             int col = 0;
+            int zq_self = -1;   // (distance-2, zf) u's own net gained color 0
             if (us[k] >= 0) {
                 int u = us[k];
                 int s = ss[k];
@@ -2196,10 +2351,20 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
                             if (D2) {   // the closed neighbourhood of u itself
                                 uint64_t *wd = col < 64 ? &mask0[u] : &hw[(long)u * PH + (col >> 6) - 1];
                                 atomicOr((unsigned long long *)wd, 1ull << (col & 63));
+                                if (zf && col == 0) zq_self = u;
                             }
                         }
                     }
                     mx = max(mx, col);
+                }
+            }
+            if (D2 && zf) {
+                const uint64_t zb = __ballot(zq_self >= 0);
+                if (zb) {
+                    // s_z is free between walks
+                    if (zq_self >= 0) s_z[wid][__builtin_popcountll(zb & ((1ull << lane) - 1ull))] = zq_self;
+                    wave_sync();
+                    zflush(__builtin_popcountll(zb));
                 }
             }
             if (update_masks) {
