@@ -326,6 +326,7 @@ int run(const RunArgs &a)
                    + aligned(n_a + 1, 4)              //   loss counts
                    + aligned(n_b + 1, 1)              //   dirty nets
                    + aligned(n_a + 1, 1)              //   vertices with a net holding color 0
+                   + aligned(n_a + 1, 4)              //   winners of color 0 of the round
                    + aligned(fr_a + 1, 4) * 3         // front lists, front flags
                    + aligned(fr_b + 1, 4) * 4;        //   dirty-net list, its stamps, two zero-net lists
     const bool noalloc = a.ext != nullptr;
@@ -371,6 +372,7 @@ int run(const RunArgs &a)
     int *sp_cnt = ar.take<int>(n_a + 1);
     uint8_t *sp_dirty = ar.take<uint8_t>(n_b + 1);
     uint8_t *zf = ar.take<uint8_t>(n_a + 1);
+    int *z0l = ar.take<int>(n_a + 1);
     int *FL[2] = {ar.take<int>(fr_a + 1), ar.take<int>(fr_a + 1)};
     int *infront = ar.take<int>(fr_a + 1);
     int *DL = ar.take<int>(fr_b + 1);
@@ -1001,8 +1003,9 @@ int run(const RunArgs &a)
                                                                  FL[par ^ 1], &ctrl->fl_n[par ^ 1]);
                 } else {
                     k_apply<D2><<<gt, TILE_BLOCK, 0, s>>>(g, Wc, ctrl, par, st, lose, mask0, tile_count, rec, rr, 1, hw,
-                                                          PH, spr ? sp_cnt : nullptr, zfr ? zf : nullptr);
-                    k_compact<<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 0, 1, host);
+                                                          PH, spr ? sp_cnt : nullptr, zfr ? zf : nullptr, z0l);
+                    k_compact<D2><<<gt, TILE_BLOCK, 0, s>>>(Wc, n_a, ctrl, par, st, tile_count, Wn, rec, rr, 0, 1, host,
+                                                            g, z0l, zfr ? zf : nullptr);
                     if (!zfr) zf_valid = false;
                 }
             }

@@ -75,6 +75,7 @@ struct Ctrl {
     int win;             // winners of the round so far
     unsigned done_blocks;   // blocks of the closing kernel that have finished
     int dl_n;            // nets listed for this round's removal
+    int z0n[2];          // winners of color 0 listed for the zf marking, by round parity
     int pad2[1];
 };
 

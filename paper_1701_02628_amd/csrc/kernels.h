@@ -130,6 +130,7 @@ __global__ void k_init_ctrl(Ctrl *c, int n_w, int max_color)
         c->dl_n = 0;
         c->win = 0;
         c->done_blocks = 0;
+        c->z0n[0] = c->z0n[1] = 0;
     }
 }
 
@@ -2182,16 +2183,14 @@ __global__ void k_conflict_vertex(Graph g, const int *W, Ctrl *ctrl, int par, co
 // wave queues its winners of a tile in LDS and walks their rows 64 winners at
 // a time as one flat range, so the row offsets and the rows are each one
 // round of loads).  Writes the number of uncolored entries of each tile.
-// With zf (first-fit vertex rounds with standing proposals): a winner of
-// color 0 proposed it because none of its nets held color 0 (and a net that
-// gains color 0 makes every member that still proposes 0 lose and propose
-// again), so each of its nets gains color 0 here for the first time, and
-// their members are marked in zf.
+// With zf (first-fit vertex rounds with standing proposals) the winners of
+// color 0 are listed in z0l for k_compact, which marks their neighbourhoods.
 template <bool D2>
 __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, Ctrl *ctrl, int par, int *st,
                                                       uint8_t *lose, uint64_t *mask0, int *tile_count,
                                                       RoundRec *rec, int round, int update_masks, uint64_t *hw,
-                                                      int PH, const int *lcnt, uint8_t *zf = nullptr)
+                                                      int PH, const int *lcnt, const uint8_t *zf = nullptr,
+                                                      int *z0l = nullptr)
 {
     constexpr int NWV = TILE_BLOCK / WAVE;
     constexpr int WQ = 2 * WAVE;   // winners queued per wave before their rows are walked
@@ -2199,56 +2198,18 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
     __shared__ int s_u[NWV][WQ];
     __shared__ int s_col[NWV][WQ];
     __shared__ int s_pre[NWV][64], s_beg[NWV][64];
-    constexpr int ZQ = 512;   // nets that gained color 0, queued per wave (zf)
-    __shared__ int s_z[NWV][ZQ];
-    __shared__ int s_zpre[NWV][64], s_zbeg[NWV][64];
     const int n = list ? ctrl->n_w[par] : g.n_a;
     const int ntiles = (n + TILE - 1) / TILE;
     const int lane = lane_id(), wid = threadIdx.x / WAVE;
-    // the members of the queued nets into zf, as one flat range per 64 nets
-    // (distance-2: the center too), eight stores in flight per lane
-    auto zflush = [&](int zn) {
-        for (int c0 = 0; c0 < zn; c0 += 64) {
-            const int j = c0 + lane;
-            int beg = 0, d = 0;
-            if (j < zn) {
-                const int v = s_z[wid][j];
-                beg = g.b_off[v];
-                d = g.b_off[v + 1] - beg;
-                if (D2) zf[v] = 1;
-            }
-            const int incl = wave_incl_scan(d);
-            const int total = __shfl(incl, 63);
-            s_zpre[wid][lane] = incl - d;
-            s_zbeg[wid][lane] = beg;
-            wave_sync();
-            for (int f0 = 0; f0 < total; f0 += 8 * WAVE) {
-                int x[8];
-#pragma unroll
-                for (int q = 0; q < 8; q++) {
-                    const int f = f0 + q * WAVE + lane;
-                    x[q] = -1;
-                    if (f < total) {
-                        const int r = row_of(s_zpre[wid], f);
-                        x[q] = g.b_idx[s_zbeg[wid][r] + f - s_zpre[wid][r]];
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < 8; q++)
-                    if (x[q] >= 0) zf[x[q]] = 1;
-            }
-            wave_sync();
-        }
-    };
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctrl->n_w[par ^ 1] = 0;
         ctrl->n_heavy = 0;
+        ctrl->z0n[par ^ 1] = 0;   // the next round's list of color-0 winners
     }
     // the queued winners' rows, 64 winners at a time: row offsets in one
     // pass, then the rows as one flat range, one color word update per entry
     // (mask0 for colors below 64, else the color's higher word)
     auto walk = [&](int qn) {
-        int zn = 0;
         for (int c0 = 0; c0 < qn; c0 += 64) {
             const int j = c0 + lane;
             int beg = 0, d = 0;
@@ -2275,37 +2236,15 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
                         cq[q] = s_col[wid][c0 + r];
                     }
                 }
-                bool gained[4];
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
-                    gained[q] = false;
                     if (tgt[q] < 0) continue;
                     const int c = cq[q];
                     uint64_t *wd = c < 64 ? &mask0[tgt[q]] : &hw[(long)tgt[q] * PH + (c >> 6) - 1];
                     atomicOr((unsigned long long *)wd, 1ull << (c & 63));
-                    // a first-fit proposal 0 means no net of the winner held
-                    // color 0: each of its nets gains color 0 now, once
-                    gained[q] = zf && c == 0;
-                }
-                if (zf) {
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        const uint64_t bal = __ballot(gained[q]);
-                        if (gained[q]) s_z[wid][zn + __builtin_popcountll(bal & ((1ull << lane) - 1ull))] = tgt[q];
-                        zn += __builtin_popcountll(bal);
-                    }
-                    if (zn > ZQ - 4 * WAVE) {
-                        wave_sync();
-                        zflush(zn);
-                        zn = 0;
-                    }
                 }
             }
             wave_sync();
-        }
-        if (zn > 0) {
-            wave_sync();
-            zflush(zn);
         }
     };
     constexpr int KS = TILE / TILE_BLOCK;
@@ -2327,7 +2266,7 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
         for (int k = 0; k < KS; k++) {
             bool q64 = false;
             int col = 0;
-            int zq_self = -1;   // (distance-2, zf) u's own net gained color 0
+            bool z0 = false;   // (zf) a winner of color 0
             if (us[k] >= 0) {
                 int u = us[k];
                 int s = ss[k];
@@ -2351,20 +2290,21 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_apply(Graph g, const int *list, 
                             if (D2) {   // the closed neighbourhood of u itself
                                 uint64_t *wd = col < 64 ? &mask0[u] : &hw[(long)u * PH + (col >> 6) - 1];
                                 atomicOr((unsigned long long *)wd, 1ull << (col & 63));
-                                if (zf && col == 0) zq_self = u;
                             }
                         }
                     }
                     mx = max(mx, col);
+                    z0 = zf && (s & TENT) && col == 0;
                 }
             }
-            if (D2 && zf) {
-                const uint64_t zb = __ballot(zq_self >= 0);
+            if (zf) {
+                // winners of color 0 onto the list k_compact marks from
+                const uint64_t zb = __ballot(z0);
                 if (zb) {
-                    // s_z is free between walks
-                    if (zq_self >= 0) s_z[wid][__builtin_popcountll(zb & ((1ull << lane) - 1ull))] = zq_self;
-                    wave_sync();
-                    zflush(__builtin_popcountll(zb));
+                    int zbase = 0;
+                    if (lane == 0) zbase = atomicAdd(&ctrl->z0n[par], __builtin_popcountll(zb));
+                    zbase = __shfl(zbase, 0);
+                    if (z0) z0l[zbase + __builtin_popcountll(zb & ((1ull << lane) - 1ull))] = us[k];
                 }
             }
             if (update_masks) {
@@ -2580,10 +2520,62 @@ __global__ void __launch_bounds__(256) k_front_push(Graph g, const int *zl, cons
 // ranked by wave ballots in index order.
 // With count_round, a round whose worklist was empty leaves everything as is;
 // otherwise the round is counted and its record completed.
+// zf (first-fit vertex rounds with standing proposals): a winner of color 0
+// proposed it because none of its nets held color 0 (a net that gains color
+// 0 makes every member still proposing 0 lose and propose again), so each of
+// its nets gains color 0 now, for the first time.  After the compaction,
+// every wave takes winners from z0l and marks the members of their nets
+// (distance-2: the centers too) in zf, one flat range per 64 nets.
+template <bool D2>
+__device__ void zero_front_mark(const Graph &g, const int *z0l, int nz, uint8_t *zf, int *s_pre, int *s_beg)
+{
+    const int lane = lane_id();
+    const int nwv = blockDim.x / WAVE, wv = blockIdx.x * nwv + threadIdx.x / WAVE;
+    for (int i = wv; i < nz; i += gridDim.x * nwv) {
+        const int u = z0l[i];
+        const int ab = g.a_off[u], ad = g.a_off[u + 1] - ab;
+        for (int c0 = 0; c0 < ad + (D2 ? 1 : 0); c0 += WAVE) {
+            // nets c0 .. c0 + 63 of u (distance-2: u's own net last)
+            const int j = c0 + lane;
+            int v = -1, beg = 0, d = 0;
+            if (j < ad) v = g.a_idx[ab + j];
+            else if (D2 && j == ad) v = u;
+            if (v >= 0) {
+                beg = g.b_off[v];
+                d = g.b_off[v + 1] - beg;
+                if (D2) zf[v] = 1;
+            }
+            const int incl = wave_incl_scan(d);
+            const int total = __shfl(incl, WAVE - 1);
+            s_pre[lane] = incl - d;
+            s_beg[lane] = beg;
+            wave_sync();
+            for (int f0 = 0; f0 < total; f0 += 8 * WAVE) {
+                int x[8];
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    const int f = f0 + q * WAVE + lane;
+                    x[q] = -1;
+                    if (f < total) {
+                        const int r = row_of(s_pre, f);
+                        x[q] = g.b_idx[s_beg[r] + f - s_pre[r]];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 8; q++)
+                    if (x[q] >= 0) zf[x[q]] = 1;
+            }
+            wave_sync();
+        }
+    }
+}
+
+template <bool D2 = false>
 __global__ void __launch_bounds__(TILE_BLOCK) k_compact(const int *list, int n_static, Ctrl *ctrl, int par,
                                                         const int *st, const int *tile_count, int *out,
                                                         RoundRec *rec, int round, int mode, int count_round,
-                                                        int *host)
+                                                        int *host, Graph g = Graph{}, const int *z0l = nullptr,
+                                                        uint8_t *zf = nullptr)
 {
     constexpr int KS = TILE / TILE_BLOCK;
     constexpr int NWV = TILE_BLOCK / WAVE;
@@ -2648,6 +2640,11 @@ __global__ void __launch_bounds__(TILE_BLOCK) k_compact(const int *list, int n_s
             }
         }
         __syncthreads();
+    }
+    if (zf) {
+        __shared__ int s_zp[TILE_BLOCK / WAVE][WAVE], s_zb[TILE_BLOCK / WAVE][WAVE];
+        const int wid = threadIdx.x / WAVE;
+        zero_front_mark<D2>(g, z0l, ctrl->z0n[par], zf, s_zp[wid], s_zb[wid]);
     }
 }
 
