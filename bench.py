@@ -76,6 +76,16 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the coloring of one graph "
               "is not sharded across GPUs in this build", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch4096" and int(os.environ.get("GPU_MAX_HW_QUEUES") or 4) < 16:
+        # the serving session keeps persistent kernels on some streams while
+        # uploads and whole-device calls run on others; kernels on one
+        # hardware queue run in order, so with HIP's default of 4 queues
+        # those streams would wait for the serving kernels.  The HIP runtime
+        # reads the queue count when it loads: run in a child process with 16
+        # (nothing here has touched the device yet).
+        import subprocess
+        env = dict(os.environ, GPU_MAX_HW_QUEUES="16")
+        sys.exit(subprocess.call([sys.executable] + sys.argv, env=env))
     import numpy as np
     import torch
 

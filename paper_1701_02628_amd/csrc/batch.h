@@ -665,8 +665,8 @@ struct ServeRing {
 // by DMA after this kernel started, possibly into memory an earlier request
 // used), copies the descriptor to LDS and runs the graph; the graph's
 // completion reaches the host through its done word.  A workgroup leaves
-// after idle_spins empty polls (about 20 ms) or when stop is set, so every
-// wave exits.  Workgroups count themselves in `active` and publish the
+// after idle_spins empty polls (about 14 us apart) or when stop is set, so
+// every wave exits.  Workgroups count themselves in `active` and publish the
 // claims in `claimed`, so the host can launch more workgroups (another launch
 // of this kernel, on another stream) while published requests wait
 // unclaimed behind the few workgroups still busy with long graphs.
@@ -691,8 +691,15 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_serve(ServeRing *ring, int cap,
                     spin = 0;   // another workgroup took it: not idle
                     continue;
                 }
-                if (__hip_atomic_load(&ring->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
-                __builtin_amdgcn_s_sleep(64);
+                if ((spin & 15) == 15 && __hip_atomic_load(&ring->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))
+                    break;
+                // about 14 us between polls of host memory: hundreds of idle
+                // workgroups polling faster load the path that the uploads
+                // and the done words take
+                __builtin_amdgcn_s_sleep(127);
+                __builtin_amdgcn_s_sleep(127);
+                __builtin_amdgcn_s_sleep(127);
+                __builtin_amdgcn_s_sleep(127);
             }
             if (k >= 0) __threadfence_system();
             s_k = k;

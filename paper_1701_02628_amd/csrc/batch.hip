@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -46,6 +47,10 @@ hipStream_t side_stream(int i)
     }
     return streams[dev][i];
 }
+
+// Serving: graphs of at least this many memberships take an idle
+// whole-device thread when one is free (see bgpc_session::loop).
+constexpr long long LIGHT_LOAD_NNZ = 50000;
 
 // Graphs that one workgroup would color far slower than the whole device:
 // many nets to rescan every round and colors past the net masks, or simply
@@ -499,7 +504,8 @@ struct bgpc_session {
     RangeAlloc *alloc = nullptr;
     std::vector<hipStream_t> streams;   // uploads
     std::vector<hipEvent_t> events;     // free upload events
-    static constexpr int KSTREAMS = 3;  // serving-kernel launches that may run at once
+    static constexpr int KSTREAMS = 6;  // most serving-kernel launches that may run at once
+    int nk = 1;                         // launches allowed at once (from the hardware queues)
     hipStream_t kstream[KSTREAMS] = {}; // one per launch in flight
     hipEvent_t kdone[KSTREAMS] = {};    // recorded after each launch
     bool klaunched[KSTREAMS] = {};
@@ -517,7 +523,8 @@ struct bgpc_session {
     std::condition_variable cv_work, cv_done, cv_dev;
     std::deque<Req *> submitted;    // guarded by mu
     std::vector<Req *> completed;   // guarded by mu
-    std::deque<Req *> dev_queue;    // guarded by mu
+    std::deque<Req *> dev_queue;    // guarded by mu: graphs that need the whole device
+    std::deque<Req *> dev_light;    // guarded by mu: graphs sent to idle whole-device threads under light load
     std::deque<Req *> pending;      // worker only: waiting for admission
     std::deque<std::pair<Req *, hipEvent_t>> uploading;   // worker only: arrays on their way
     std::vector<Req *> running;     // worker only: published, done word not yet seen
@@ -526,6 +533,7 @@ struct bgpc_session {
     bool stop = false;              // guarded by mu
     bool kernels_stopped = false;   // worker only: after an error, the serving kernels have left
     bool dev_stop = false;          // guarded by mu: set once the worker has handed over every request
+    int dev_busy = 0;               // guarded by mu: whole-device threads running a request
     int error = 0;
 
     bool upload(Req *q);
@@ -651,7 +659,15 @@ void bgpc_session::loop()
             while (!submitted.empty()) {
                 Req *q = submitted.front();
                 submitted.pop_front();
-                if (q->device) {
+                // light load: a graph that one workgroup of the serving
+                // kernel would color slowly takes an idle whole-device
+                // thread instead (same colors, far lower latency); under
+                // load those threads stay busy and graphs go to the kernel
+                if (!q->device && q->mode != MODE_DENSE && q->r.nnz >= LIGHT_LOAD_NNZ &&
+                    dev_busy + (int)(dev_queue.size() + dev_light.size()) < (int)dev_streams.size()) {
+                    dev_light.push_back(q);
+                    cv_dev.notify_one();
+                } else if (q->device) {
                     dev_queue.push_back(q);
                     cv_dev.notify_one();
                 } else {
@@ -664,7 +680,7 @@ void bgpc_session::loop()
             // a failed call: nothing more is published, and no workgroup may
             // still read a request's arrays when its pool range is released
             __atomic_store_n(&ring->stop, 1, __ATOMIC_RELEASE);
-            for (int k = 0; k < KSTREAMS; k++)
+            for (int k = 0; k < nk; k++)
                 if (klaunched[k]) (void)hipEventSynchronize(kdone[k]);
             for (auto &u : uploading) (void)hipEventSynchronize(u.second);
             kernels_stopped = true;
@@ -705,7 +721,7 @@ void bgpc_session::loop()
         // millisecond
         if (!running.empty() && !error) {
             int in_flight = 0, free_k = -1;
-            for (int k = 0; k < KSTREAMS; k++) {
+            for (int k = 0; k < nk; k++) {
                 bool alive = false;
                 if (klaunched[k]) {
                     hipError_t e = hipEventQuery(kdone[k]);
@@ -721,8 +737,12 @@ void bgpc_session::loop()
             const bool starved = tail > claimed && active < cus &&
                                  std::chrono::steady_clock::now() - klast > std::chrono::milliseconds(1);
             if (free_k >= 0 && !error && (in_flight == 0 || starved)) {
-                // about 20 ms of empty polls before a workgroup leaves
-                k_serve<<<std::max(1, cus * 2), BATCH_BLOCK, 0, kstream[free_k]>>>(ring_dev, cap, head, 12000);
+                // about 20 ms of empty polls (1,500 polls 14 us apart) before a workgroup leaves; an
+                // extra launch brings only as many workgroups as requests
+                // wait, so that idle polling does not crowd the device
+                const int grid = in_flight == 0 ? std::max(1, cus * 2)
+                                                : std::max(8, std::min(cus * 2, tail - claimed));
+                k_serve<<<grid, BATCH_BLOCK, 0, kstream[free_k]>>>(ring_dev, cap, head, 1500);
                 if (hipGetLastError() != hipSuccess || hipEventRecord(kdone[free_k], kstream[free_k]) != hipSuccess)
                     error = BGPC_E_HIP;
                 klaunched[free_k] = true;
@@ -802,19 +822,23 @@ void bgpc_session::dev_loop(int t)
         Req *q = nullptr;
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv_dev.wait(lk, [&] { return dev_stop || !dev_queue.empty(); });
-            if (dev_queue.empty()) {   // dev_stop and nothing left
+            cv_dev.wait(lk, [&] { return dev_stop || !dev_queue.empty() || !dev_light.empty(); });
+            if (dev_queue.empty() && dev_light.empty()) {   // dev_stop and nothing left
                 lk.unlock();
                 release_thread_state();
                 break;
             }
-            q = dev_queue.front();
-            dev_queue.pop_front();
+            // graphs that need the whole device first
+            std::deque<Req *> &from = dev_queue.empty() ? dev_light : dev_queue;
+            q = from.front();
+            from.pop_front();
+            dev_busy++;
         }
         q->t_admit = now_s();
         dev_run(q, dev_streams[t]);
         {
             std::lock_guard<std::mutex> lk(mu);
+            dev_busy--;
             completed.push_back(q);
         }
         cv_done.notify_all();
@@ -846,7 +870,16 @@ BGPC_API bgpc_session *bgpc_session_create(size_t mem_budget, int32_t max_slots,
         ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
         if (ok) S->dev_streams.push_back(st);
     }
-    for (int k = 0; k < bgpc_session::KSTREAMS; k++) {
+    // kernels on one hardware queue run in order: a second serving launch
+    // only helps when its stream can have a queue of its own (HIP gives a
+    // process GPU_MAX_HW_QUEUES queues, 4 unless set; the session's upload,
+    // whole-device and kernel streams then share them)
+    {
+        const char *e = std::getenv("GPU_MAX_HW_QUEUES");
+        const int hwq = e ? std::atoi(e) : 4;
+        S->nk = hwq >= 16 ? bgpc_session::KSTREAMS : 1;
+    }
+    for (int k = 0; k < S->nk; k++) {
         ok = ok && hipStreamCreateWithFlags(&S->kstream[k], hipStreamNonBlocking) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&S->kdone[k], hipEventDisableTiming) == hipSuccess;
     }
@@ -945,7 +978,7 @@ BGPC_API void bgpc_session_destroy(bgpc_session *S)
     if (S->worker.joinable()) S->worker.join();
     // every request is done: the serving kernel's workgroups leave
     __atomic_store_n(&S->ring->stop, 1, __ATOMIC_RELEASE);
-    for (int k = 0; k < bgpc_session::KSTREAMS; k++) (void)hipStreamSynchronize(S->kstream[k]);
+    for (int k = 0; k < S->nk; k++) (void)hipStreamSynchronize(S->kstream[k]);
     {
         std::lock_guard<std::mutex> lk(S->mu);
         S->dev_stop = true;
@@ -961,7 +994,7 @@ BGPC_API void bgpc_session_destroy(bgpc_session *S)
         (void)hipStreamSynchronize(st);
         (void)hipStreamDestroy(st);
     }
-    for (int k = 0; k < bgpc_session::KSTREAMS; k++) {
+    for (int k = 0; k < S->nk; k++) {
         (void)hipStreamDestroy(S->kstream[k]);
         (void)hipEventDestroy(S->kdone[k]);
     }
