@@ -403,6 +403,8 @@ int run(const RunArgs &a)
     // allocation)
     int *ell = nullptr;
     int ell_w = 0;
+    // pending lists of the nets above SMALL_NET (standing proposals)
+    int *pend_l = nullptr, *pend_n = nullptr;
     long mc_ub = -1;   // upper bound of every color present before the next round
     // (decided from the graph's shape below)
     bool planes_ok = !(o.flags & BGPC_INCREMENTAL) && !noalloc;   // the words are allocated as colors grow
@@ -431,8 +433,8 @@ int run(const RunArgs &a)
     std::vector<hipEvent_t> round_ev;
     const bool time_rounds = o.log && o.log->cap > 0 && o.log->round_ms;
     bool sp_reset = true, sp_used = false;
-    const SPState sp_none = {nullptr, nullptr, nullptr};
-    const SPState sp_state = {sp_bits, sp_cnt, sp_dirty};
+    const SPState sp_none = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    SPState sp_state = {sp_bits, sp_cnt, sp_dirty, nullptr, nullptr};   // pending lists added below
     auto ensure_planes = [&](long bound) {
         const long need = bound < 64 ? 0 : (bound >> 6);
         if (need <= PH || PH >= max_PH) return;
@@ -549,8 +551,18 @@ int run(const RunArgs &a)
                 ell = nullptr;
                 ell_w = 0;
             } else {
-                k_build_ell<<<grid_for((long)ell_w * n_b, nthr, di.cus * 16), nthr, 0, s>>>(g, ell_w, ell);
+                k_build_ell<<<grid_for(n_b, ELL_BLOCK, di.cus * 8), ELL_BLOCK, 0, s>>>(g, ell_w, ell);
             }
+        }
+        if (sp_on && !noalloc && n_big > 0) {
+            if (hipMallocAsync((void **)&pend_l, (size_t)(a.nnz + (D2 ? n_b : 0) + 1) * 4, s) != hipSuccess ||
+                hipMallocAsync((void **)&pend_n, ((size_t)n_b + 1) * 4, s) != hipSuccess) {
+                (void)hipGetLastError();
+                if (pend_l) (void)hipFreeAsync(pend_l, s);
+                pend_l = pend_n = nullptr;
+            }
+            sp_state.pl = pend_l;
+            sp_state.pn = pend_n;
         }
         // distance-2 degree bound: most nets of a vertex x largest net
         const long two_hop = std::min<long>((long)h_shape[2] * (long)max_net, 1L << 30);
@@ -811,6 +823,7 @@ int run(const RunArgs &a)
                                                                                            (long)sp_words * 2);
                 k_fill_i32<<<g_a, nthr, 0, s>>>(sp_cnt, 0, n_a + 1);
                 k_fill_u8<<<g_b, nthr, 0, s>>>(sp_dirty, 1, n_b + 1);
+                if (pend_l) k_pending_init<D2><<<g_big, 256, 0, s>>>(g, big, &shape[1], pend_l, pend_n);
                 sp_reset = false;
             }
             const bool spr = !net_mode && r < inc_start && sp_on;   // this round keeps standing proposals
@@ -979,7 +992,7 @@ int run(const RunArgs &a)
                     if (front)
                         LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_list<D2><<<g_list, LIST_BLOCK, 0, s>>>(g, st, done_net, sp_state, DL, &ctrl->dl_n, PCNT(r))));
                     else if (spr && ell)
-                        LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2, true, true><<<g_sp, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), sp_state, ell, ell_w)));
+                        LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2, true, !D2><<<g_sp, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), sp_state, ell, ell_w)));
                     else if (spr)
                         LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2, true><<<g_sp, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), sp_state)));
                     else
@@ -1112,7 +1125,8 @@ finish:
     for (hipEvent_t e : round_ev) (void)hipEventDestroy(e);
     if (h_states) (void)hipHostFree(h_states);
     if (hw) (void)hipFreeAsync(hw, s);
-    for (void *p : {(void *)hv_id, (void *)hv_list, (void *)hv_slices, (void *)hv_counts, (void *)hv_F, (void *)ell})
+    for (void *p : {(void *)hv_id, (void *)hv_list, (void *)hv_slices, (void *)hv_counts, (void *)hv_F, (void *)ell,
+                    (void *)pend_l, (void *)pend_n})
         if (p) (void)hipFreeAsync(p, s);
     ar.release();
     if (!ar.async) (void)hipGetLastError();

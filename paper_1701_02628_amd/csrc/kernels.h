@@ -1551,6 +1551,12 @@ struct SPState {
     unsigned long long *lbits;   // bit of position p of net v at lpos(v) + p
     int *lcnt;
     uint8_t *dirty;
+    // nets above SMALL_NET (optional): the positions of the members still
+    // uncolored or proposing, at lpos(v) .. lpos(v) + pn[v] - 1, in any
+    // order.  A member colored in a vertex-based round stays colored, so
+    // each scan keeps only the pending ones and later scans read fewer.
+    int *pl;
+    int *pn;
 };
 
 // first position of net v in lbits (distance-2 nets hold one more member)
@@ -1588,13 +1594,45 @@ struct EllSrc {
     }
 };
 
-// thread per net: its row read in order, the column written across threads
-__global__ void k_build_ell(Graph g, int w, int *ell)
+// a wave per 64 nets: their first w members gathered net by net into LDS
+// (neighbouring lanes read neighbouring members), then written position by
+// position (neighbouring lanes write neighbouring nets)
+constexpr int ELL_BLOCK = 256;
+__global__ void __launch_bounds__(ELL_BLOCK) k_build_ell(Graph g, int w, int *ell)
 {
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n_b; v += gridDim.x * blockDim.x) {
-        const int b = g.b_off[v], d = g.b_off[v + 1] - b;
-        int *col = ell + v;
-        for (int p = 0; p < w; p++) col[p * g.n_b] = p < d ? g.b_idx[b + p] : -1;
+    constexpr int NW = ELL_BLOCK / WAVE;
+    __shared__ int s_t[NW][WAVE * ELL_W];
+    __shared__ int s_b[NW][WAVE], s_d[NW][WAVE];
+    const int wid = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    for (int v0 = (blockIdx.x * NW + wid) * WAVE; v0 < g.n_b; v0 += gridDim.x * NW * WAVE) {
+        const int v = v0 + lane;
+        int b = 0, d = 0;
+        if (v < g.n_b) {
+            b = g.b_off[v];
+            d = min(g.b_off[v + 1] - b, w);
+        }
+        s_b[wid][lane] = b;
+        s_d[wid][lane] = d;
+        wave_sync();
+        for (int f0 = 0; f0 < WAVE * w; f0 += 8 * WAVE) {
+            int x[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int f = f0 + q * WAVE + lane;
+                const bool in = f < WAVE * w;
+                const int j = in ? f / w : 0, p = f - j * w;
+                x[q] = (in && p < s_d[wid][j]) ? g.b_idx[s_b[wid][j] + p] : -1;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int f = f0 + q * WAVE + lane;
+                if (f < WAVE * w) s_t[wid][f] = x[q];
+            }
+        }
+        wave_sync();
+        if (v < g.n_b)
+            for (int p = 0; p < w; p++) ell[p * g.n_b + v] = s_t[wid][lane * w + p];
+        wave_sync();
     }
 }
 
@@ -1709,6 +1747,7 @@ __device__ __forceinline__ int scan_net(int v, int b, int e, Src src, int rel, c
 // flight), queues the dirty nets with their offsets in LDS and scans them 64
 // at a time, one net per lane, members read straight from the net lists.
 constexpr int SP_PF = 4;
+constexpr int SP_Q = 64 * SP_PF + 64;   // queue entries: the rest of a drain plus SP_PF stretches
 template <bool D2, bool ELLS>
 __device__ void conflict_dirty(const Graph &g, const int *st, uint8_t *done, const SPState &sp, int lb, int nb,
                                int *qv, int *qb, int *qe, int &walked_nets, int &scanned_members, const int *ell,
@@ -1716,10 +1755,11 @@ __device__ void conflict_dirty(const Graph &g, const int *st, uint8_t *done, con
 {
     const int lane = threadIdx.x, stride = nb * 64;
     int qn = 0;
-    auto drain = [&](int cnt) {
-        const int v = lane < cnt ? qv[lane] : -1;
+    // scans queue entries off .. off + cnt - 1, one net per lane
+    auto drain = [&](int off, int cnt) {
+        const int v = lane < cnt ? qv[off + lane] : -1;
         if (v >= 0) {
-            const int b = qb[lane], e = qe[lane];
+            const int b = qb[off + lane], e = qe[off + lane];
             const int sz = e - b + (D2 ? 1 : 0);
             if (sz >= 2 && sz <= SMALL_NET) {
                 const long lpos = (long)b + (D2 ? v : 0);
@@ -1735,23 +1775,6 @@ __device__ void conflict_dirty(const Graph &g, const int *st, uint8_t *done, con
             }
             if (sz <= SMALL_NET) sp.dirty[v] = 0;   // larger nets: k_conflict_big
         }
-        __syncthreads();
-        // move the rest of the queue to its front
-        const int rest = qn - cnt;
-        int kv = 0, kb = 0, ke = 0;
-        if (lane < rest) {
-            kv = qv[cnt + lane];
-            kb = qb[cnt + lane];
-            ke = qe[cnt + lane];
-        }
-        __syncthreads();
-        if (lane < rest) {
-            qv[lane] = kv;
-            qb[lane] = kb;
-            qe[lane] = ke;
-        }
-        qn = rest;
-        __syncthreads();
     };
     for (int base0 = lb * 64; base0 < g.n_b; base0 += SP_PF * stride) {
         uint8_t fd[SP_PF], fn[SP_PF];
@@ -1765,23 +1788,40 @@ __device__ void conflict_dirty(const Graph &g, const int *st, uint8_t *done, con
             ob[k] = in ? g.b_off[v] : 0;
             oe[k] = in ? g.b_off[v + 1] : 0;
         }
+        // the dirty nets of the SP_PF stretches onto the queue (qn < 64 here)
 #pragma unroll
         for (int k = 0; k < SP_PF; k++) {
-            const int v = base0 + k * stride + lane;
             const bool d = fd[k] && !fn[k];
             const uint64_t bal = __ballot(d);
             if (d) {
                 const int r = qn + __builtin_popcountll(bal & ((1ull << lane) - 1ull));
-                qv[r] = v;
+                qv[r] = base0 + k * stride + lane;
                 qb[r] = ob[k];
                 qe[r] = oe[k];
             }
             qn += __builtin_popcountll(bal);
-            __syncthreads();
-            if (qn >= 64) drain(64);
         }
+        __syncthreads();
+        int qs = 0;
+        for (; qn - qs >= 64; qs += 64) drain(qs, 64);
+        // the rest (fewer than 64) to the front of the queue
+        const int rest = qn - qs;
+        int kv = 0, kb = 0, ke = 0;
+        if (lane < rest) {
+            kv = qv[qs + lane];
+            kb = qb[qs + lane];
+            ke = qe[qs + lane];
+        }
+        __syncthreads();
+        if (lane < rest) {
+            qv[lane] = kv;
+            qb[lane] = kb;
+            qe[lane] = ke;
+        }
+        qn = rest;
+        __syncthreads();
     }
-    if (qn > 0) drain(qn);
+    if (qn > 0) drain(0, qn);
 }
 
 template <bool D2, bool SP = false, bool ELLS = false>
@@ -1794,7 +1834,7 @@ __global__ void __launch_bounds__(64) k_conflict_small(Graph g, const int *st, u
     const int stride = nb * 64;
     if constexpr (SP) {
         // the round's nets are counted by k_census (profiling only)
-        __shared__ int q[3][128];
+        __shared__ int q[3][SP_Q];
         int scanned = 0;
         conflict_dirty<D2, ELLS>(g, st, done, sp, lb, nb, q[0], q[1], q[2], walked_nets, scanned, ell, ell_w);
         if (prof) {
@@ -1944,36 +1984,58 @@ static_assert(3 * BIG_LIST + 2 * (2 * BIG_LIST) <= WIN_COLORS && (BIG_LIST & (BI
 template <bool D2>
 __device__ void conflict_large(const Graph &g, const int *st, uint8_t *lose, uint8_t *done, int v, int sz, long lpos,
                                int tent_only, const SPState &sp, int *sh, int list_cap, int maxc, int *s_scan,
-                               int *s_cnt)
+                               int *s_cnt, int *s_keep)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     int *lst = sh;                      // (position, member, color) per proposal
     int *hsh = sh + 3 * list_cap;       // hash of the listed proposals
-    if (tid == 0) *s_cnt = 0;
+    const bool plm = sp.pl != nullptr && tent_only;
+    const int np = plm ? sp.pn[v] : sz;
+    if (tid == 0) {
+        *s_cnt = 0;
+        *s_keep = 0;
+    }
     __syncthreads();
     int pending = 0;
-    for (int k0 = tid; k0 < sz; k0 += 4 * nt) {
-        int xs[4], ss[4];
-#pragma unroll
-        for (int i = 0; i < 4; i++) xs[i] = k0 + i * nt < sz ? Acc<D2>::member(g, v, k0 + i * nt) : -1;
-#pragma unroll
-        for (int i = 0; i < 4; i++) ss[i] = xs[i] >= 0 ? st[xs[i]] : 0;
+    for (int base = 0; base < np; base += 4 * nt) {
+        int ps[4], xs[4], ss[4];
 #pragma unroll
         for (int i = 0; i < 4; i++) {
+            const int k = base + tid + i * nt;
+            ps[i] = k < np ? (plm ? sp.pl[lpos + k] : k) : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++) xs[i] = ps[i] >= 0 ? Acc<D2>::member(g, v, ps[i]) : -1;
+#pragma unroll
+        for (int i = 0; i < 4; i++) ss[i] = xs[i] >= 0 ? st[xs[i]] : 0;
+        bool keep[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            keep[i] = false;
             if (xs[i] < 0) continue;
             const int s = ss[i];
-            pending += (s < 0 || (s & TENT)) ? 1 : 0;
+            keep[i] = s < 0 || (s & TENT);
+            pending += keep[i] ? 1 : 0;
             if (tent_only && s >= 0 && (s & TENT)) {
                 const int q = atomicAdd(s_cnt, 1);
                 if (q < list_cap) {
-                    lst[3 * q] = k0 + i * nt;
+                    lst[3 * q] = ps[i];
                     lst[3 * q + 1] = xs[i];
                     lst[3 * q + 2] = cur_color(s);
                 }
             }
         }
+        if (plm) {
+            // this stretch read by every thread: its pending positions go to
+            // the front of the list (never past entries not yet read)
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+                if (keep[i]) sp.pl[lpos + atomicAdd(s_keep, 1)] = ps[i];
+        }
     }
     pending = block_sum(pending, s_scan);
+    if (plm && tid == 0) sp.pn[v] = pending;
     if (sp.lbits && tid == 0) sp.dirty[v] = 0;
     if (pending == 0) {
         if (tid == 0) done[v] = 1;
@@ -2037,83 +2099,187 @@ __device__ void conflict_large(const Graph &g, const int *st, uint8_t *lose, uin
     }
 }
 
+// A net whose pending members fit one wave (pending lists, vertex-based
+// rounds): lane l takes the l-th listed position; a proposer loses iff a
+// proposer of lower rank in the net proposes the same color (compared lane
+// by lane through shuffles).  The list keeps the pending positions.
+template <bool D2>
+__device__ void wave_pending_net(const Graph &g, const int *st, uint8_t *done, const SPState &sp, int v, long lpos,
+                                 int np)
+{
+    const int lane = lane_id();
+    int p = -1, x = 0x7fffffff, s = -1;
+    if (lane < np) {
+        p = sp.pl[lpos + lane];
+        x = Acc<D2>::member(g, v, p);
+        s = st[x];
+    }
+    const bool keep = lane < np && (s < 0 || (s & TENT));
+    const bool prop = lane < np && s >= 0 && (s & TENT);
+    const int c = prop ? cur_color(s) : -1;
+    bool lost = false;
+    for (uint64_t b = __ballot(prop); b; b &= b - 1) {
+        const int j = __builtin_ctzll(b);
+        const int cj = __shfl(c, j), xj = __shfl(x, j);
+        if (prop && cj == c && xj < x) lost = true;
+    }
+    if (prop) sp_set(sp, lpos + p, x, lost);
+    const uint64_t kb = __ballot(keep);
+    if (keep) sp.pl[lpos + __builtin_popcountll(kb & ((1ull << lane) - 1ull))] = p;
+    if (lane == 0) {
+        sp.pn[v] = __builtin_popcountll(kb);
+        if (!kb) done[v] = 1;
+        sp.dirty[v] = 0;
+    }
+}
+
+// pending lists of the nets above SMALL_NET: every position (standing
+// proposals start, or restart after a net-based round)
+template <bool D2>
+__global__ void k_pending_init(Graph g, const int *big, const int *n_big_p, int *pl, int *pn)
+{
+    const int n_big = *n_big_p;
+    for (int bi = blockIdx.x; bi < n_big; bi += gridDim.x) {
+        const int v = big[bi];
+        const int sz = Acc<D2>::size(g, v);
+        const long lpos = sp_lpos<D2>(g, v);
+        for (int k = threadIdx.x; k < sz; k += blockDim.x) pl[lpos + k] = k;
+        if (threadIdx.x == 0) pn[v] = sz;
+    }
+}
+
 template <bool D2>
 __global__ void __launch_bounds__(BIG_BLOCK) k_conflict_big(Graph g, const int *st, uint8_t *lose, uint8_t *done,
                                                             const int *big, const int *n_big_p, Ctrl *ctrl,
                                                             int tent_only, SPState sp, int huge_elsewhere)
 {
     extern __shared__ int sh[];
-    __shared__ int s_scan[20], s_cnt;
+    __shared__ int s_scan[20], s_cnt, s_keep;
+    constexpr int BIG_CHUNK = 64;
+    __shared__ int s_list[BIG_CHUNK], s_ln;
     const int n_big = *n_big_p;
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (int bi = blockIdx.x; bi < n_big; bi += gridDim.x) {
-        int v = big[bi];
-        if (done[v] || (sp.lbits && !sp.dirty[v])) continue;
-        const long lpos = sp.lbits ? sp_lpos<D2>(g, v) : 0;
-        int sz = Acc<D2>::size(g, v);
-        if (sz <= HASH_MAX) {
-            // members and states read once into registers (the block holds
-            // BIG_PER_THREAD per thread), all loads of a batch in flight
-            int xs[BIG_PER_THREAD], ss[BIG_PER_THREAD];
-#pragma unroll
-            for (int i = 0; i < BIG_PER_THREAD; i++) {
-                const int k = tid + i * BIG_BLOCK;
-                xs[i] = k < sz ? Acc<D2>::member(g, v, k) : -1;
-            }
-            int pending = 0;
-#pragma unroll
-            for (int i = 0; i < BIG_PER_THREAD; i++) {
-                ss[i] = xs[i] >= 0 ? st[xs[i]] : 0;
-                pending += (xs[i] >= 0 && (ss[i] < 0 || (ss[i] & TENT))) ? 1 : 0;
-            }
-            pending = block_sum(pending, s_scan);
-            if (sp.lbits && tid == 0) sp.dirty[v] = 0;
-            if (pending == 0) {
-                if (tid == 0) done[v] = 1;
-                continue;
-            }
-            int cap = 64;
-            while (cap < 2 * sz) cap <<= 1;
-            int *keys = sh, *minr = sh + cap;
-            for (int i = tid; i < cap; i += nt) {
-                keys[i] = -1;
-                minr[i] = 0x7fffffff;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < BIG_PER_THREAD; i++) {
-                const int x = xs[i], s = ss[i];
-                if (x < 0 || (tent_only && !(s >= 0 && (s & TENT)))) continue;
-                const int c = cur_color(s);
-                if (c < 0) continue;
-                unsigned h = hash_color(c) & (cap - 1);
-                for (;;) {
-                    int prev = atomicCAS(&keys[h], -1, c);
-                    if (prev == -1 || prev == c) {
-                        atomicMin(&minr[h], x);
-                        break;
-                    }
-                    h = (h + 1) & (cap - 1);
+    // BIG_CHUNK nets at a time: a thread per net checks its flags, the nets
+    // to scan are listed in LDS, then the block scans them one by one
+    for (int base = blockIdx.x * BIG_CHUNK; base < n_big; base += gridDim.x * BIG_CHUNK) {
+        if (tid == 0) s_ln = 0;
+        __syncthreads();
+        if (tid < BIG_CHUNK && base + tid < n_big) {
+            const int v = big[base + tid];
+            if (!done[v] && !(sp.lbits && !sp.dirty[v])) s_list[atomicAdd(&s_ln, 1)] = v;
+        }
+        __syncthreads();
+        const int ln = s_ln;
+        if (sp.pl && tent_only) {
+            // nets with at most 64 pending members: a wave each, no barriers
+            const int wid = tid / WAVE;
+            for (int li = wid; li < ln; li += BIG_BLOCK / WAVE) {
+                const int v = s_list[li];
+                const int np = sp.pn[v];
+                if (np <= WAVE && !(huge_elsewhere && Acc<D2>::size(g, v) > HASH_MAX)) {
+                    wave_pending_net<D2>(g, st, done, sp, v, sp_lpos<D2>(g, v), np);
+                    if (lane_id() == 0) s_list[li] = -1;
                 }
             }
             __syncthreads();
-#pragma unroll
-            for (int i = 0; i < BIG_PER_THREAD; i++) {
-                const int x = xs[i], s = ss[i];
-                if (x < 0 || (tent_only && !(s >= 0 && (s & TENT)))) continue;
-                const int c = cur_color(s);
-                if (c < 0) continue;
-                unsigned h = hash_color(c) & (cap - 1);
-                while (keys[h] != c) h = (h + 1) & (cap - 1);
-                if (sp.lbits) sp_set(sp, lpos + tid + i * BIG_BLOCK, x, minr[h] != x);
-                else if (minr[h] != x) lose[x] = 1;
-            }
-            __syncthreads();
-            continue;
         }
-        if (huge_elsewhere && sz > HASH_MAX) continue;   // k_conflict_huge
-        conflict_large<D2>(g, st, lose, done, v, sz, lpos, tent_only, sp, sh, BIG_LIST, ctrl->max_color, s_scan,
-                           &s_cnt);
+        for (int li = 0; li < ln; li++) {
+            const int v = s_list[li];
+            if (v < 0) continue;
+            const long lpos = sp.lbits ? sp_lpos<D2>(g, v) : 0;
+            int sz = Acc<D2>::size(g, v);
+            if (sz <= HASH_MAX) {
+                // members and states read once into registers (the block holds
+                // BIG_PER_THREAD per thread), all loads of a batch in flight;
+                // with pending lists only the listed positions
+                const bool plm = sp.pl != nullptr && tent_only;
+                const int np = plm ? sp.pn[v] : sz;
+                int xs[BIG_PER_THREAD], ss[BIG_PER_THREAD], ps[BIG_PER_THREAD];
+    #pragma unroll
+                for (int i = 0; i < BIG_PER_THREAD; i++) {
+                    const int k = tid + i * BIG_BLOCK;
+                    ps[i] = k < np ? (plm ? sp.pl[lpos + k] : k) : -1;
+                }
+    #pragma unroll
+                for (int i = 0; i < BIG_PER_THREAD; i++) xs[i] = ps[i] >= 0 ? Acc<D2>::member(g, v, ps[i]) : -1;
+                // pending members (low 16 bits) and proposers (high bits), one sum
+                int counts = 0;
+    #pragma unroll
+                for (int i = 0; i < BIG_PER_THREAD; i++) {
+                    ss[i] = xs[i] >= 0 ? st[xs[i]] : 0;
+                    counts += (xs[i] >= 0 && (ss[i] < 0 || (ss[i] & TENT))) ? 1 : 0;
+                    counts += (xs[i] >= 0 && ss[i] >= 0 && (ss[i] & TENT)) ? (1 << 16) : 0;
+                }
+                if (tid == 0) s_cnt = 0;
+                counts = block_sum(counts, s_scan);
+                const int pending = counts & 0xffff, nprop = counts >> 16;
+                if (plm) {
+                    // the list keeps the pending positions (every read of it is done)
+    #pragma unroll
+                    for (int i = 0; i < BIG_PER_THREAD; i++)
+                        if (xs[i] >= 0 && (ss[i] < 0 || (ss[i] & TENT))) sp.pl[lpos + atomicAdd(&s_cnt, 1)] = ps[i];
+                    if (tid == 0) sp.pn[v] = pending;
+                }
+                if (sp.lbits && tid == 0) sp.dirty[v] = 0;
+                if (pending == 0) {
+                    if (tid == 0) done[v] = 1;
+                    continue;
+                }
+                if (tent_only && nprop <= 1) {
+                    // a lone proposer keeps its proposal in this net
+                    if (sp.lbits) {
+    #pragma unroll
+                        for (int i = 0; i < BIG_PER_THREAD; i++)
+                            if (xs[i] >= 0 && ss[i] >= 0 && (ss[i] & TENT)) sp_set(sp, lpos + ps[i], xs[i], false);
+                    }
+                    __syncthreads();
+                    continue;
+                }
+                // hash of the proposed colors (tent_only: nprop entries at most)
+                int cap = 64;
+                while (cap < 2 * (tent_only ? nprop : sz)) cap <<= 1;
+                int *keys = sh, *minr = sh + cap;
+                for (int i = tid; i < cap; i += nt) {
+                    keys[i] = -1;
+                    minr[i] = 0x7fffffff;
+                }
+                __syncthreads();
+    #pragma unroll
+                for (int i = 0; i < BIG_PER_THREAD; i++) {
+                    const int x = xs[i], s = ss[i];
+                    if (x < 0 || (tent_only && !(s >= 0 && (s & TENT)))) continue;
+                    const int c = cur_color(s);
+                    if (c < 0) continue;
+                    unsigned h = hash_color(c) & (cap - 1);
+                    for (;;) {
+                        int prev = atomicCAS(&keys[h], -1, c);
+                        if (prev == -1 || prev == c) {
+                            atomicMin(&minr[h], x);
+                            break;
+                        }
+                        h = (h + 1) & (cap - 1);
+                    }
+                }
+                __syncthreads();
+    #pragma unroll
+                for (int i = 0; i < BIG_PER_THREAD; i++) {
+                    const int x = xs[i], s = ss[i];
+                    if (x < 0 || (tent_only && !(s >= 0 && (s & TENT)))) continue;
+                    const int c = cur_color(s);
+                    if (c < 0) continue;
+                    unsigned h = hash_color(c) & (cap - 1);
+                    while (keys[h] != c) h = (h + 1) & (cap - 1);
+                    if (sp.lbits) sp_set(sp, lpos + ps[i], x, minr[h] != x);
+                    else if (minr[h] != x) lose[x] = 1;
+                }
+                __syncthreads();
+                continue;
+            }
+            if (huge_elsewhere && sz > HASH_MAX) continue;   // k_conflict_huge
+            conflict_large<D2>(g, st, lose, done, v, sz, lpos, tent_only, sp, sh, BIG_LIST, ctrl->max_color, s_scan,
+                               &s_cnt, &s_keep);
+        }
+        __syncthreads();
     }
 }
 
@@ -2127,14 +2293,19 @@ __global__ void __launch_bounds__(HUGE_BLOCK) k_conflict_huge(Graph g, const int
                                                               int tent_only, SPState sp, int list_cap)
 {
     extern __shared__ int sh[];
-    __shared__ int s_scan[20], s_cnt;
+    __shared__ int s_scan[20], s_cnt, s_keep;
     const int n_huge = *n_huge_p;
     for (int hi = blockIdx.x; hi < n_huge; hi += gridDim.x) {
         const int v = huge[hi];
         if (done[v] || (sp.lbits && !sp.dirty[v])) continue;
         const long lpos = sp.lbits ? sp_lpos<D2>(g, v) : 0;
+        if (sp.pl && tent_only && sp.pn[v] <= WAVE) {
+            // few pending members left: one wave, no barriers
+            if (threadIdx.x < WAVE) wave_pending_net<D2>(g, st, done, sp, v, lpos, sp.pn[v]);
+            continue;
+        }
         conflict_large<D2>(g, st, lose, done, v, Acc<D2>::size(g, v), lpos, tent_only, sp, sh, list_cap,
-                           ctrl->max_color, s_scan, &s_cnt);
+                           ctrl->max_color, s_scan, &s_cnt, &s_keep);
     }
 }
 
