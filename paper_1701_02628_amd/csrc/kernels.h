@@ -2074,24 +2074,29 @@ __device__ void conflict_large(const Graph &g, const int *st, uint8_t *lose, uin
         __syncthreads();
         return;
     }
+    // more proposals than the list holds: windows of WIN_COLORS colors, over
+    // the pending positions (all positions without pending lists)
+    const int nk = plm ? pending : sz;
     for (int base = 0; base <= maxc; base += WIN_COLORS) {
         for (int i = tid; i < WIN_COLORS; i += nt) sh[i] = 0x7fffffff;
         __syncthreads();
-        for (int k = tid; k < sz; k += nt) {
-            int x = Acc<D2>::member(g, v, k);
+        for (int k = tid; k < nk; k += nt) {
+            const int p = plm ? sp.pl[lpos + k] : k;
+            int x = Acc<D2>::member(g, v, p);
             int s = st[x];
             if (tent_only && !(s >= 0 && (s & TENT))) continue;
             int c = cur_color(s) - base;
             if (c >= 0 && c < WIN_COLORS) atomicMin(&sh[c], x);
         }
         __syncthreads();
-        for (int k = tid; k < sz; k += nt) {
-            int x = Acc<D2>::member(g, v, k);
+        for (int k = tid; k < nk; k += nt) {
+            const int p = plm ? sp.pl[lpos + k] : k;
+            int x = Acc<D2>::member(g, v, p);
             int s = st[x];
             if (tent_only && !(s >= 0 && (s & TENT))) continue;
             int c = cur_color(s) - base;
             if (c >= 0 && c < WIN_COLORS) {
-                if (sp.lbits) sp_set(sp, lpos + k, x, sh[c] != x);
+                if (sp.lbits) sp_set(sp, lpos + p, x, sh[c] != x);
                 else if (sh[c] != x) lose[x] = 1;
             }
         }
