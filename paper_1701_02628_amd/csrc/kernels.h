@@ -1738,10 +1738,12 @@ __device__ __forceinline__ int scan_net(int v, int b, int e, Src src, int rel, c
 // One wave per 64 consecutive nets of at most SMALL_NET members.  The wave
 // copies its stretch of the net lists into LDS with coalesced loads, then
 // every lane scans its own net.  Nets whose members were all colored at an
-// earlier round are marked done and skipped: no vertex can join them again
-// until a net-based round evicts (the driver then clears the marks).  With
-// tent_only, only proposed colors take part (after a vertex-based round no
-// colored vertex can clash).
+// earlier round are marked done (1) and skipped: no vertex can join them
+// again until a net-based round evicts (the driver then clears the marks).
+// Nets with one member still pending are marked 2: no clash can arise in
+// them in vertex-based rounds, which skip them too; net-based rounds scan
+// them.  With tent_only, only proposed colors take part (after a
+// vertex-based round no colored vertex can clash).
 // Standing proposals (SP): only dirty nets are scanned.  The wave reads the
 // flags and row offsets of SP_PF of its stretches at once (coalesced, all in
 // flight), queues the dirty nets with their offsets in LDS and scans them 64
@@ -1769,7 +1771,10 @@ __device__ void conflict_dirty(const Graph &g, const int *st, uint8_t *done, con
                                            lpos);
                 else
                     pending = scan_net<D2>(v, b, e, g.b_idx, 0, st, nullptr, 1, &sp, lpos);
-                if (pending == 0) done[v] = 1;
+                // at most one member still pending: no clash can arise in
+                // this net in later vertex-based rounds (marked 2: skipped
+                // there, scanned again by net-based rounds)
+                if (pending <= 1) done[v] = pending == 0 ? 1 : 2;
                 scanned_members += sz;
                 walked_nets++;
             }
@@ -1854,7 +1859,7 @@ __global__ void __launch_bounds__(64) k_conflict_small(Graph g, const int *st, u
             if (v < g.n_b) {
                 nb_ = g.b_off[v];
                 ne_ = g.b_off[v + 1];
-                nskip = done[v];
+                nskip = tent_only ? done[v] : (uint8_t)(done[v] == 1);
             }
             noff0 = g.b_off[bs];
             noffe = g.b_off[min(bs + 64, g.n_b)];
@@ -2133,7 +2138,7 @@ __device__ void wave_pending_net(const Graph &g, const int *st, uint8_t *done, c
     if (keep) sp.pl[lpos + __builtin_popcountll(kb & ((1ull << lane) - 1ull))] = p;
     if (lane == 0) {
         sp.pn[v] = __builtin_popcountll(kb);
-        if (!kb) done[v] = 1;
+        if (__builtin_popcountll(kb) <= 1) done[v] = kb ? 2 : 1;   // see conflict_dirty
         sp.dirty[v] = 0;
     }
 }
@@ -2171,7 +2176,8 @@ __global__ void __launch_bounds__(BIG_BLOCK) k_conflict_big(Graph g, const int *
         __syncthreads();
         if (tid < BIG_CHUNK && base + tid < n_big) {
             const int v = big[base + tid];
-            if (!done[v] && !(sp.lbits && !sp.dirty[v])) s_list[atomicAdd(&s_ln, 1)] = v;
+            const bool fin = tent_only ? done[v] != 0 : done[v] == 1;
+            if (!fin && !(sp.lbits && !sp.dirty[v])) s_list[atomicAdd(&s_ln, 1)] = v;
         }
         __syncthreads();
         const int ln = s_ln;
@@ -2302,7 +2308,7 @@ __global__ void __launch_bounds__(HUGE_BLOCK) k_conflict_huge(Graph g, const int
     const int n_huge = *n_huge_p;
     for (int hi = blockIdx.x; hi < n_huge; hi += gridDim.x) {
         const int v = huge[hi];
-        if (done[v] || (sp.lbits && !sp.dirty[v])) continue;
+        if ((tent_only ? done[v] != 0 : done[v] == 1) || (sp.lbits && !sp.dirty[v])) continue;
         const long lpos = sp.lbits ? sp_lpos<D2>(g, v) : 0;
         if (sp.pl && tent_only && sp.pn[v] <= WAVE) {
             // few pending members left: one wave, no barriers
