@@ -496,7 +496,7 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
     int local_max = -1;
     // the next 64 entries and their row offsets are loaded while the current
     // ones are colored
-    int nw_ = -1, nbeg = 0, nend = 0, nst = -1;
+    int nw_ = -1, nbeg = 0, nend = 0, nst = -1, nffc = 0;
     uint8_t nzf = 1;
     auto fetch = [&](int bs) {
         int i = bs + lane;
@@ -504,6 +504,7 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
         if (nw_ >= 0) {
             nbeg = g.a_off[nw_];
             nend = g.a_off[nw_ + 1];
+            nffc = ffc[nw_];
             if ((FRONT && fl_out) || (!FRONT && zf)) nst = st[nw_];
             if (!FRONT && zf) nzf = zf[nw_];
         }
@@ -523,10 +524,14 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
             fbase = __shfl(fbase, 0);
             if (w >= 0) fl_out[fbase + __builtin_popcountll(bal & ((1ull << lane) - 1ull))] = w;
         }
-        const int beg = w >= 0 ? nbeg : 0, d = w >= 0 ? nend - nbeg : 0;
+        // a vertex of more than 64 nets whose last first-fit answer was 64 or
+        // more still has colors 0..63 all forbidden (F only grows in these
+        // rounds): its nets' masks are not read, it goes to k_vcolor_wide
+        const bool full64 = w >= 0 && nend - nbeg > 64 && nffc >= 64;
+        const int beg = w >= 0 ? nbeg : 0, d = (w >= 0 && !full64) ? nend - nbeg : 0;
         fetch(base + stride);
         uint64_t m = 0;
-        if (D2 && w >= 0) m = mask0[w];
+        if (D2 && w >= 0 && !full64) m = mask0[w];
         int incl = wave_incl_scan(d);
         int total = __shfl(incl, 63);
         int pre = incl - d;
@@ -609,7 +614,9 @@ __global__ void __launch_bounds__(64) k_vcolor_ff(Graph g, const int *W, Ctrl *c
         bool changed = false;     // (front-driven rounds) w's nets go on the dirty list
         if (w >= 0) {
             int col = -1;
-            if (~m) {
+            if (full64) {
+                // k_vcolor_wide, below
+            } else if (~m) {
                 col = __builtin_ctzll(~m);
             } else if (PH > 0 && d <= 64) {
                 // colors 0..63 all forbidden: the higher words, from the
