@@ -165,18 +165,28 @@ __global__ void k_net_shape(Graph g, int *max_net, int *big_list, int *n_big, un
 template <bool D2>
 __global__ void k_owner(Graph g, int *owner)
 {
-    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < g.n_a; u += gridDim.x * blockDim.x) {
-        int best = -1, best_sz = -1;
-        int k = Acc<D2>::nets_count(g, u);
-        for (int j = 0; j < k; j++) {
-            int v = Acc<D2>::net_at(g, u, j);
-            int sz = Acc<D2>::size(g, v);
-            if (sz > best_sz || (sz == best_sz && v < best)) {
-                best = v;
-                best_sz = sz;
-            }
+    // key of a net: larger size first, then lower id (0: no net)
+    auto key_of = [&](int v) {
+        return ((unsigned long long)(Acc<D2>::size(g, v) + 1) << 32) | (unsigned)(0x7fffffff - v);
+    };
+    const int lane = lane_id();
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x + threadIdx.x - lane; base < g.n_a; base += stride) {
+        const int u = base + lane;
+        const int k = u < g.n_a ? Acc<D2>::nets_count(g, u) : 0;
+        const bool coop = k > 4 * WAVE;   // long rows: the whole wave, below
+        unsigned long long key = 0;
+        if (!coop)
+            for (int j = 0; j < k; j++) key = max(key, key_of(Acc<D2>::net_at(g, u, j)));
+        for (uint64_t bal = __ballot(coop); bal; bal &= bal - 1) {
+            const int j = __builtin_ctzll(bal);
+            const int uj = __shfl(u, j), kj = __shfl(k, j);
+            unsigned long long acc = 0;
+            for (int t = lane; t < kj; t += WAVE) acc = max(acc, key_of(Acc<D2>::net_at(g, uj, t)));
+            for (int o = WAVE / 2; o > 0; o >>= 1) acc = max(acc, shfl64(acc, lane ^ o));
+            if (lane == j) key = acc;
         }
-        owner[u] = best;
+        if (u < g.n_a) owner[u] = key ? 0x7fffffff - (int)(unsigned)(key & 0xffffffffull) : -1;
     }
 }
 
