@@ -824,6 +824,7 @@ int run(const RunArgs &a)
                 k_fill_i32<<<g_a, nthr, 0, s>>>(sp_cnt, 0, n_a + 1);
                 k_fill_u8<<<g_b, nthr, 0, s>>>(sp_dirty, 1, n_b + 1);
                 if (pend_l) k_pending_init<D2><<<g_big, 256, 0, s>>>(g, big, &shape[1], pend_l, pend_n);
+                if (pend_l && !ell) k_pending_init_small<D2><<<g_b, nthr, 0, s>>>(g, pend_l, pend_n);
                 sp_reset = false;
             }
             const bool spr = !net_mode && r < inc_start && sp_on;   // this round keeps standing proposals
@@ -993,6 +994,8 @@ int run(const RunArgs &a)
                         LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_list<D2><<<g_list, LIST_BLOCK, 0, s>>>(g, st, done_net, sp_state, DL, &ctrl->dl_n, PCNT(r))));
                     else if (spr && ell)
                         LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2, true, !D2><<<g_sp, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), sp_state, ell, ell_w)));
+                    else if (spr && pend_l)
+                        LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2, true, false, true><<<g_sp, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), sp_state)));
                     else if (spr)
                         LAUNCH_PROF(BGPC_PROF_CONFLICT, (k_conflict_small<D2, true><<<g_sp, 64, 0, s>>>(g, st, lose, done_net, 1, PCNT(r), sp_state)));
                     else

@@ -1752,6 +1752,98 @@ __device__ __forceinline__ int scan_net(int v, int b, int e, Src src, int rel, c
     return pending;
 }
 
+// scan_net over the pending list of a net of at most SMALL_NET members
+// (standing proposals; positions in rank order, the distance-2 center merged
+// at its rank): only the listed members are read, and the list keeps, in
+// order, those still pending.  Colored members take no part in a
+// vertex-based round's removal and carry no verdict bits, so the verdicts
+// equal scan_net's.  Returns the number of members still pending.
+template <bool D2>
+__device__ __forceinline__ int scan_net_list(const Graph &g, int v, int b, int e, const int *st, const SPState &sp,
+                                             long lpos)
+{
+    const int *src = g.b_idx;
+    const int size = e - b + (D2 ? 1 : 0);
+    int cpos = size;
+    if (D2) {
+        int lo = b, hi = e;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (src[mid] < v) lo = mid + 1;
+            else hi = mid;
+        }
+        cpos = lo - b;
+    }
+    auto member = [&](int p) {
+        if (!D2) return src[b + p];
+        if (p < cpos) return src[b + p];
+        if (p == cpos) return v;
+        return src[b + p - 1];
+    };
+    const long w0 = lpos >> 6;
+    const int sh = (int)(lpos & 63);
+    unsigned long long a0 = __atomic_load_n(&sp.lbits[w0], __ATOMIC_RELAXED);
+    unsigned long long a1 = sh + size > 64 ? __atomic_load_n(&sp.lbits[w0 + 1], __ATOMIC_RELAXED) : 0ull;
+    const int np = sp.pn[v];
+    uint64_t seen = 0, lm = 0;
+    bool wide = false;
+    int kept = 0;
+    for (int k0 = 0; k0 < np; k0 += SCAN_BATCH) {
+        int ps[SCAN_BATCH], xs[SCAN_BATCH], ss[SCAN_BATCH];
+#pragma unroll
+        for (int q = 0; q < SCAN_BATCH; q++) ps[q] = k0 + q < np ? sp.pl[lpos + k0 + q] : -1;
+#pragma unroll
+        for (int q = 0; q < SCAN_BATCH; q++) xs[q] = ps[q] >= 0 ? member(ps[q]) : -1;
+#pragma unroll
+        for (int q = 0; q < SCAN_BATCH; q++) ss[q] = xs[q] >= 0 ? st[xs[q]] : 0;
+#pragma unroll
+        for (int q = 0; q < SCAN_BATCH; q++) {
+            if (xs[q] < 0) continue;
+            const int s = ss[q];
+            // in place: every entry up to k0 + q has been read
+            if (s < 0 || (s & TENT)) sp.pl[lpos + kept++] = ps[q];
+            if (!(s >= 0 && (s & TENT))) continue;
+            const int c = s & COLOR_MASK;
+            if (c < 64) {
+                if ((seen >> c) & 1ull) lm |= 1ull << ps[q];
+                seen |= 1ull << c;
+            } else {
+                wide = true;
+            }
+        }
+    }
+    if (wide) {
+        // pairwise for colors >= 64 over the kept list, in rank order
+        for (int k = 0; k < kept; k++) {
+            const int p = sp.pl[lpos + k];
+            const int s = st[member(p)];
+            if (!(s >= 0 && (s & TENT))) continue;
+            const int c = s & COLOR_MASK;
+            if (c < 64) continue;
+            for (int k2 = 0; k2 < k; k2++) {
+                const int t = st[member(sp.pl[lpos + k2])];
+                if (t >= 0 && (t & TENT) && (t & COLOR_MASK) == c) {
+                    lm |= 1ull << p;
+                    break;
+                }
+            }
+        }
+    }
+    unsigned long long old = (a0 >> sh) | (sh ? (a1 << (64 - sh)) : 0ull);
+    if (size < 64) old &= (1ull << size) - 1ull;
+    const unsigned long long chg = old ^ lm;
+    if (chg) {
+        atomicXor(&sp.lbits[w0], chg << sh);
+        if (sh + size > 64) atomicXor(&sp.lbits[w0 + 1], chg >> (64 - sh));
+        for (unsigned long long m = chg; m; m &= m - 1) {
+            const int p = __builtin_ctzll(m);
+            atomicAdd(&sp.lcnt[member(p)], ((lm >> p) & 1ull) ? 1 : -1);
+        }
+    }
+    sp.pn[v] = kept;
+    return kept;
+}
+
 // One wave per 64 consecutive nets of at most SMALL_NET members.  The wave
 // copies its stretch of the net lists into LDS with coalesced loads, then
 // every lane scans its own net.  Nets whose members were all colored at an
@@ -1767,7 +1859,7 @@ __device__ __forceinline__ int scan_net(int v, int b, int e, Src src, int rel, c
 // at a time, one net per lane, members read straight from the net lists.
 constexpr int SP_PF = 4;
 constexpr int SP_Q = 64 * SP_PF + 64;   // queue entries: the rest of a drain plus SP_PF stretches
-template <bool D2, bool ELLS>
+template <bool D2, bool ELLS, bool LISTS>
 __device__ void conflict_dirty(const Graph &g, const int *st, uint8_t *done, const SPState &sp, int lb, int nb,
                                int *qv, int *qb, int *qe, int &walked_nets, int &scanned_members, const int *ell,
                                int ell_w)
@@ -1786,6 +1878,8 @@ __device__ void conflict_dirty(const Graph &g, const int *st, uint8_t *done, con
                 if constexpr (ELLS)
                     pending = scan_net<D2>(v, b, e, EllSrc{ell + v, g.b_idx, g.n_b, b, ell_w}, 0, st, nullptr, 1, &sp,
                                            lpos);
+                else if constexpr (LISTS)
+                    pending = scan_net_list<D2>(g, v, b, e, st, sp, lpos);
                 else
                     pending = scan_net<D2>(v, b, e, g.b_idx, 0, st, nullptr, 1, &sp, lpos);
                 // at most one member still pending: no clash can arise in
@@ -1846,7 +1940,7 @@ __device__ void conflict_dirty(const Graph &g, const int *st, uint8_t *done, con
     if (qn > 0) drain(0, qn);
 }
 
-template <bool D2, bool SP = false, bool ELLS = false>
+template <bool D2, bool SP = false, bool ELLS = false, bool LISTS = false>
 __global__ void __launch_bounds__(64) k_conflict_small(Graph g, const int *st, uint8_t *lose, uint8_t *done,
                                                        int tent_only, unsigned long long *prof, SPState sp,
                                                        const int *ell = nullptr, int ell_w = 0)
@@ -1858,7 +1952,7 @@ __global__ void __launch_bounds__(64) k_conflict_small(Graph g, const int *st, u
         // the round's nets are counted by k_census (profiling only)
         __shared__ int q[3][SP_Q];
         int scanned = 0;
-        conflict_dirty<D2, ELLS>(g, st, done, sp, lb, nb, q[0], q[1], q[2], walked_nets, scanned, ell, ell_w);
+        conflict_dirty<D2, ELLS, LISTS>(g, st, done, sp, lb, nb, q[0], q[1], q[2], walked_nets, scanned, ell, ell_w);
         if (prof) {
             int ws = wave_sum(scanned);
             if (lane == 0 && ws) atomicAdd(&prof[4 * (blockIdx.x & 63) + 3], (unsigned long long)ws);
@@ -2157,6 +2251,20 @@ __device__ void wave_pending_net(const Graph &g, const int *st, uint8_t *done, c
         sp.pn[v] = __builtin_popcountll(kb);
         if (__builtin_popcountll(kb) <= 1) done[v] = kb ? 2 : 1;   // see conflict_dirty
         sp.dirty[v] = 0;
+    }
+}
+
+// pending lists of the nets of at most SMALL_NET members (used by the
+// standing-proposal scan without the column-major copy): every position
+template <bool D2>
+__global__ void k_pending_init_small(Graph g, int *pl, int *pn)
+{
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n_b; v += gridDim.x * blockDim.x) {
+        const int sz = Acc<D2>::size(g, v);
+        if (sz > SMALL_NET) continue;
+        const long lpos = sp_lpos<D2>(g, v);
+        for (int k = 0; k < sz; k++) pl[lpos + k] = k;
+        pn[v] = sz;
     }
 }
 
