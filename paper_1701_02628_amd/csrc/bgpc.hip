@@ -544,7 +544,7 @@ int run(const RunArgs &a)
         // (its candidate listing) and standing proposals
         const bool front = front_possible && n_big == 0 && n_huge == 0 && max_net <= SMALL_NET &&
                            !(o.flags & BGPC_NET_BALANCE);
-        if (!D2 && sp_on && !noalloc && max_net >= 2 && (long)std::min(max_net, ELL_W) * n_b < (1L << 31)) {
+        if (!D2 && sp_on && !noalloc && max_net >= 2 && n_big == 0 && (long)std::min(max_net, ELL_W) * n_b < (1L << 31)) {
             ell_w = std::min(max_net, ELL_W);
             if (hipMallocAsync((void **)&ell, (size_t)ell_w * (size_t)n_b * 4, s) != hipSuccess) {
                 (void)hipGetLastError();
