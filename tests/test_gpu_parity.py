@@ -197,6 +197,25 @@ def test_d2gc_rmat_small(cuda, mask):
     assert oracle.violations(adj, colors) == 0
 
 
+@pytest.mark.parametrize("mask", [0, 1, 0b10, 0b101])
+def test_standing_proposals_mixed_schedules(cuda, mask):
+    """Standing proposals forced on small graphs with nets above 64 members
+    (pending lists, nets left with one pending member skipped by vertex
+    rounds, first-fit skips through zf) under schedules that alternate
+    vertex- and net-based rounds, distance-1 and distance-2: colors, rounds
+    and round log equal the oracle's."""
+    t = bgpc.tuning(standing=1)
+    adj = synth.rmat(11, 8, 0.57, 0.19, 0.19, seed=9)
+    ref = oracle.d2gc(adj, net_color_mask=mask)
+    res, colors = _gpu_d2(cuda, adj, net_color_mask=mask, tune=t)
+    _compare_full(res, colors, ref)
+    if mask:
+        g = synth.skewed(30000, 30000, seed=5, kmax=3000, name="skewed30k")
+        ref = oracle.bgpc(g, net_color_mask=mask)
+        res, colors = _gpu_bgpc(cuda, g, net_color_mask=mask, tune=t)
+        _compare_full(res, colors, ref)
+
+
 def test_d2gc_policies(cuda):
     adj = synth.rmat(10, 4, 0.57, 0.19, 0.19, seed=10)
     for kw in (dict(policy=1), dict(policy=2), dict(policy=1, net_color_mask=1), dict(policy=3, net_color_mask=1)):
