@@ -1297,21 +1297,38 @@ __global__ void k_sl_keys(Graph g, const int *R, const int *n_p, const unsigned 
                           unsigned long long *key, unsigned long long *dmin)
 {
     const int n = *n_p;
+    const int lane = lane_id();
+    const int stride = gridDim.x * blockDim.x;
     unsigned long long m = ~0ull;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int x = R[i];
-        const int nn = Acc<D2>::nets_count(g, x);
+    // a lane per present vertex; rows of more than 256 nets summed by the
+    // whole wave
+    for (int i0 = blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < n; i0 += stride) {
+        const int i = i0 + lane;
+        const int x = i < n ? R[i] : -1;
+        const int nn = x >= 0 ? Acc<D2>::nets_count(g, x) : 0;
+        const bool coop = nn > 4 * WAVE;
         unsigned long long r = 0;
-        for (int k = 0; k < nn; k++) r += (unsigned long long)removed[Acc<D2>::net_at(g, x, k)];
-        const unsigned long long kx = base[x] - r;
-        key[x] = kx;
-        m = kx < m ? kx : m;
+        if (!coop)
+            for (int k = 0; k < nn; k++) r += (unsigned long long)removed[Acc<D2>::net_at(g, x, k)];
+        for (uint64_t bal = __ballot(coop); bal; bal &= bal - 1) {
+            const int j = __builtin_ctzll(bal);
+            const int xj = __shfl(x, j), nj = __shfl(nn, j);
+            unsigned long long acc = 0;
+            for (int k = lane; k < nj; k += WAVE) acc += (unsigned long long)removed[Acc<D2>::net_at(g, xj, k)];
+            for (int o = WAVE / 2; o > 0; o >>= 1) acc += shfl64(acc, lane ^ o);
+            if (lane == j) r = acc;
+        }
+        if (x >= 0) {
+            const unsigned long long kx = base[x] - r;
+            key[x] = kx;
+            m = kx < m ? kx : m;
+        }
     }
     for (int d = WAVE / 2; d > 0; d >>= 1) {
         const unsigned long long o = (unsigned long long)__shfl_xor((long long)m, d);
         m = o < m ? o : m;
     }
-    if (lane_id() == 0 && m != ~0ull) atomicMin(dmin, m);
+    if (lane == 0 && m != ~0ull) atomicMin(dmin, m);
 }
 
 // flags of the step: present vertices at or below the threshold leave
@@ -1328,15 +1345,26 @@ __global__ void k_sl_flags(const int *R, const int *n_p, const unsigned long lon
     }
 }
 
-// removed(v) += 1 for every net of every vertex removed in this step
+// removed(v) += 1 for every net of every vertex removed in this step (rows
+// of more than 256 nets by the whole wave)
 template <bool D2>
 __global__ void k_sl_remove(Graph g, const int *B, const int *nb_p, int *removed)
 {
     const int n = *nb_p;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int u = B[i];
-        const int nn = Acc<D2>::nets_count(g, u);
-        for (int k = 0; k < nn; k++) atomicAdd(&removed[Acc<D2>::net_at(g, u, k)], 1);
+    const int lane = lane_id();
+    const int stride = gridDim.x * blockDim.x;
+    for (int i0 = blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < n; i0 += stride) {
+        const int i = i0 + lane;
+        const int u = i < n ? B[i] : -1;
+        const int nn = u >= 0 ? Acc<D2>::nets_count(g, u) : 0;
+        const bool coop = nn > 4 * WAVE;
+        if (!coop)
+            for (int k = 0; k < nn; k++) atomicAdd(&removed[Acc<D2>::net_at(g, u, k)], 1);
+        for (uint64_t bal = __ballot(coop); bal; bal &= bal - 1) {
+            const int j = __builtin_ctzll(bal);
+            const int uj = __shfl(u, j), nj = __shfl(nn, j);
+            for (int k = lane; k < nj; k += WAVE) atomicAdd(&removed[Acc<D2>::net_at(g, uj, k)], 1);
+        }
     }
 }
 
