@@ -617,15 +617,11 @@ def _short(name):
     return m.group(1) if m else name.split("(")[0]
 
 
-def summarize_counters(fetch_dir, write_dir, workload):
-    """Per-kernel calibrated HBM bytes of one --counter-run call.
-
-    FETCH_SIZE and WRITE_SIZE are in KiB per dispatch.  The 256 MiB
-    device-to-device copy dispatched first (--copy-calibration) moves 256 MiB
-    each way; the ratio of that to what the counters report is the
-    calibration factor of each counter.  Round 0 is every dispatch from the
-    first coloring launch through the first compaction launch."""
-    fetch, write = _read_counter_csv(fetch_dir), _read_counter_csv(write_dir)
+def calibrated_traffic(fetch, write):
+    """From the (kernel name, KiB) dispatch lists of the FETCH_SIZE and
+    WRITE_SIZE passes: (read factor, write factor, per-kernel bytes per
+    launch and launches, round-0 bytes).  The first copy dispatch is the
+    256 MiB calibration; only the library's kernels are counted."""
     if len(fetch) != len(write) or not fetch:
         raise SystemExit(f"dispatch lists differ or are empty ({len(fetch)} vs {len(write)})")
     cal = [i for i, (n, _) in enumerate(fetch) if "copyBuffer" in n or "copy" in n.lower()]
@@ -654,6 +650,19 @@ def summarize_counters(fetch_dir, write_dir, workload):
                 in_r0 = False
     for e in kernels.values():
         e["bytes_per_launch"] = e.pop("bytes_total") / e["launches_per_call"]
+    return f_read, f_write, kernels, round0
+
+
+def summarize_counters(fetch_dir, write_dir, workload):
+    """Per-kernel calibrated HBM bytes of one --counter-run call.
+
+    FETCH_SIZE and WRITE_SIZE are in KiB per dispatch.  The 256 MiB
+    device-to-device copy dispatched first (--copy-calibration) moves 256 MiB
+    each way; the ratio of that to what the counters report is the
+    calibration factor of each counter.  Round 0 is every dispatch from the
+    first coloring launch through the first compaction launch."""
+    fetch, write = _read_counter_csv(fetch_dir), _read_counter_csv(write_dir)
+    f_read, f_write, kernels, round0 = calibrated_traffic(fetch, write)
     path = os.path.join(ROOT, "profiles", "traffic.json")
     rec = {}
     if os.path.exists(path):
