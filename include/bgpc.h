@@ -403,12 +403,21 @@ BGPC_API int bgpc_color_batch(bgpc_batch_item *items, int32_t n_items, const bgp
  * while others run overlap on the device.  A request completes as soon as
  * its own graph is done: its workgroup copies the colors to host memory and
  * then sets a done word that the worker polls.  The kernel's workgroups leave
- * after about 20 ms without work (the worker launches it again when work is
- * published) and when the session is destroyed.  Requests that
+ * after about 20 ms without work and when the session is destroyed; the
+ * worker launches the kernel again when work is published, and launches more
+ * (as many workgroups as requests wait) when requests wait unclaimed while
+ * fewer workgroups than compute units remain -- up to six launches at once
+ * when the process has 16 or more hardware queues (GPU_MAX_HW_QUEUES, read
+ * when the HIP runtime starts; HIP's default is 4, and then one launch, since
+ * kernels on one hardware queue run in order).  Requests that
  * bgpc_color_batch would give to the whole device are colored by bgpc_color
- * on three more threads, each with a stream of its own; their arrays are
- * allocated outside the pool.  A request's colors equal what bgpc_color returns for
- * its graph alone.  Calls on one session may come from any thread.
+ * on three more threads, each with a stream of its own; under light load a
+ * request of 50,000 or more memberships also takes such a thread when one is
+ * idle.  Their arrays are allocated outside the pool.  With 4 hardware
+ * queues those streams share queues with the serving kernel and wait for it:
+ * serving processes should start with GPU_MAX_HW_QUEUES of 16 or more.  A
+ * request's colors equal what bgpc_color returns for its graph alone.  Calls
+ * on one session may come from any thread.
  *
  * bgpc_request: host arrays (csr_A offsets / indices = a_off / a_idx, csr_B =
  * b_off / b_idx), read at submit (shape and checks, as in bgpc_color_batch)
